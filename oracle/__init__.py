@@ -1,0 +1,302 @@
+"""TEST INFRASTRUCTURE ONLY: the FP64 CPU oracle of the NURBS Splatting render path.
+
+A plain, slow, brute-force reference (``nsplat_oracle.cpp``) that follows the
+paper step by step (Sec. 3.1-3.4, Eq. 1-9, Suppl. S2 Eq. S1-S3, Eq. 14) and
+composites every Gaussian at every pixel.  Only ``tests/``, the smoke check and
+the CPU-baseline leg of the benchmark may import it.  It shares no code with
+the GPU library and the GPU library never calls it.
+
+Inputs are "curve batches": any object with the numpy attributes
+``scene, degree, flags, key_off, tau_off, key_xy, key_w, key_s, tau, color,
+opacity, hw, bg, channels`` (see ``paper_2606_31764_amd.synth``), converted
+here to FP64 (exactly: they are FP32 values).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nsplat_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Table S1 defaults, plus the readings the paper leaves open (alpha clamp,
+# termination threshold, fill padding).  cutoff <= 0: no support cutoff.
+DEFAULTS = dict(delta_c=10.0, delta_b=0.5, rho=2.0, eta=1.5, gamma=5.0, nl_factor=3.0,
+                fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=0.0, kappa=4)
+
+P_COUNT, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_FLAG = range(8)
+KIND = dict(key_x=1, key_y=2, key_w=3, key_s=4, tau=5, opacity=6, color0=7, color1=8, color2=9)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Curves(ctypes.Structure):
+    _fields_ = [("n_curves", ctypes.c_int32), ("channels", ctypes.c_int32)] + [
+        (n, ctypes.c_void_p) for n in ("scene", "degree", "flags", "key_off", "tau_off",
+                                        "key_xy", "key_w", "key_s", "tau", "color", "opacity")]
+
+
+class _Scenes(ctypes.Structure):
+    _fields_ = [("n_scenes", ctypes.c_int32), ("hw", ctypes.c_void_p), ("bg", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
+                                                "fill_pad", "h", "alpha_max", "eps_T", "cutoff")] + [
+        ("kappa", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "or_plan": (i64, [vp, vp, vp, vp, vp]),
+            "or_gaussians": (i64, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "or_bin": (i64, [i64, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, i64]),
+            "or_composite": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp]),
+            "or_param_grad_seeds": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
+            "or_param_grad_full": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "or_curve_knots": (i32, [i32, i32, i32, i32, vp, vp]),
+            "or_curve_eval": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, i32, vp]),
+            "or_basis_all": (i32, [i32, i32, vp, dbl, vp, vp]),
+            "or_arc_length": (dbl, [i32, i32, i32, i32, vp, vp, vp, vp, i32]),
+            "or_sdf": (i32, [i32, vp, dbl, dbl, vp]),
+            "or_anneal": (dbl, [dbl, dbl, dbl, dbl, dbl, dbl]),
+            "or_num_threads": (i32, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype, f.argtypes = res, args
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class _Batch:
+    """FP64 / int32 copies of a curve batch, kept alive with the ctypes views."""
+
+    def __init__(self, b, params):
+        self.keep = dict(
+            scene=np.ascontiguousarray(b.scene, np.int32), degree=np.ascontiguousarray(b.degree, np.int32),
+            flags=np.ascontiguousarray(b.flags, np.int32), key_off=np.ascontiguousarray(b.key_off, np.int32),
+            tau_off=np.ascontiguousarray(b.tau_off, np.int32),
+            key_xy=np.ascontiguousarray(b.key_xy, np.float64), key_w=np.ascontiguousarray(b.key_w, np.float64),
+            key_s=np.ascontiguousarray(b.key_s, np.float64), tau=np.ascontiguousarray(b.tau, np.float64),
+            color=np.ascontiguousarray(b.color, np.float64), opacity=np.ascontiguousarray(b.opacity, np.float64),
+            hw=np.ascontiguousarray(b.hw, np.int32), bg=np.ascontiguousarray(b.bg, np.float64))
+        k = self.keep
+        self.n_curves = int(len(k["degree"]))
+        self.channels = int(b.channels)
+        self.curves = _Curves(self.n_curves, self.channels, *[_p(k[n]) for n in (
+            "scene", "degree", "flags", "key_off", "tau_off", "key_xy", "key_w", "key_s", "tau", "color", "opacity")])
+        self.scenes = _Scenes(int(len(k["hw"])), _p(k["hw"]), _p(k["bg"]))
+        pr = dict(DEFAULTS)
+        pr.update({n: v for n, v in (params or {}).items() if n in DEFAULTS})
+        self.pdict = pr
+        self.params = _Params(*[float(pr[n]) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
+                                                      "fill_pad", "h", "alpha_max", "eps_T", "cutoff")],
+                              int(pr["kappa"]))
+
+    def refs(self):
+        return ctypes.byref(self.curves), ctypes.byref(self.scenes), ctypes.byref(self.params)
+
+
+def plan(batch, params=None):
+    """Per-curve plan [N][8] (count, n_samples, ix0, iy0, nx, ny, g_offset, near-int flag),
+    arc lengths L [N], and the total number of Gaussians."""
+    B = _Batch(batch, params)
+    pl = np.zeros((B.n_curves, 8), np.int32)
+    L = np.zeros(B.n_curves, np.float64)
+    G = lib().or_plan(*B.refs(), _p(pl), _p(L))
+    return pl, L, int(G)
+
+
+def gaussians(batch, params=None, frozen_plan=None):
+    """Gaussians in emission order: dict(mu [G,2], sigma, opacity, curve, local, plan, L)."""
+    B = _Batch(batch, params)
+    if frozen_plan is None:
+        pl, L, G = plan(batch, params)
+    else:
+        pl = np.ascontiguousarray(frozen_plan, np.int32)
+        L = None
+        G = int(pl[:, P_COUNT].sum())
+    mu = np.zeros((G, 2)); sg = np.zeros(G); op = np.zeros(G)
+    cv = np.zeros(G, np.int32); lc = np.zeros(G, np.int32)
+    lib().or_gaussians(*B.refs(), _p(pl), _p(mu), _p(sg), _p(op), _p(cv), _p(lc))
+    return dict(mu=mu, sigma=sg, opacity=op, curve=cv, local=lc, plan=pl, L=L)
+
+
+def tile_key_count(hw, tile):
+    hw = np.asarray(hw)
+    return int(sum(((h + tile - 1) // tile) * ((w + tile - 1) // tile) for h, w in hw))
+
+
+def bin_gaussians(batch, g, tile=16, k_sigma=6.0):
+    """Sec. 3.4 binning emulated in FP32 from the oracle's own centres: returns
+    (ranges [n_tiles, 2] int32, idx [pairs] int32)."""
+    hw = np.ascontiguousarray(batch.hw, np.int32)
+    sc = _Scenes(int(len(hw)), _p(hw), None)
+    gscene = np.ascontiguousarray(np.asarray(batch.scene, np.int32)[g["curve"]], np.int32)
+    mu = np.ascontiguousarray(g["mu"], np.float64)
+    sg = np.ascontiguousarray(g["sigma"], np.float64)
+    nt = tile_key_count(hw, tile)
+    ranges = np.zeros((nt, 2), np.int32)
+    n = lib().or_bin(len(sg), _p(mu), _p(sg), _p(gscene), ctypes.byref(sc), tile, float(k_sigma),
+                     _p(ranges), None, 0)
+    idx = np.zeros(max(n, 1), np.int32)
+    lib().or_bin(len(sg), _p(mu), _p(sg), _p(gscene), ctypes.byref(sc), tile, float(k_sigma),
+                 _p(ranges), _p(idx), n)
+    return ranges, idx[:n]
+
+
+def _image_layout(batch):
+    C = int(batch.channels)
+    hw = np.asarray(batch.hw)
+    n_img = int(sum(C * h * w for h, w in hw))
+    n_t = int(sum(h * w for h, w in hw))
+    return C, n_img, n_t
+
+
+def composite(batch, g, params=None, pixels=None, upstream=None):
+    """Eq. 8-9 by brute force.  pixels None: full images, returned flat
+    (per scene [C][H][W] concatenated) with T_final flat ([H][W] per scene).
+    pixels [n,3] (scene, y, x): values [n, C] and T [n].  With upstream (same
+    layout as the image) also returns adj [G, 7]: the gradient of
+    sum(upstream * I) w.r.t. (mx, my, sigma, opacity, colour[0..2]) per Gaussian."""
+    B = _Batch(batch, params)
+    C, n_img, n_t = _image_layout(batch)
+    G = len(g["sigma"])
+    mu = np.ascontiguousarray(g["mu"], np.float64)
+    sg = np.ascontiguousarray(g["sigma"], np.float64)
+    op = np.ascontiguousarray(g["opacity"], np.float64)
+    cv = np.ascontiguousarray(g["curve"], np.int32)
+    if pixels is None:
+        img = np.zeros(n_img); T = np.zeros(n_t); pix = None; npix = 0
+    else:
+        pix = np.ascontiguousarray(pixels, np.int32).reshape(-1, 3)
+        npix = len(pix)
+        img = np.zeros((npix, C)); T = np.zeros(npix)
+    up = None if upstream is None else np.ascontiguousarray(upstream, np.float64)
+    adj = np.zeros((G, 7)) if up is not None else None
+    lib().or_composite(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)), _p(mu), _p(sg), _p(op), _p(cv),
+                       G, npix, _p(pix), _p(img), _p(T), _p(up), _p(adj))
+    if up is None:
+        return img, T
+    return img, T, adj
+
+
+def param_grad(batch, g, adj, params=None):
+    """Gradient of the loss w.r.t. every curve parameter, given per-Gaussian adjoints."""
+    B = _Batch(batch, params)
+    k = B.keep
+    out = dict(key_xy=np.zeros_like(k["key_xy"]), key_w=np.zeros_like(k["key_w"]),
+               key_s=np.zeros_like(k["key_s"]), tau=np.zeros_like(k["tau"]),
+               color=np.zeros_like(k["color"]), opacity=np.zeros_like(k["opacity"]))
+    lib().or_param_grad_full(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
+                             _p(np.ascontiguousarray(adj, np.float64)),
+                             *[_p(out[n]) for n in ("key_xy", "key_w", "key_s", "tau", "color", "opacity")])
+    return out
+
+
+def param_grad_seeds(batch, g, adj, seeds, params=None):
+    """Selected gradient components; seeds [n, 3] = (curve, kind, local index)."""
+    B = _Batch(batch, params)
+    sd = np.ascontiguousarray(seeds, np.int32).reshape(-1, 3)
+    out = np.zeros(len(sd))
+    lib().or_param_grad_seeds(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
+                              _p(np.ascontiguousarray(adj, np.float64)), len(sd), _p(sd), _p(out))
+    return out
+
+
+def render(batch, params=None, frozen_plan=None):
+    g = gaussians(batch, params, frozen_plan)
+    img, T = composite(batch, g, params)
+    return img, T, g
+
+
+def loss_and_grad(batch, target, params=None, frozen_plan=None):
+    """L = sum (I - I*)^2 and its gradient w.r.t. every curve parameter (FP64)."""
+    g = gaussians(batch, params, frozen_plan)
+    img, T = composite(batch, g, params)
+    up = 2.0 * (img - target)
+    _, _, adj = composite(batch, g, params, upstream=up)
+    return float(np.sum((img - target) ** 2)), param_grad(batch, g, adj, params), g, img
+
+
+# --- single-curve geometry (closed-form tests) --------------------------------------
+
+def curve_knots(p, closed, tau, nk):
+    tau = np.ascontiguousarray(tau, np.float64)
+    U = np.zeros(len(tau) + 2 * p + 2)
+    n = lib().or_curve_knots(p, int(closed), nk, len(tau), _p(tau), _p(U))
+    return U[:n]
+
+
+def curve_eval(p, closed, key_xy, key_w, key_s, tau, t, full=False):
+    """(x, y, s, dx/du, dy/du, ds/du) at u = a + t (b - a)."""
+    kx = np.ascontiguousarray(key_xy, np.float64).reshape(-1, 2)
+    kw = np.ascontiguousarray(key_w, np.float64)
+    ks = np.ascontiguousarray(key_s, np.float64)
+    tu = np.ascontiguousarray(tau, np.float64)
+    t = np.ascontiguousarray(np.atleast_1d(t), np.float64)
+    out = np.zeros((len(t), 6))
+    lib().or_curve_eval(p, int(closed), len(kx), len(tu), _p(kx), _p(kw), _p(ks), _p(tu), len(t), _p(t),
+                        int(full), _p(out))
+    return out
+
+
+def basis_all(U, p, u):
+    U = np.ascontiguousarray(U, np.float64)
+    m = len(U) - 1
+    N = np.zeros(m - p); dN = np.zeros(m - p)
+    span = lib().or_basis_all(m, p, _p(U), float(u), _p(N), _p(dN))
+    return N, dN, span
+
+
+def arc_length(p, closed, key_xy, key_w, key_s, tau, n_L):
+    kx = np.ascontiguousarray(key_xy, np.float64).reshape(-1, 2)
+    kw = np.ascontiguousarray(key_w, np.float64)
+    ks = np.ascontiguousarray(key_s, np.float64)
+    tu = np.ascontiguousarray(tau, np.float64)
+    return lib().or_arc_length(p, int(closed), len(kx), len(tu), _p(kx), _p(kw), _p(ks), _p(tu), int(n_L))
+
+
+def sdf(poly, q):
+    b = np.ascontiguousarray(poly, np.float64).reshape(-1, 2)
+    out = np.zeros(3)
+    lib().or_sdf(len(b), _p(b), float(q[0]), float(q[1]), _p(out))
+    return out  # (d, wn, sdf)
+
+
+def anneal(t, T, hmax, hmin, tb, te):
+    return lib().or_anneal(float(t), float(T), float(hmax), float(hmin), float(tb), float(te))
+
+
+def num_threads():
+    return lib().or_num_threads()
+
+
+def timed(fn, *a, **kw):
+    t0 = time.perf_counter()
+    r = fn(*a, **kw)
+    return r, time.perf_counter() - t0
