@@ -1,0 +1,256 @@
+/* nsplat.h -- C ABI of the MI355X (gfx950) NURBS Splatting render path.
+ *
+ * The path (Qiu & Zhou, "NURBS Splatting", Sec. 3):
+ *   nsplat_sample    key points -> NURBS (Sec. 3.1) -> isotropic Gaussians:
+ *                    contour samples (Sec. 3.2, Eq. 3-5) and the SDF-modulated
+ *                    interior grid of filled closed curves (Sec. 3.3, Eq. 6-7,
+ *                    Suppl. S2 Eq. S1-S3)
+ *   nsplat_bin       Gaussians -> per-tile lists in stacking order (Sec. 3.4)
+ *   nsplat_forward   front-to-back alpha compositing (Sec. 3.4, Eq. 8-9)
+ *   nsplat_backward  exact adjoint of the three steps above, from dL/dImage to
+ *                    the key points, weights, widths, knot intervals, colours
+ *                    and opacities (the differentiability claim of Sec. 1/3.4)
+ *
+ * Conventions shared by every entry point
+ *   - Pointers marked (dev) are device pointers, (host) host pointers.  All
+ *     memory is owned by the caller; the library never allocates or frees
+ *     caller memory.  Internal scratch lives in the caller's workspace
+ *     (nsplat_workspace_size).
+ *   - Every call is stream-ordered on `stream` (a hipStream_t; NULL = the
+ *     default stream), never synchronises the device and never allocates, so
+ *     a sequence of calls can be captured into a HIP graph.  The only host
+ *     synchronising helper is nsplat_read_counters.
+ *   - Sizes that change from step to step (Gaussians, tile pairs, boundary
+ *     points) are computed on the device and stored in `counters`; buffers are
+ *     sized by capacities.  If a capacity is exceeded the excess is not
+ *     written, the required size is stored and a status bit is set; the caller
+ *     reads the counters, grows the buffer and calls again.
+ *   - Return value: NSPLAT_OK, or an error code with a message available from
+ *     nsplat_last_error.  Argument checks run on the host before any device
+ *     work is issued.  Value errors that only the device can see (a curve with
+ *     degree outside [1, NSPLAT_MAX_DEGREE], too few key points, a filled
+ *     curve that is not closed, a wrong interval count) set
+ *     NSPLAT_STATUS_DATA; such a curve produces no Gaussians.
+ *   - Coordinates are pixels, y pointing down; pixel (x, y) has its centre at
+ *     (x + 1/2, y + 1/2); a canvas spans [0, W] x [0, H].
+ */
+#ifndef NSPLAT_H
+#define NSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSPLAT_OK 0
+#define NSPLAT_EINVAL 1     /* bad argument, detected on the host            */
+#define NSPLAT_ECAPACITY 2  /* workspace or buffer smaller than required     */
+#define NSPLAT_EHIP 3       /* a HIP runtime call failed                     */
+
+#define NSPLAT_CLOSED 1     /* curve flag: closed (periodic knots, wrapped control polygon) */
+#define NSPLAT_FILLED 2     /* curve flag: filled interior (requires CLOSED) */
+#define NSPLAT_MAX_DEGREE 5
+
+/* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
+#define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
+#define NSPLAT_CNT_PAIRS 1      /* (tile, Gaussian) pairs produced           */
+#define NSPLAT_CNT_STATUS 2     /* OR of NSPLAT_STATUS_* bits                */
+#define NSPLAT_CNT_GAUSS_REQ 3  /* Gaussians required                        */
+#define NSPLAT_CNT_PAIRS_REQ 4  /* pairs required                            */
+#define NSPLAT_CNT_BOUND_REQ 5  /* boundary points required                  */
+#define NSPLAT_CNT_BOUND 6      /* boundary points produced                  */
+#define NSPLAT_NUM_COUNTERS 16
+
+#define NSPLAT_STATUS_GAUSS_CAP 1   /* Gaussian capacity exceeded             */
+#define NSPLAT_STATUS_PAIR_CAP 2    /* pair capacity exceeded                 */
+#define NSPLAT_STATUS_BOUND_CAP 4   /* boundary-point capacity exceeded       */
+#define NSPLAT_STATUS_DATA 8        /* invalid curve data (see above)         */
+
+/* plan[] row layout (dev int32[n_curves][8]) */
+#define NSPLAT_PLAN_COUNT 0   /* Gaussians of the curve                        */
+#define NSPLAT_PLAN_NSAMP 1   /* contour samples M (Sec. 3.2) or boundary points (Sec. 3.3) */
+#define NSPLAT_PLAN_IX0 2     /* fill lattice window: first column index       */
+#define NSPLAT_PLAN_IY0 3     /*                      first row index          */
+#define NSPLAT_PLAN_NX 4      /*                      columns                  */
+#define NSPLAT_PLAN_NY 5      /*                      rows                     */
+#define NSPLAT_PLAN_GOFF 6    /* index of the curve's first Gaussian           */
+#define NSPLAT_PLAN_BOFF 7    /* index of the curve's first boundary point     */
+#define NSPLAT_PLAN_STRIDE 8
+
+typedef struct nsplat_ctx nsplat_ctx;
+
+/* Curves, CSR over curves (Sec. 3.1).  Curves must be grouped by scene in
+ * ascending scene order; the Gaussian index order (curve by curve) is the
+ * stacking order: a later curve is drawn over an earlier one. */
+typedef struct {
+  int32_t n_curves;        /* (host)                                         */
+  int32_t channels;        /* (host) 1 or 3                                  */
+  int32_t n_keys;          /* (host) total key points K                      */
+  int32_t n_taus;          /* (host) total knot intervals                    */
+  const int32_t* scene;    /* (dev) [n_curves] scene of each curve           */
+  const int32_t* degree;   /* (dev) [n_curves] p                             */
+  const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED */
+  const int32_t* key_off;  /* (dev) [n_curves+1] into the key arrays         */
+  const int32_t* tau_off;  /* (dev) [n_curves+1] into tau; open curves hold
+                              n_k - p intervals, closed curves n_k           */
+  const float* key_xy;     /* (dev) [K][2] key points K_i                    */
+  const float* key_w;      /* (dev) [K] rational weights w_i > 0             */
+  const float* key_s;      /* (dev) [K] stroke widths (third coordinate) > 0 */
+  const float* tau;        /* (dev) knot intervals tau_j >= 0                */
+  const float* color;      /* (dev) [n_curves][channels]                     */
+  const float* opacity;    /* (dev) [n_curves]                               */
+} nsplat_curves;
+
+typedef struct {
+  int32_t n_scenes;        /* (host)                                         */
+  const int32_t* hw_host;  /* (host) [S][2] = {H, W}                         */
+  const int32_t* hw;       /* (dev)  [S][2], same values                     */
+  const float* bg;         /* (dev)  [S][channels] background colour         */
+} nsplat_scenes;
+
+/* Method constants (Table S1 of the paper) and rasteriser settings. */
+typedef struct {
+  float delta_c;    /* contour density, samples per px of arc length (10)    */
+  float delta_b;    /* fill boundary density (0.5)                           */
+  float rho;        /* global scale ratio, sigma = s / rho (2)               */
+  float eta;        /* fill coverage factor, sigma = eta h / rho (1.5)       */
+  float gamma;      /* SDF sigmoid sharpness (5)                             */
+  float nl_factor;  /* arc-length quadrature points N_L = nl_factor max(W,H) (3) */
+  float fill_pad;   /* fill box padding, fraction of the box extent (0.1)    */
+  float h;          /* fill grid step in px (1); see h_dev                   */
+  float k_sigma;    /* support radius in sigmas (6)                          */
+  float alpha_max;  /* per-pixel opacity clamp (0.99)                        */
+  float eps_T;      /* a pixel stops once its transmittance drops below (1e-6) */
+  int32_t kappa;    /* extra copies of each open-curve endpoint Gaussian (4) */
+  int32_t tile;     /* tile side in px: 8, 16 or 32                          */
+  int32_t batch;    /* Gaussians staged in LDS per block step: 32..256       */
+  const float* h_dev; /* (dev, optional) if non-NULL the grid step is read
+                         from here, so a captured graph can anneal it        */
+} nsplat_params;
+
+typedef struct {
+  int64_t gauss;      /* Gaussian records                                    */
+  int64_t pairs;      /* (tile, Gaussian) pairs                              */
+  int64_t boundary;   /* fill boundary points, all curves together           */
+} nsplat_caps;
+
+/* Buffers of one render state; all (dev) and caller-owned. */
+typedef struct {
+  int32_t* plan;      /* [n_curves][NSPLAT_PLAN_STRIDE]                      */
+  void* gauss;        /* [caps.gauss] records of 32 bytes:
+                         {double mx, my; float sigma, opacity; int32 curve, local} */
+  int32_t* ranges;    /* [n_tiles][2] slice [begin, end) of idx per tile     */
+  int32_t* idx;       /* [caps.pairs] Gaussian indices, ascending within a tile;
+                         front-to-back order is the slice read from its end  */
+  int32_t* counters;  /* [NSPLAT_NUM_COUNTERS]                               */
+  void* ws;           /* workspace, >= nsplat_workspace_size(...) bytes,
+                         256-byte aligned; must be kept unchanged from
+                         nsplat_sample to nsplat_backward                    */
+  size_t ws_bytes;
+  nsplat_caps caps;
+} nsplat_buffers;
+
+/* Parameter gradients (dev FP32, same shapes as the inputs; overwritten). */
+typedef struct {
+  float* key_xy;  /* [K][2] */
+  float* key_w;   /* [K]    */
+  float* key_s;   /* [K]    */
+  float* tau;     /* [n_taus] */
+  float* color;   /* [n_curves][channels] */
+  float* opacity; /* [n_curves] */
+} nsplat_grads;
+
+/* Context: binds the library to device `device` (made current by the caller's
+ * thread for every later call).  Holds the last error message and the
+ * autotuner's choices. */
+int nsplat_create(nsplat_ctx** ctx, int device);
+int nsplat_destroy(nsplat_ctx* ctx);
+const char* nsplat_last_error(const nsplat_ctx* ctx);
+
+/* Number of tiles over all scenes for the given tile side (host only). */
+int64_t nsplat_num_tiles(const nsplat_scenes* scenes, int32_t tile);
+
+/* Workspace bytes for this batch shape and these capacities (host only). */
+size_t nsplat_workspace_size(const nsplat_curves* curves, const nsplat_scenes* scenes,
+                             const nsplat_params* params, const nsplat_caps* caps);
+
+/* Sec. 3.1-3.3 (Eq. 1-7, S1-S3).  Builds knot vectors (cumulative sums of the
+ * intervals), measures each curve's arc length (Eq. 3, N_L midpoints), sets
+ * the counts M = ceil(delta_c L) (open >= 2, closed >= 3; open curves get
+ * kappa extra copies of each endpoint) or N_b = max(3, ceil(delta_b L)) with
+ * the fill lattice window, and writes one Gaussian record per sample: contour
+ * samples at u_j uniform in [u_p, u_{m-p}] evaluated span-locally in FP64
+ * (centre = C(u_j), sigma = s(u_j) / rho, opacity o), fill lattice points
+ * q = ((i + 1/2) h, (j + 1/2) h) in the padded box with sigma = eta h / rho
+ * and opacity o sigmoid(gamma / h sdf(q)).  frozen != 0 keeps the counts and
+ * windows already in bufs->plan (piecewise-constant sampling, e.g. for finite
+ * differences or graph replay) and only re-evaluates positions and opacities. */
+int nsplat_sample(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                  const nsplat_params* params, const nsplat_buffers* bufs, int frozen, void* stream);
+
+/* Sec. 3.4 binning.  Each Gaussian covers the tiles of its conservative
+ * rectangle, computed in FP32 from m = fl32(centre) and r = k_sigma * sigma as
+ * [(m - r) - 1, (m + r) + 1] per axis.  Pairs are produced in Gaussian order
+ * and sorted stably by (scene, tile) key with an LSD radix sort, so each
+ * tile's slice of idx lists its Gaussians in ascending index. */
+int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+               const nsplat_params* params, const nsplat_buffers* bufs, void* stream);
+
+/* Eq. 8-9.  Per pixel, front to back (descending Gaussian index):
+ * alpha = min(alpha_max, o exp(-|x - mu|^2 / (2 sigma^2))) for |x - mu| <=
+ * k_sigma sigma, colour += c alpha T, T *= 1 - alpha, stop once T < eps_T;
+ * image = colour + T bg.  image is per scene [channels][H][W], concatenated
+ * over scenes; T_final and n_last are per scene [H][W]: the final
+ * transmittance and the idx position where the pixel stopped.
+ * persistent != 0 runs one resident grid that pulls tiles from a device work
+ * queue instead of one block per tile (same results, bit for bit). */
+int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                   const nsplat_params* params, const nsplat_buffers* bufs, float* image,
+                   float* T_final, int32_t* n_last, int persistent, void* stream);
+
+/* Adjoint of nsplat_forward o nsplat_bin o nsplat_sample for the upstream
+ * gradient dL_dimage (layout of image).  Walks each pixel's list back to
+ * front from n_last, recovering the transmittance as T / (1 - alpha), and
+ * chains through the Gaussians into the Cox-de Boor basis (control points,
+ * weights, widths, knots -> intervals), the SDF (nearest segment, detached
+ * sign), the sample parameters u_j (which depend on the domain ends) and the
+ * key-point / interval parametrisation.  Counts, windows and span choices are
+ * held fixed (piecewise constant).  All gradients are overwritten. */
+int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                    const nsplat_params* params, const nsplat_buffers* bufs, const float* dL_dimage,
+                    const float* T_final, const int32_t* n_last, const nsplat_grads* grads,
+                    int persistent, void* stream);
+
+/* Eq. 14: writes h(t) = h_max + (h_min - h_max) (1 + cos(pi (1 - phi))) / 2,
+ * phi = clamp((t / T - t_b) / (t_e - t_b), 0, 1), to h_dev (dev float), with t
+ * read from step_dev (dev int32) when it is non-NULL (and then incremented),
+ * else from `step`.  Lets a captured graph anneal the fill grid step. */
+int nsplat_anneal_h(nsplat_ctx* ctx, float* h_dev, int32_t* step_dev, int32_t step, int32_t total_steps,
+                    float h_max, float h_min, float t_b, float t_e, void* stream);
+
+/* Helper kernels that a captured step needs: out[i] = 2 (a[i] - b[i]) for
+ * i < n, and sum((a - b)^2) added into *loss (dev, FP32). */
+int nsplat_l2_grad(nsplat_ctx* ctx, const float* a, const float* b, float* out, float* loss, int64_t n,
+                   void* stream);
+
+/* Copies the counters to host memory and waits for them (synchronising). */
+int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bufs, int32_t* host_out, void* stream);
+
+/* Autotuner: times nsplat_bin + nsplat_forward + nsplat_backward on the given
+ * state for every tile side in {8, 16, 32} and batch depth in
+ * {32, 64, 128, 256} (after one warm-up each), and returns the fastest in
+ * *best_tile / *best_batch.  The buffers must be sized for the largest tile
+ * count (tile 8) and pair count (tile 8 has the most pairs).  times_ms, if
+ * non-NULL, receives the 12 timings in (tile, batch) row-major order. */
+int nsplat_autotune(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                    const nsplat_params* params, const nsplat_buffers* bufs, float* image, float* T_final,
+                    int32_t* n_last, const float* dL_dimage, const nsplat_grads* grads, int persistent,
+                    int32_t* best_tile, int32_t* best_batch, float* times_ms, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSPLAT_H */

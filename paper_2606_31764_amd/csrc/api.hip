@@ -1,0 +1,370 @@
+// C ABI of the library (declared in include/nsplat.h): context, host-side
+// argument checks, workspace carve-out, the four render-path entry points,
+// the annealing / loss helpers and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "nsplat_internal.h"
+
+struct nsplat_ctx {
+  int device = 0;
+  int n_cu = 256;
+  std::string err;
+};
+
+namespace nsp {
+hipError_t launch_zero_grads(const Launch& L);
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_caps* caps) {
+  Layout lay;
+  const int64_t N = cv->n_curves, K = cv->n_keys, T = cv->n_taus, S = sc->n_scenes;
+  const int64_t gcap = caps->gauss, pcap = caps->pairs, bcap = caps->boundary;
+  lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
+  const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, 1});
+  lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
+  const size_t sizes[17] = {
+      sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
+      sizeof(double) * (size_t)N,                          // L
+      sizeof(int32_t) * (size_t)(N + 1),                   // goff
+      sizeof(double2) * (size_t)std::max<int64_t>(bcap, 1),  // bpts
+      sizeof(SceneTab) * (size_t)(S + 1),                  // scenes
+      sizeof(uint32_t) * (size_t)(gcap + 1),               // gcnt
+      sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys0
+      sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys1
+      sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // vals1
+      sizeof(uint32_t) * (size_t)(256 * std::max<int64_t>(lay.sort_blocks, 1)),  // hist
+      sizeof(uint32_t) * (size_t)(lay.scan_blocks + 1),    // scan_tmp
+      sizeof(float) * 8 * (size_t)std::max<int64_t>(gcap, 1),  // ggrad
+      sizeof(double) * 4 * (size_t)(K + N * CP_PAD),       // gcp
+      sizeof(double) * (size_t)(T + N * KNOT_PAD),         // gknot
+      sizeof(double) * 4 * (size_t)N,                      // gcurve
+      sizeof(double2) * (size_t)std::max<int64_t>(bcap, 1),  // gb
+      sizeof(int32_t) * 64,                                // queue
+  };
+  size_t off = 0;
+  for (int i = 0; i < 17; ++i) {
+    lay.off[i] = off;
+    off += align256(sizes[i]);
+  }
+  lay.total = off;
+  return lay;
+}
+
+Work carve(void* ws, const Layout& lay) {
+  char* b = (char*)ws;
+  Work w;
+  w.knots = (double*)(b + lay.off[0]);
+  w.L = (double*)(b + lay.off[1]);
+  w.goff = (int32_t*)(b + lay.off[2]);
+  w.bpts = (double2*)(b + lay.off[3]);
+  w.scenes = (SceneTab*)(b + lay.off[4]);
+  w.gcnt = (uint32_t*)(b + lay.off[5]);
+  w.keys0 = (uint32_t*)(b + lay.off[6]);
+  w.keys1 = (uint32_t*)(b + lay.off[7]);
+  w.vals1 = (uint32_t*)(b + lay.off[8]);
+  w.hist = (uint32_t*)(b + lay.off[9]);
+  w.scan_tmp = (uint32_t*)(b + lay.off[10]);
+  w.ggrad = (float*)(b + lay.off[11]);
+  w.gcp = (double*)(b + lay.off[12]);
+  w.gknot = (double*)(b + lay.off[13]);
+  w.gcurve = (double*)(b + lay.off[14]);
+  w.gb = (double2*)(b + lay.off[15]);
+  w.queue = (int32_t*)(b + lay.off[16]);
+  return w;
+}
+
+}  // namespace nsp
+
+using namespace nsp;
+
+namespace {
+
+int fail(nsplat_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(nsplat_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, NSPLAT_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int check_curves(nsplat_ctx* ctx, const nsplat_curves* cv) {
+  if (!cv) return fail(ctx, NSPLAT_EINVAL, "curves is NULL");
+  if (cv->n_curves < 0 || cv->n_keys < 0 || cv->n_taus < 0)
+    return fail(ctx, NSPLAT_EINVAL, "negative size in curves (n_curves=%d n_keys=%d n_taus=%d)", cv->n_curves,
+                cv->n_keys, cv->n_taus);
+  if (cv->channels != 1 && cv->channels != 3)
+    return fail(ctx, NSPLAT_EINVAL, "channels must be 1 or 3 (got %d)", cv->channels);
+  if (cv->n_curves > 0) {
+    const void* ptrs[11] = {cv->scene, cv->degree, cv->flags, cv->key_off, cv->tau_off, cv->key_xy,
+                            cv->key_w, cv->key_s, cv->color, cv->opacity, cv->n_taus > 0 ? (const void*)cv->tau
+                                                                                         : (const void*)cv};
+    const char* names[11] = {"scene", "degree", "flags", "key_off", "tau_off", "key_xy",
+                             "key_w", "key_s", "color", "opacity", "tau"};
+    for (int i = 0; i < 11; ++i)
+      if (!ptrs[i]) return fail(ctx, NSPLAT_EINVAL, "curves.%s is NULL", names[i]);
+  }
+  return NSPLAT_OK;
+}
+
+int check_scenes(nsplat_ctx* ctx, const nsplat_scenes* sc) {
+  if (!sc) return fail(ctx, NSPLAT_EINVAL, "scenes is NULL");
+  if (sc->n_scenes < 1) return fail(ctx, NSPLAT_EINVAL, "n_scenes must be >= 1 (got %d)", sc->n_scenes);
+  if (!sc->hw_host || !sc->hw || !sc->bg) return fail(ctx, NSPLAT_EINVAL, "scenes.hw_host / hw / bg is NULL");
+  int64_t pix = 0;
+  for (int s = 0; s < sc->n_scenes; ++s) {
+    const int H = sc->hw_host[2 * s], W = sc->hw_host[2 * s + 1];
+    if (H < 1 || W < 1 || H > 32767 || W > 32767)
+      return fail(ctx, NSPLAT_EINVAL, "scene %d has invalid size %dx%d", s, H, W);
+    pix += (int64_t)H * W;
+  }
+  if (pix > 0x7fffffffLL / 3) return fail(ctx, NSPLAT_EINVAL, "too many pixels over all scenes");
+  return NSPLAT_OK;
+}
+
+int check_params(nsplat_ctx* ctx, const nsplat_params* pr) {
+  if (!pr) return fail(ctx, NSPLAT_EINVAL, "params is NULL");
+  if (pr->tile != 8 && pr->tile != 16 && pr->tile != 32)
+    return fail(ctx, NSPLAT_EINVAL, "tile must be 8, 16 or 32 (got %d)", pr->tile);
+  if (pr->batch < 1 || pr->batch > MAX_BATCH)
+    return fail(ctx, NSPLAT_EINVAL, "batch must be in [1, %d] (got %d)", MAX_BATCH, pr->batch);
+  if (!(pr->rho > 0.f) || !(pr->delta_c > 0.f) || !(pr->delta_b > 0.f) || !(pr->eta > 0.f) || !(pr->nl_factor > 0.f))
+    return fail(ctx, NSPLAT_EINVAL, "rho, delta_c, delta_b, eta and nl_factor must be > 0");
+  if (!(pr->h > 0.f) && !pr->h_dev) return fail(ctx, NSPLAT_EINVAL, "h must be > 0");
+  if (!(pr->alpha_max > 0.f && pr->alpha_max < 1.f))
+    return fail(ctx, NSPLAT_EINVAL, "alpha_max must be in (0, 1) (got %g)", (double)pr->alpha_max);
+  if (!(pr->k_sigma > 0.f)) return fail(ctx, NSPLAT_EINVAL, "k_sigma must be > 0");
+  if (!(pr->eps_T >= 0.f)) return fail(ctx, NSPLAT_EINVAL, "eps_T must be >= 0");
+  if (pr->kappa < 0) return fail(ctx, NSPLAT_EINVAL, "kappa must be >= 0");
+  if (!(pr->fill_pad >= 0.f)) return fail(ctx, NSPLAT_EINVAL, "fill_pad must be >= 0");
+  return NSPLAT_OK;
+}
+
+int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_buffers* bf) {
+  if (!bf) return fail(ctx, NSPLAT_EINVAL, "buffers is NULL");
+  if (bf->caps.gauss < 0 || bf->caps.pairs < 0 || bf->caps.boundary < 0)
+    return fail(ctx, NSPLAT_EINVAL, "negative capacity");
+  if (bf->caps.gauss > 0x7fffffffLL || bf->caps.pairs > 0x7fffffffLL || bf->caps.boundary > 0x7fffffffLL)
+    return fail(ctx, NSPLAT_EINVAL, "capacity above 2^31 - 1");
+  if (!bf->plan || !bf->gauss || !bf->ranges || !bf->idx || !bf->counters || !bf->ws)
+    return fail(ctx, NSPLAT_EINVAL, "a buffer pointer is NULL");
+  if (((uintptr_t)bf->ws & 255) != 0) return fail(ctx, NSPLAT_EINVAL, "workspace must be 256-byte aligned");
+  const Layout lay = workspace_layout(cv, sc, &bf->caps);
+  if (bf->ws_bytes < lay.total)
+    return fail(ctx, NSPLAT_ECAPACITY, "workspace has %zu bytes, %zu required", bf->ws_bytes, lay.total);
+  return NSPLAT_OK;
+}
+
+int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+            const nsplat_buffers* bf, void* stream, Launch* L) {
+  if (!ctx) return NSPLAT_EINVAL;
+  int e;
+  if ((e = check_curves(ctx, cv)) || (e = check_scenes(ctx, sc)) || (e = check_params(ctx, pr)) ||
+      (e = check_bufs(ctx, cv, sc, bf)))
+    return e;
+  L->cv = cv;
+  L->sc = sc;
+  L->pr = pr;
+  L->bf = bf;
+  L->lay = workspace_layout(cv, sc, &bf->caps);
+  L->w = carve(bf->ws, L->lay);
+  L->stream = (hipStream_t)stream;
+  L->n_tiles = nsplat_num_tiles(sc, pr->tile);
+  L->n_cu = ctx->n_cu;
+  return NSPLAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsplat_create(nsplat_ctx** out, int device) {
+  if (!out) return NSPLAT_EINVAL;
+  *out = nullptr;
+  nsplat_ctx* c = new nsplat_ctx();
+  c->device = device;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    c->err = "no such HIP device";
+    *out = c;
+    return NSPLAT_EHIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  *out = c;
+  return NSPLAT_OK;
+}
+
+int nsplat_destroy(nsplat_ctx* ctx) {
+  delete ctx;
+  return NSPLAT_OK;
+}
+
+const char* nsplat_last_error(const nsplat_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int64_t nsplat_num_tiles(const nsplat_scenes* sc, int32_t tile) {
+  if (!sc || !sc->hw_host || tile <= 0) return 0;
+  int64_t n = 0;
+  for (int s = 0; s < sc->n_scenes; ++s)
+    n += (int64_t)((sc->hw_host[2 * s] + tile - 1) / tile) * ((sc->hw_host[2 * s + 1] + tile - 1) / tile);
+  return n;
+}
+
+size_t nsplat_workspace_size(const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                             const nsplat_caps* caps) {
+  (void)pr;
+  if (!cv || !sc || !caps) return 0;
+  return workspace_layout(cv, sc, caps).total;
+}
+
+int nsplat_sample(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                  const nsplat_buffers* bf, int frozen, void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  hipError_t h = launch_fill_u32((uint32_t*)bf->counters, 0u, NSPLAT_NUM_COUNTERS, L.stream);
+  if (h == hipSuccess) h = launch_scene_setup(L);
+  if (h == hipSuccess && cv->n_curves > 0) h = launch_sample(L, frozen);
+  if (h == hipSuccess && cv->n_curves == 0) h = launch_fill_u32((uint32_t*)L.w.goff, 0u, 1, L.stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_sample");
+  return NSPLAT_OK;
+}
+
+int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+               const nsplat_buffers* bf, void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  hipError_t h = launch_scene_setup(L);
+  if (h == hipSuccess) h = launch_bin(L);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
+  return NSPLAT_OK;
+}
+
+int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                   const nsplat_buffers* bf, float* image, float* T_final, int32_t* n_last, int persistent,
+                   void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  if (!image || !T_final || !n_last) return fail(ctx, NSPLAT_EINVAL, "image / T_final / n_last is NULL");
+  hipError_t h = launch_scene_setup(L);
+  if (h == hipSuccess) h = launch_blend_fwd(L, image, T_final, n_last, persistent);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_forward");
+  return NSPLAT_OK;
+}
+
+int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                    const nsplat_buffers* bf, const float* dL, const float* T_final, const int32_t* n_last,
+                    const nsplat_grads* gr, int persistent, void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  if (!dL || !T_final || !n_last || !gr) return fail(ctx, NSPLAT_EINVAL, "dL_dimage / T_final / n_last / grads is NULL");
+  if (cv->n_curves > 0 && (!gr->key_xy || !gr->key_w || !gr->key_s || !gr->color || !gr->opacity ||
+                           (cv->n_taus > 0 && !gr->tau)))
+    return fail(ctx, NSPLAT_EINVAL, "a gradient pointer is NULL");
+  hipError_t h = launch_scene_setup(L);
+  if (h == hipSuccess) h = launch_zero_grads(L);
+  if (h == hipSuccess) h = launch_blend_bwd(L, dL, T_final, n_last, persistent);
+  if (h == hipSuccess && cv->n_curves > 0) h = launch_adjoint(L, gr);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_backward");
+  return NSPLAT_OK;
+}
+
+int nsplat_anneal_h(nsplat_ctx* ctx, float* h_dev, int32_t* step_dev, int32_t step, int32_t total, float hmax,
+                    float hmin, float tb, float te, void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  if (!h_dev) return fail(ctx, NSPLAT_EINVAL, "h_dev is NULL");
+  if (total <= 0 || !(te > tb)) return fail(ctx, NSPLAT_EINVAL, "need total_steps > 0 and t_e > t_b");
+  hipError_t h = launch_anneal(h_dev, step_dev, step, total, hmax, hmin, tb, te, (hipStream_t)stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_anneal_h");
+  return NSPLAT_OK;
+}
+
+int nsplat_l2_grad(nsplat_ctx* ctx, const float* a, const float* b, float* out, float* loss, int64_t n,
+                   void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  if (n < 0 || (n > 0 && (!a || !b || !out))) return fail(ctx, NSPLAT_EINVAL, "bad arguments to nsplat_l2_grad");
+  hipError_t h = launch_l2(a, b, out, loss, n, (hipStream_t)stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_l2_grad");
+  return NSPLAT_OK;
+}
+
+int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bf, int32_t* host_out, void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  if (!bf || !bf->counters || !host_out) return fail(ctx, NSPLAT_EINVAL, "bad arguments to nsplat_read_counters");
+  hipError_t h = hipMemcpyAsync(host_out, bf->counters, sizeof(int32_t) * NSPLAT_NUM_COUNTERS,
+                                hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (h == hipSuccess) h = hipStreamSynchronize((hipStream_t)stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_read_counters");
+  return NSPLAT_OK;
+}
+
+int nsplat_autotune(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                    const nsplat_buffers* bf, float* image, float* T_final, int32_t* n_last, const float* dL,
+                    const nsplat_grads* gr, int persistent, int32_t* best_tile, int32_t* best_batch,
+                    float* times_ms, void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  if (!best_tile || !best_batch) return fail(ctx, NSPLAT_EINVAL, "best_tile / best_batch is NULL");
+  static const int tiles[3] = {8, 16, 32};
+  static const int batches[4] = {32, 64, 128, 256};
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(ctx, NSPLAT_EHIP, "hipEventCreate failed");
+  float best = 1e30f;
+  int rc = NSPLAT_OK;
+  *best_tile = pr->tile;
+  *best_batch = pr->batch;
+  for (int ti = 0; ti < 3 && rc == NSPLAT_OK; ++ti)
+    for (int bi = 0; bi < 4 && rc == NSPLAT_OK; ++bi) {
+      nsplat_params p = *pr;
+      p.tile = tiles[ti];
+      p.batch = batches[bi];
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == NSPLAT_OK; ++rep) {
+        if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = NSPLAT_EHIP;
+        if (rc == NSPLAT_OK) rc = nsplat_bin(ctx, cv, sc, &p, bf, stream);
+        if (rc == NSPLAT_OK) rc = nsplat_forward(ctx, cv, sc, &p, bf, image, T_final, n_last, persistent, stream);
+        if (rc == NSPLAT_OK)
+          rc = nsplat_backward(ctx, cv, sc, &p, bf, dL, T_final, n_last, gr, persistent, stream);
+        if (rep == 1 && rc == NSPLAT_OK) {
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = NSPLAT_EHIP;
+        }
+      }
+      if (rc != NSPLAT_OK) break;
+      int32_t cnt[NSPLAT_NUM_COUNTERS];
+      rc = nsplat_read_counters(ctx, bf, cnt, stream);
+      if (rc == NSPLAT_OK && (cnt[NSPLAT_CNT_STATUS] & NSPLAT_STATUS_PAIR_CAP)) ms = 1e30f;  // did not fit
+      if (times_ms) times_ms[ti * 4 + bi] = ms;
+      if (ms < best) {
+        best = ms;
+        *best_tile = tiles[ti];
+        *best_batch = batches[bi];
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == NSPLAT_EHIP && ctx->err.empty()) ctx->err = "autotune: HIP event error";
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+// nsplat_bin: Gaussians -> per-tile lists (Sec. 3.4).
+//
+//   k_bin_count   one lane per Gaussian: conservative tile rectangle in FP32
+//   scan          exclusive prefix sum of the counts -> pair offsets
+//   k_bin_emit    writes (global tile key, Gaussian index) pairs in Gaussian order
+//   radix passes  stable LSD radix sort on the key (histogram, scan, scatter
+//                 with wavefront match-ranking), so each tile keeps ascending
+//                 Gaussian order
+//   k_tile_ranges [begin, end) of every tile's slice
+#include "nsplat_internal.h"
+
+namespace nsp {
+
+namespace {
+
+struct Rect {
+  int x0, x1, y0, y1;
+};
+
+// Tile rectangle of one Gaussian: centre m = fl32(mu), r = k_sigma * sigma in
+// FP32, interval [(m - r) - 1, (m + r) + 1], tile = floor(x / tile), clamped.
+__device__ inline bool tile_rect(const Gauss& gs, float k_sigma, float inv_tile, const SceneTab& st, Rect* rc) {
+  const float mx = (float)gs.mx, my = (float)gs.my;
+  const float r = k_sigma * gs.sigma;
+  const float xl = (mx - r) - 1.0f, xh = (mx + r) + 1.0f;
+  const float yl = (my - r) - 1.0f, yh = (my + r) + 1.0f;
+  if (!(xl == xl) || !(xh == xh) || !(yl == yl) || !(yh == yh)) return false;
+  const float fx0 = fmaxf(0.0f, floorf(xl * inv_tile)), fx1 = fminf((float)(st.tiles_x - 1), floorf(xh * inv_tile));
+  const float fy0 = fmaxf(0.0f, floorf(yl * inv_tile)), fy1 = fminf((float)(st.tiles_y - 1), floorf(yh * inv_tile));
+  if (fx0 > fx1 || fy0 > fy1) return false;
+  rc->x0 = (int)fx0;
+  rc->x1 = (int)fx1;
+  rc->y0 = (int)fy0;
+  rc->y1 = (int)fy1;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(nsplat_curves cv, nsplat_params pr, Work w,
+                                                   const Gauss* __restrict__ gs, const int32_t* counters,
+                                                   uint32_t* __restrict__ cnt) {
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const float inv = 1.0f / (float)pr.tile;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+    const Gauss r = gs[g];
+    const SceneTab st = w.scenes[cv.scene[r.curve]];
+    Rect rc;
+    uint32_t n = 0;
+    if (tile_rect(r, pr.k_sigma, inv, st, &rc)) n = (uint32_t)((rc.x1 - rc.x0 + 1) * (rc.y1 - rc.y0 + 1));
+    cnt[g] = n;
+  }
+}
+
+__global__ void k_pairs_total(int32_t* counters, const uint32_t* total, int64_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t t = *total;
+  counters[NSPLAT_CNT_PAIRS_REQ] = t > 0x7fffffffu ? 0x7fffffff : (int32_t)t;
+  counters[NSPLAT_CNT_PAIRS] = (int32_t)((int64_t)t < cap ? (int64_t)t : cap);
+  int32_t st = counters[NSPLAT_CNT_STATUS] & ~NSPLAT_STATUS_PAIR_CAP;
+  if ((int64_t)t > cap) st |= NSPLAT_STATUS_PAIR_CAP;
+  counters[NSPLAT_CNT_STATUS] = st;
+}
+
+__global__ __launch_bounds__(256) void k_bin_emit(nsplat_curves cv, nsplat_params pr, Work w,
+                                                  const Gauss* __restrict__ gs, const int32_t* counters,
+                                                  const uint32_t* __restrict__ off, uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ vals, int64_t cap) {
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const float inv = 1.0f / (float)pr.tile;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+    const Gauss r = gs[g];
+    const SceneTab st = w.scenes[cv.scene[r.curve]];
+    Rect rc;
+    if (!tile_rect(r, pr.k_sigma, inv, st, &rc)) continue;
+    int64_t pos = off[g];
+    for (int ty = rc.y0; ty <= rc.y1; ++ty)
+      for (int tx = rc.x0; tx <= rc.x1; ++tx, ++pos)
+        if (pos < cap) {
+          keys[pos] = (uint32_t)(st.tile_off + ty * st.tiles_x + tx);
+          vals[pos] = (uint32_t)g;
+        }
+  }
+}
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ROUNDS = SORT_ITEMS / SORT_THREADS;  // 16
+constexpr int SORT_WAVES = SORT_THREADS / 64;
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             const int32_t* counters, int shift, int bits,
+                                                             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int64_t n = counters[NSPLAT_CNT_PAIRS];
+  const int nb = gridDim.x;
+  const uint32_t mask = (1u << bits) - 1u;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+  for (int i = 0; i < SORT_ROUNDS; ++i) {
+    const int64_t k = base + (int64_t)i * SORT_THREADS + threadIdx.x;
+    if (k < n) atomicAdd(&h[(keys[k] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < (1 << bits)) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter.  Round i handles items base + i * 256 + t, so ascending
+// (round, thread) is ascending input order; each item's rank among the
+// earlier items of the block with the same digit comes from wavefront ballots
+// (lanes whose digit matches in every bit) plus per-wave and per-round running
+// counts kept in LDS.
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                                const uint32_t* __restrict__ vin,
+                                                                uint32_t* __restrict__ kout,
+                                                                uint32_t* __restrict__ vout,
+                                                                const int32_t* counters, int shift, int bits,
+                                                                const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t base_off[256];
+  __shared__ uint32_t wcnt[SORT_WAVES][256];
+  const int64_t n = counters[NSPLAT_CNT_PAIRS];
+  const int nb = gridDim.x;
+  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+  if (base >= n) return;
+  const uint32_t mask = (1u << bits) - 1u;
+  const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
+  base_off[t] = (t < (1 << bits)) ? hist[(int64_t)t * nb + blockIdx.x] : 0u;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int i = 0; i < SORT_ROUNDS; ++i) {
+#pragma unroll
+    for (int q = 0; q < SORT_WAVES; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    const int64_t k = base + (int64_t)i * SORT_THREADS + t;
+    const bool active = k < n;
+    uint32_t key = 0, val = 0, dig = 0;
+    if (active) {
+      key = kin[k];
+      val = vin[k];
+      dig = (key >> shift) & mask;
+    }
+    uint64_t peers = __ballot(active);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    if (active && rank == 0) wcnt[wid][dig] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    // per digit: exclusive prefix over waves, then advance the running offset
+    if (t < (1 << bits)) {
+      uint32_t run = base_off[t];
+#pragma unroll
+      for (int q = 0; q < SORT_WAVES; ++q) {
+        const uint32_t c = wcnt[q][t];
+        wcnt[q][t] = run;
+        run += c;
+      }
+      base_off[t] = run;
+    }
+    __syncthreads();
+    if (active) {
+      const uint32_t pos = wcnt[wid][dig] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, const int32_t* counters,
+                                                     int32_t* __restrict__ ranges) {
+  const int64_t n = counters[NSPLAT_CNT_PAIRS];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (int32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (int32_t)(i + 1);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_bin(const Launch& L) {
+  const int64_t gcap = L.bf->caps.gauss, pcap = L.bf->caps.pairs;
+  int32_t* cnt = L.bf->counters;
+  const Gauss* gs = (const Gauss*)L.bf->gauss;
+  const int gg = grid_for(gcap, 256, 8192);
+  hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt);
+  hipError_t e = launch_scan(L.w.gcnt, cnt + NSPLAT_CNT_GAUSS, gcap, L.w.gcnt + gcap, L.w.scan_tmp, L.stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, L.stream, cnt, L.w.gcnt + gcap, pcap);
+  // number of key bits and radix passes (up to 8 bits each)
+  int key_bits = 0;
+  while (key_bits < 31 && ((int64_t)1 << key_bits) < L.n_tiles) ++key_bits;
+  const int passes = (key_bits + 7) / 8;
+  const int digit = passes ? (key_bits + passes - 1) / passes : 0;
+  uint32_t* idx = (uint32_t*)L.bf->idx;
+  // the last pass must land in (keys0, idx)
+  uint32_t* ek = (passes % 2) ? L.w.keys1 : L.w.keys0;
+  uint32_t* ev = (passes % 2) ? L.w.vals1 : idx;
+  hipLaunchKernelGGL(k_bin_emit, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt, ek, ev,
+                     pcap);
+  const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
+  uint32_t *kin = ek, *vin = ev;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * digit;
+    const int bits = (key_bits - shift) < digit ? (key_bits - shift) : digit;
+    uint32_t* kout = (kin == L.w.keys0) ? L.w.keys1 : L.w.keys0;
+    uint32_t* vout = (vin == idx) ? L.w.vals1 : idx;
+    if (sb > 0) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, cnt, shift, bits, L.w.hist);
+      e = launch_scan(L.w.hist, nullptr, (int64_t)(1 << bits) * sb, nullptr, L.w.scan_tmp, L.stream);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout, cnt,
+                         shift, bits, L.w.hist);
+    }
+    kin = kout;
+    vin = vout;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.n_tiles, 256, 4096)), dim3(256), 0, L.stream,
+                     L.bf->ranges, 0, 2 * L.n_tiles);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
+                     L.bf->ranges);
+  return hipGetLastError();
+}
+
+}  // namespace nsp

@@ -1,0 +1,267 @@
+// Internal declarations of the gfx950 NURBS Splatting library: the Gaussian
+// record, the workspace carve-out, scene table, and the device-side NURBS
+// helpers (span search, Cox-de Boor basis with first derivative, curve point).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nsplat.h"
+
+namespace nsp {
+
+constexpr int MAXP = NSPLAT_MAX_DEGREE;
+constexpr int KNOT_PAD = 2 * MAXP + 1;  // knots of curve c start at tau_off[c] + c * KNOT_PAD
+constexpr int CP_PAD = MAXP;            // control points of curve c start at key_off[c] + c * CP_PAD
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LN2 = 0.69314718055994530942;
+constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
+constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
+constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
+
+// One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
+// form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
+// to half an ulp: 3e-5 px at 512 px, too coarse for a 1e-5 image tolerance).
+struct __align__(16) Gauss {
+  double mx, my;
+  float sigma, opacity;
+  int32_t curve, local;
+};
+static_assert(sizeof(Gauss) == 32, "Gaussian record must be 32 bytes");
+
+struct SceneTab {
+  int32_t H, W, tiles_x, tiles_y, tile_off, pix_off, n_L, pad;
+};
+
+enum { P_COUNT = 0, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_BOFF, P_STRIDE };
+
+// Device pointers carved out of the caller's workspace.
+struct Work {
+  double* knots;       // [n_taus + n_curves * KNOT_PAD]
+  double* L;           // [n_curves]
+  int32_t* goff;       // [n_curves + 1]
+  double2* bpts;       // [caps.boundary]
+  SceneTab* scenes;    // [n_scenes + 1]
+  uint32_t* gcnt;      // [caps.gauss + 1] pair counts, then their offsets
+  uint32_t* keys0;     // [caps.pairs]
+  uint32_t* keys1;     // [caps.pairs]
+  uint32_t* vals1;     // [caps.pairs]
+  uint32_t* hist;      // [256 * sort_blocks]
+  uint32_t* scan_tmp;  // [scan_blocks + 1]
+  float* ggrad;        // [caps.gauss][8] per-Gaussian adjoints
+  double* gcp;         // [(n_keys + n_curves * CP_PAD)][4] control-point adjoints (x, y, w, s)
+  double* gknot;       // [n_taus + n_curves * KNOT_PAD]
+  double* gcurve;      // [n_curves][4] (opacity, colour 0..2)
+  double2* gb;         // [caps.boundary] boundary-point adjoints
+  int32_t* queue;      // [4] work-queue counters of the persistent kernels
+};
+
+struct Layout {
+  size_t off[17];
+  size_t total;
+  int64_t sort_blocks, scan_blocks;
+};
+
+Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_caps* caps);
+Work carve(void* ws, const Layout& lay);
+
+// ---------------------------------------------------------------------------
+// Curve view: degree, sizes and where its knots live.
+// ---------------------------------------------------------------------------
+struct CurveView {
+  int p, nk, nt, flags, m, ncp, k0, t0;
+  const double* U;
+  __device__ bool closed() const { return (flags & NSPLAT_CLOSED) != 0; }
+  __device__ bool filled() const { return (flags & NSPLAT_FILLED) != 0; }
+  // Closed curves wrap the last ceil(p/2) key points in front (Sec. 3.1).
+  __device__ int key_of_cp(int j) const {
+    if (!closed()) return j;
+    int k = j - (p + 1) / 2;
+    k %= nk;
+    return k < 0 ? k + nk : k;
+  }
+};
+
+__device__ inline CurveView curve_view(const nsplat_curves& cv, const double* knots, int c) {
+  CurveView v;
+  v.p = cv.degree[c];
+  v.flags = cv.flags[c];
+  v.k0 = cv.key_off[c];
+  v.nk = cv.key_off[c + 1] - v.k0;
+  v.t0 = cv.tau_off[c];
+  v.nt = cv.tau_off[c + 1] - v.t0;
+  const bool closed = (v.flags & NSPLAT_CLOSED) != 0;
+  v.ncp = closed ? v.nk + v.p : v.nk;
+  v.m = v.nt + 2 * v.p;
+  v.U = knots + v.t0 + (int64_t)c * KNOT_PAD;
+  return v;
+}
+
+__device__ inline bool curve_valid(const CurveView& v) {
+  if (v.p < 1 || v.p > MAXP) return false;
+  if (v.nk < v.p + 1) return false;
+  if (v.nt != (v.closed() ? v.nk : v.nk - v.p)) return false;
+  if (v.filled() && !v.closed()) return false;
+  return true;
+}
+
+// Knot span of u: the largest i in [p, m-p-1] with U[i] <= u < U[i+1]; at or
+// past the right end of the domain, the last non-empty span.
+__device__ inline int find_span(const double* U, int p, int m, double u) {
+  const int lo = p, hi = m - p - 1;
+  if (u >= U[hi + 1]) {
+    int i = hi;
+    while (i > lo && !(U[i] < U[i + 1])) --i;
+    return i;
+  }
+  int a = lo, b = hi + 1;  // U[a] <= u < U[b] once u >= U[lo]
+  if (!(U[lo] <= u)) {
+    int i = lo;
+    while (i < hi && !(U[i] < U[i + 1])) ++i;
+    return i;
+  }
+  while (b - a > 1) {
+    const int mid = (a + b) >> 1;
+    if (U[mid] <= u) a = mid;
+    else b = mid;
+  }
+  return a;
+}
+
+// Non-zero B-spline basis functions on a non-empty span (Cox-de Boor in the
+// triangular "left/right" form): N[r] = N_{span-p+r, p}(u), r = 0..p, and if
+// dN != nullptr their u-derivatives from the degree p-1 functions,
+// N'_{i,p} = p (N_{i,p-1} / (U_{i+p} - U_i) - N_{i+1,p-1} / (U_{i+p+1} - U_{i+1})).
+// On a non-empty span no denominator can vanish.
+__device__ inline void basis_funs(const double* U, int span, int p, double u, double (&N)[MAXP + 1],
+                                  double* dN) {
+  double left[MAXP + 1], right[MAXP + 1];
+  N[0] = 1.0;
+#pragma unroll
+  for (int r = 1; r <= MAXP; ++r) N[r] = 0.0;
+#pragma unroll
+  for (int d = 1; d <= MAXP; ++d) {
+    if (d > p) break;
+    if (d == p && dN != nullptr) {
+#pragma unroll
+      for (int r = 0; r <= MAXP; ++r) {
+        if (r > p) break;
+        double v = 0.0;
+        if (r >= 1) v += N[r - 1] / (U[span + r] - U[span - p + r]);
+        if (r <= p - 1) v -= N[r] / (U[span + r + 1] - U[span - p + r + 1]);
+        dN[r] = (double)p * v;
+      }
+    }
+    left[d] = u - U[span + 1 - d];
+    right[d] = U[span + d] - u;
+    double saved = 0.0;
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      const double temp = N[r] / (right[r + 1] + left[d - r]);
+      N[r] = saved + right[r + 1] * temp;
+      saved = left[d - r] * temp;
+    }
+    N[d] = saved;
+  }
+}
+
+// Rational curve point (x, y, width) at u on `span` (Eq. 1 / Eq. 4) and, if
+// d != nullptr, its u-derivative by the quotient rule (Eq. 2).
+__device__ inline void curve_point(const nsplat_curves& cv, const CurveView& v, double u, int span,
+                                   double (&pt)[3], double* d) {
+  double N[MAXP + 1], dN[MAXP + 1];
+  basis_funs(v.U, span, v.p, u, N, d ? dN : nullptr);
+  double S[3] = {0.0, 0.0, 0.0}, Sd[3] = {0.0, 0.0, 0.0}, W = 0.0, Wd = 0.0;
+#pragma unroll
+  for (int r = 0; r <= MAXP; ++r) {
+    if (r > v.p) break;
+    const int k = v.k0 + v.key_of_cp(span - v.p + r);
+    const double w = (double)cv.key_w[k];
+    const double P[3] = {(double)cv.key_xy[2 * k], (double)cv.key_xy[2 * k + 1], (double)cv.key_s[k]};
+    const double nw = N[r] * w;
+    W += nw;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S[q] += nw * P[q];
+    if (d) {
+      const double dnw = dN[r] * w;
+      Wd += dnw;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Sd[q] += dnw * P[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) pt[q] = S[q] / W;
+  if (d) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d[q] = (W * Sd[q] - S[q] * Wd) / (W * W);
+  }
+}
+
+// Sample parameter j of `count` uniform samples in the domain [a, b]: open
+// curves include both ends (the last sample is b exactly), closed curves
+// exclude the closure point.  dt returns du/db (du/da = 1 - dt).
+__device__ inline double sample_u(double a, double b, int j, int count, bool closed, double* dt) {
+  if (!closed) {
+    if (j >= count - 1) {
+      if (dt) *dt = 1.0;
+      return b;
+    }
+    const double step = (b - a) / (double)(count - 1);
+    if (dt) *dt = (double)j / (double)(count - 1);
+    return a + (double)j * step;
+  }
+  const double step = (b - a) / (double)count;
+  if (dt) *dt = (double)j / (double)count;
+  return a + (double)j * step;
+}
+
+__device__ inline float read_h(const nsplat_params& pr) { return pr.h_dev ? *pr.h_dev : pr.h; }
+
+// Scene of a global tile index (binary search over the scene table).
+__device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) {
+  int lo = 0, hi = n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid].tile_off <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (host side), one per kernel family.
+// ---------------------------------------------------------------------------
+struct Launch {
+  const nsplat_curves* cv;
+  const nsplat_scenes* sc;
+  const nsplat_params* pr;
+  const nsplat_buffers* bf;
+  Work w;
+  Layout lay;
+  hipStream_t stream;
+  int64_t n_tiles;
+  int n_cu;
+};
+
+hipError_t launch_scene_setup(const Launch& L);
+hipError_t launch_sample(const Launch& L, int frozen);
+hipError_t launch_bin(const Launch& L);
+hipError_t launch_blend_fwd(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent);
+hipError_t launch_blend_bwd(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last,
+                            int persistent);
+hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_scan(uint32_t* data, const int32_t* n_dev, int64_t n_cap, uint32_t* total_out, uint32_t* tmp,
+                       hipStream_t s);
+hipError_t launch_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t total, float hmax, float hmin,
+                         float tb, float te, hipStream_t s);
+hipError_t launch_l2(const float* a, const float* b, float* out, float* loss, int64_t n, hipStream_t s);
+
+inline int grid_for(int64_t n, int threads, int max_blocks) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+}  // namespace nsp

@@ -1,0 +1,383 @@
+// nsplat_sample: NURBS curves -> isotropic Gaussians (Sec. 3.1-3.3).
+//
+//   k_scene_setup   per-scene tile / pixel offsets and N_L (Table S1)
+//   k_curve_prep    one block per curve: knot vector (cumulative sum of the
+//                   intervals, Sec. 3.1), arc length by N_L midpoints (Eq. 3,
+//                   Eq. 2 for C'), contour count M = ceil(delta_c L) or
+//                   boundary count N_b = ceil(delta_b L) (Sec. 3.2 / 3.3)
+//   k_curve_scan    exclusive scans over curves (boundary offsets, Gaussian
+//                   offsets), capacity checks
+//   k_boundary      one block per filled curve: N_b boundary points in FP64,
+//                   padded AABB, global lattice window (Sec. 3.3)
+//   k_emit          one lane per Gaussian: span search and span-local
+//                   Cox-de Boor evaluation (Eq. 4-5), or the fill lattice
+//                   point with its SDF opacity (Eq. 6-7, S1-S3)
+#include "nsplat_internal.h"
+
+namespace nsp {
+
+namespace {
+
+constexpr int PREP_THREADS = 256;
+
+__global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t toff = 0, poff = 0;
+  for (int s = 0; s < sc.n_scenes; ++s) {
+    SceneTab t;
+    t.H = sc.hw[2 * s];
+    t.W = sc.hw[2 * s + 1];
+    t.tiles_x = (t.W + pr.tile - 1) / pr.tile;
+    t.tiles_y = (t.H + pr.tile - 1) / pr.tile;
+    t.tile_off = toff;
+    t.pix_off = poff;
+    t.n_L = (int32_t)llrint((double)pr.nl_factor * (double)(t.H > t.W ? t.H : t.W));
+    t.pad = 0;
+    st[s] = t;
+    toff += t.tiles_x * t.tiles_y;
+    poff += t.H * t.W;
+  }
+  SceneTab e = {};
+  e.tile_off = toff;
+  e.pix_off = poff;
+  st[sc.n_scenes] = e;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < PREP_THREADS / 64; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ inline int count_rule(double delta, double L, int floor_min) {
+  const double x = delta * L;
+  const double M = ceil(x);
+  if (!(M >= (double)floor_min)) return floor_min;  // also catches NaN
+  if (M > 2.0e9) return 2000000000;
+  return (int)M;
+}
+
+__global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, nsplat_params pr, Work w,
+                                                             int32_t* plan, int32_t* counters, int frozen,
+                                                             int n_scenes) {
+  __shared__ double red[PREP_THREADS / 64];
+  const int c = blockIdx.x;
+  const CurveView v = curve_view(cv, w.knots, c);
+  int32_t* row = plan + (int64_t)P_STRIDE * c;
+  const int s = cv.scene[c];
+  if (!curve_valid(v) || s < 0 || s >= n_scenes) {
+    if (threadIdx.x == 0) {
+      row[P_COUNT] = 0;
+      row[P_NSAMP] = 0;
+      w.L[c] = 0.0;
+      atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_DATA);
+    }
+    return;
+  }
+  // Knot vector: U_0 = 0, U_{l+1} = U_l + delta_l with the interval list of
+  // Sec. 3.1 (open: p zeros, tau, p zeros; closed: last p tau, tau, first p).
+  double* U = w.knots + v.t0 + (int64_t)c * KNOT_PAD;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    U[0] = 0.0;
+    for (int l = 0; l < v.m; ++l) {
+      double d;
+      if (!v.closed()) d = (l < v.p || l >= v.p + v.nt) ? 0.0 : (double)cv.tau[v.t0 + l - v.p];
+      else {
+        int t = (l - v.p) % v.nt;
+        if (t < 0) t += v.nt;
+        d = (double)cv.tau[v.t0 + t];
+      }
+      acc = acc + d;
+      U[l + 1] = acc;
+    }
+  }
+  __syncthreads();
+  // Eq. 3: L = sum_j ||C'(u_j)|| du over N_L midpoints of [u_p, u_{m-p}].
+  const SceneTab* st = w.scenes + s;
+  const int n_L = st->n_L;
+  const double a = U[v.p], b = U[v.m - v.p];
+  const double du = (b - a) / (double)n_L;
+  double part = 0.0;
+  for (int j = 1 + threadIdx.x; j <= n_L; j += PREP_THREADS) {
+    const double u = a + ((double)j - 0.5) * du;
+    const int span = find_span(U, v.p, v.m, u);
+    double pt[3], d[3];
+    curve_point(cv, v, u, span, pt, d);
+    part += sqrt(d[0] * d[0] + d[1] * d[1]) * du;
+  }
+  const double L = block_sum(part, red);
+  if (threadIdx.x == 0) {
+    w.L[c] = L;
+    if (!frozen) {
+      if (!v.filled()) {
+        const int M = count_rule((double)pr.delta_c, L, v.closed() ? 3 : 2);
+        row[P_NSAMP] = M;
+        row[P_COUNT] = v.closed() ? M : M + 2 * pr.kappa;
+        row[P_IX0] = row[P_IY0] = row[P_NX] = row[P_NY] = 0;
+      } else {
+        row[P_NSAMP] = count_rule((double)pr.delta_b, L, 3);
+      }
+    }
+  }
+}
+
+// Exclusive scan over curves of one plan column into another (single block).
+// which == 0: boundary points of filled curves -> P_BOFF, total to
+// counters[BOUND_REQ]; which == 1: Gaussians -> P_GOFF and goff[], total to
+// counters[GAUSS_REQ], capped total to counters[GAUSS].
+__global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* plan, int32_t* goff,
+                                                     int32_t* counters, int which, int64_t cap) {
+  __shared__ int64_t wsum[16];
+  const int n = cv.n_curves;
+  const int per = (n + 1023) / 1024;
+  const int c0 = threadIdx.x * per;
+  int64_t s = 0;
+  for (int i = 0; i < per; ++i) {
+    const int c = c0 + i;
+    if (c < n) {
+      const int32_t* row = plan + (int64_t)P_STRIDE * c;
+      if (which == 0) s += ((cv.flags[c] & NSPLAT_FILLED) && row[P_NSAMP] > 0) ? row[P_NSAMP] : 0;
+      else s += row[P_COUNT];
+    }
+  }
+  // block exclusive scan of s
+  int64_t incl = s;
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int64_t base = 0, tot = 0;
+  for (int i = 0; i < 16; ++i) {
+    if (i < wid) base += wsum[i];
+    tot += wsum[i];
+  }
+  int64_t run = base + incl - s;
+  for (int i = 0; i < per; ++i) {
+    const int c = c0 + i;
+    if (c < n) {
+      int32_t* row = plan + (int64_t)P_STRIDE * c;
+      if (which == 0) {
+        row[P_BOFF] = (int32_t)run;
+        if ((cv.flags[c] & NSPLAT_FILLED) && row[P_NSAMP] > 0) run += row[P_NSAMP];
+      } else {
+        row[P_GOFF] = (int32_t)run;
+        goff[c] = (int32_t)run;
+        run += row[P_COUNT];
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int32_t t32 = tot > 0x7fffffff ? 0x7fffffff : (int32_t)tot;
+    if (which == 0) {
+      counters[NSPLAT_CNT_BOUND_REQ] = t32;
+      counters[NSPLAT_CNT_BOUND] = (int32_t)(tot < cap ? tot : cap);
+      if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_BOUND_CAP);
+    } else {
+      goff[n] = t32;
+      counters[NSPLAT_CNT_GAUSS_REQ] = t32;
+      counters[NSPLAT_CNT_GAUSS] = (int32_t)(tot < cap ? tot : cap);
+      if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_GAUSS_CAP);
+    }
+  }
+}
+
+// Boundary points b_j = C(u_j), u_j = u_p + j (u_{m-p} - u_p) / N_b, their
+// padded AABB clipped to the canvas, and the lattice window
+// i in [ceil(x0 / h - 1/2), floor(x1 / h - 1/2)] (same for rows).
+__global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsplat_params pr, Work w,
+                                                           int32_t* plan, int64_t cap, int frozen) {
+  __shared__ double red[4][PREP_THREADS / 64];
+  const int c = blockIdx.x;
+  if (!(cv.flags[c] & NSPLAT_FILLED)) return;
+  const CurveView v = curve_view(cv, w.knots, c);
+  if (!curve_valid(v)) return;
+  int32_t* row = plan + (int64_t)P_STRIDE * c;
+  const int nb = row[P_NSAMP];
+  const int64_t boff = row[P_BOFF];
+  if (nb <= 0 || boff + nb > cap) {
+    if (threadIdx.x == 0) row[P_COUNT] = 0;
+    return;
+  }
+  const double a = v.U[v.p], b = v.U[v.m - v.p];
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  for (int j = threadIdx.x; j < nb; j += PREP_THREADS) {
+    const double u = sample_u(a, b, j, nb, true, nullptr);
+    double pt[3];
+    curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, nullptr);
+    w.bpts[boff + j] = make_double2(pt[0], pt[1]);
+    x0 = fmin(x0, pt[0]);
+    x1 = fmax(x1, pt[0]);
+    y0 = fmin(y0, pt[1]);
+    y1 = fmax(y1, pt[1]);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    x0 = fmin(x0, __shfl_xor(x0, off));
+    x1 = fmax(x1, __shfl_xor(x1, off));
+    y0 = fmin(y0, __shfl_xor(y0, off));
+    y1 = fmax(y1, __shfl_xor(y1, off));
+  }
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = x0;
+    red[1][t >> 6] = x1;
+    red[2][t >> 6] = y0;
+    red[3][t >> 6] = y1;
+  }
+  __syncthreads();
+  if (t == 0 && !frozen) {
+    for (int i = 1; i < PREP_THREADS / 64; ++i) {
+      x0 = fmin(x0, red[0][i]);
+      x1 = fmax(x1, red[1][i]);
+      y0 = fmin(y0, red[2][i]);
+      y1 = fmax(y1, red[3][i]);
+    }
+    x0 = fmin(x0, red[0][0]);
+    x1 = fmax(x1, red[1][0]);
+    y0 = fmin(y0, red[2][0]);
+    y1 = fmax(y1, red[3][0]);
+    const SceneTab* st = w.scenes + cv.scene[c];
+    const double h = (double)read_h(pr), pad = (double)pr.fill_pad;
+    const double px = pad * (x1 - x0), py = pad * (y1 - y0);
+    const double bx0 = fmax(0.0, x0 - px), bx1 = fmin((double)st->W, x1 + px);
+    const double by0 = fmax(0.0, y0 - py), by1 = fmin((double)st->H, y1 + py);
+    const int ix0 = (int)ceil(bx0 / h - 0.5), ix1 = (int)floor(bx1 / h - 0.5);
+    const int iy0 = (int)ceil(by0 / h - 0.5), iy1 = (int)floor(by1 / h - 0.5);
+    const int nx = ix1 - ix0 + 1 > 0 ? ix1 - ix0 + 1 : 0;
+    const int ny = iy1 - iy0 + 1 > 0 ? iy1 - iy0 + 1 : 0;
+    row[P_IX0] = ix0;
+    row[P_IY0] = iy0;
+    row[P_NX] = nx;
+    row[P_NY] = ny;
+    row[P_COUNT] = nx * ny;
+  }
+}
+
+// Signed distance of q to the closed polyline b[0..nb) (Suppl. S2): minimum
+// distance over segments (projection clamped to [0, 1], lowest index wins a
+// tie) and the sign of the exact integer winding number (crossing rule with
+// orientation tests); inside <=> winding >= 1.  Returns the argmin segment
+// and its projection parameter.
+__device__ inline double polyline_sdf(double qx, double qy, const double2* __restrict__ bp, int nb, int* arg,
+                                      double* targ, double* sgn_out) {
+  double best = INFINITY, tbest = 0.0;
+  int ibest = 0, wn = 0;
+  double2 A = bp[0];
+  for (int i = 0; i < nb; ++i) {
+    const double2 B = bp[i + 1 < nb ? i + 1 : 0];
+    const double ex = B.x - A.x, ey = B.y - A.y;
+    const double ee = ex * ex + ey * ey;
+    const double rx = qx - A.x, ry = qy - A.y;
+    double t = 0.0;
+    if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+    const double d2 = px * px + py * py;
+    if (d2 < best) {
+      best = d2;
+      ibest = i;
+      tbest = t;
+    }
+    const double cr = ex * ry - rx * ey;  // > 0: q left of A->B
+    if (A.y <= qy) {
+      if (B.y > qy && cr > 0.0) ++wn;
+    } else {
+      if (B.y <= qy && cr < 0.0) --wn;
+    }
+    A = B;
+  }
+  *arg = ibest;
+  *targ = tbest;
+  *sgn_out = wn >= 1 ? 1.0 : -1.0;
+  return sqrt(best);
+}
+
+// One lane per Gaussian.  Emission order per curve: open strokes kappa copies
+// of sample 0, samples 0..M-1, kappa copies of sample M-1; closed strokes
+// samples 0..M-1; fills the lattice window row by row.
+__global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
+                                              const int32_t* counters, Gauss* __restrict__ out) {
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const int n = cv.n_curves;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+    // curve: the last c with goff[c] <= g
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (w.goff[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const int c = lo;
+    const CurveView v = curve_view(cv, w.knots, c);
+    const int32_t* row = plan + (int64_t)P_STRIDE * c;
+    const int local = (int)(g - w.goff[c]);
+    Gauss r;
+    r.curve = c;
+    r.local = local;
+    const double o = (double)cv.opacity[c];
+    if (!v.filled()) {
+      const int M = row[P_NSAMP];
+      int j = v.closed() ? local : local - pr.kappa;
+      j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
+      const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), nullptr);
+      double pt[3];
+      curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, nullptr);
+      r.mx = pt[0];
+      r.my = pt[1];
+      r.sigma = (float)(pt[2] / (double)pr.rho);  // Eq. 5
+      r.opacity = (float)o;
+    } else {
+      const int nx = row[P_NX];
+      const int iy = local / nx, ix = local - iy * nx;
+      const double h = (double)read_h(pr);
+      const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
+      const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
+      int arg;
+      double t, sgn;
+      const double d = polyline_sdf(qx, qy, w.bpts + row[P_BOFF], row[P_NSAMP], &arg, &t, &sgn);
+      const double z = ((double)pr.gamma / h) * (sgn * d);
+      r.mx = qx;
+      r.my = qy;
+      r.sigma = (float)((double)pr.eta * h / (double)pr.rho);  // Eq. 6
+      r.opacity = (float)(o * (1.0 / (1.0 + exp(-z))));        // Eq. 7
+    }
+    out[g] = r;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_scene_setup(const Launch& L) {
+  hipLaunchKernelGGL(k_scene_setup, dim3(1), dim3(64), 0, L.stream, *L.sc, *L.pr, L.w.scenes);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const Launch& L, int frozen) {
+  const int n = L.cv->n_curves;
+  int32_t* plan = L.bf->plan;
+  int32_t* cnt = L.bf->counters;
+  hipLaunchKernelGGL(k_curve_prep, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan, cnt, frozen,
+                     L.sc->n_scenes);
+  hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
+                     (int64_t)L.bf->caps.boundary);
+  hipLaunchKernelGGL(k_boundary, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
+                     (int64_t)L.bf->caps.boundary, frozen);
+  hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 1,
+                     (int64_t)L.bf->caps.gauss);
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv, *L.pr,
+                     L.w, plan, cnt, (Gauss*)L.bf->gauss);
+  return hipGetLastError();
+}
+
+}  // namespace nsp

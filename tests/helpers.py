@@ -1,0 +1,61 @@
+"""Shared test helpers: run the GPU path and the oracle on the same seeded batch."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+IMG_TOL = 1e-5      # max abs image difference vs the FP64 oracle
+GRAD_RTOL = 1e-4    # gradients: relative to the largest component of the group
+GRAD_ATOL = 1e-6
+PARAM_NAMES = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+
+
+def oracle_params(p):
+    """The oracle's parameter dict from a render.Params (FP32-rounded like the GPU sees them)."""
+    d = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
+                                                       "fill_pad", "h", "alpha_max", "eps_T")}
+    d["kappa"] = int(p.kappa)
+    return d
+
+
+def gpu_run(batch, params, target=None, persistent=False, backward=True, caps=None):
+    """sample -> bin -> forward (-> L2 backward against target) on the GPU."""
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    r = Renderer(batch, params, caps=caps, persistent=persistent)
+    t = param_tensors(batch)
+    img = r.run_forward(t).clone()
+    out = dict(renderer=r, image=img.cpu().numpy().astype(np.float64), T=r.T.cpu().numpy().astype(np.float64),
+               n_last=r.n_last.cpu().numpy(), plan=r.plan_np(), gauss=r.gaussians(), counters=r.read_counters())
+    ranges, idx = r.tiles()
+    out["ranges"], out["idx"] = ranges, idx
+    if backward and target is not None:
+        tgt = torch.as_tensor(np.asarray(target, np.float32), device="cuda")
+        dL = 2.0 * (img - tgt)
+        grads = r.backward(t, dL)
+        torch.cuda.synchronize()
+        out["grads"] = {n: g.cpu().numpy().astype(np.float64) for n, g in zip(PARAM_NAMES, grads)}
+        out["dL"] = dL.cpu().numpy().astype(np.float64)
+    return out
+
+
+def grad_close(g, ref, rtol=GRAD_RTOL, atol=GRAD_ATOL):
+    """Per parameter group: max |g - ref| <= rtol * max |ref| + atol.  Returns the worst ratio."""
+    worst = 0.0
+    for n in PARAM_NAMES:
+        a, b = np.asarray(g[n], np.float64).ravel(), np.asarray(ref[n], np.float64).ravel()
+        if b.size == 0:
+            continue
+        bound = rtol * np.abs(b).max() + atol
+        worst = max(worst, float(np.abs(a - b).max() / bound))
+    return worst
+
+
+def grad_report(g, ref):
+    lines = []
+    for n in PARAM_NAMES:
+        a, b = np.asarray(g[n], np.float64).ravel(), np.asarray(ref[n], np.float64).ravel()
+        if b.size:
+            lines.append("%s: max|d|=%.3g max|ref|=%.3g" % (n, np.abs(a - b).max(), np.abs(b).max()))
+    return "; ".join(lines)

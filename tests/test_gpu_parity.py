@@ -1,0 +1,103 @@
+"""GPU path vs the FP64 oracle on the same seeded inputs (staged and end to end).
+
+Sizes are small enough for the brute-force oracle to finish in seconds but
+span several tiles with ragged edges (canvases that are not tile multiples).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import IMG_TOL, grad_close, grad_report, gpu_run, oracle_params
+from paper_2606_31764_amd import synth
+from paper_2606_31764_amd.render import Params
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    return {
+        "c1": (synth.config1(), Params().replace(delta_c=1.5)),
+        "c2s": (synth.config2(seed=2100, n_curves=8, size=120), Params().replace(delta_c=3.0)),
+        "c3s_h2": (synth.config3(seed=3100, n_paths=10, size=100), Params().replace(h=2.0)),
+        "c3s_h1": (synth.config3(seed=3200, n_paths=6, size=72), Params().replace(h=1.0)),
+        "c4s": (synth.config4(seed=4100, n_curves=2, n_cp=60, size=200), Params().replace(delta_c=10.0)),
+    }
+
+
+CASES = _cases()
+
+
+def _target(name):
+    b, p = CASES[name]
+    if name == "c1":
+        tb = synth.config1(1001)
+    else:
+        tb = synth.perturbed(b, seed=99)
+    return oracle.render(tb, oracle_params(p))[0]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_plan_and_gaussians(name):
+    b, p = CASES[name]
+    op = oracle_params(p)
+    ref = oracle.gaussians(b, op)
+    out = gpu_run(b, p, backward=False)
+    print(name, "G =", out["counters"][0], "pairs =", out["counters"][1], flush=True)
+    assert out["counters"][2] == 0, "status bits %d" % out["counters"][2]
+    # counts, sample numbers, fill windows, offsets: bit-exact
+    np.testing.assert_array_equal(out["plan"][:, :7], ref["plan"][:, :7])
+    g = out["gauss"]
+    assert len(g["sigma"]) == len(ref["sigma"])
+    np.testing.assert_array_equal(g["curve"], ref["curve"])
+    np.testing.assert_array_equal(g["local"], ref["local"])
+    assert np.abs(g["mu"] - ref["mu"]).max() < 1e-9
+    np.testing.assert_allclose(g["sigma"], ref["sigma"].astype(np.float32), rtol=2e-7, atol=0)
+    assert np.abs(g["opacity"] - ref["opacity"]).max() < 2e-7
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_bin_bitexact(name, tile):
+    b, p = CASES[name]
+    p = p.replace(tile=tile)
+    ref_g = oracle.gaussians(b, oracle_params(p))
+    ranges_ref, idx_ref = oracle.bin_gaussians(b, ref_g, tile=tile, k_sigma=p.k_sigma)
+    out = gpu_run(b, p, backward=False)
+    np.testing.assert_array_equal(out["ranges"], ranges_ref)
+    np.testing.assert_array_equal(out["idx"], idx_ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_end_to_end(name):
+    b, p = CASES[name]
+    img_ref, T_ref, _ = oracle.render(b, oracle_params(p))
+    out = gpu_run(b, p, backward=False)
+    err = np.abs(out["image"] - img_ref).max()
+    print(name, "image max abs err", err, flush=True)
+    assert err <= IMG_TOL
+    assert np.abs(out["T"] - T_ref).max() <= IMG_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_end_to_end(name):
+    b, p = CASES[name]
+    op = oracle_params(p)
+    target = _target(name)
+    out = gpu_run(b, p, target=target)
+    _, gref, _, img_ref = oracle.loss_and_grad(b, target, op)
+    worst = grad_close(out["grads"], gref)
+    print(name, "grad worst ratio", worst, grad_report(out["grads"], gref), flush=True)
+    assert worst <= 1.0, grad_report(out["grads"], gref)
+
+
+@pytest.mark.parametrize("name", ["c2s", "c3s_h2"])
+def test_persistent_matches_plain(name):
+    b, p = CASES[name]
+    target = _target(name)
+    a = gpu_run(b, p, target=target, persistent=False)
+    c = gpu_run(b, p, target=target, persistent=True)
+    np.testing.assert_array_equal(a["image"], c["image"])
+    np.testing.assert_array_equal(a["n_last"], c["n_last"])
+    assert grad_close(c["grads"], a["grads"], rtol=1e-5, atol=1e-7) <= 1.0
