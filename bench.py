@@ -1,0 +1,354 @@
+"""Benchmark of the NURBS Splatting render path on one MI355X.
+
+A step is one pass of the whole path over one batch: nsplat_sample ->
+nsplat_bin -> nsplat_forward -> L2 loss gradient -> nsplat_backward.
+Workload: 256 filled closed degree-2/3 paths (6-24 key points, radii 5-80 px)
+on a 512x512 RGB canvas at fill grid step h = 1 (about 1M Gaussians), seeded
+synthetic data.  Prints one JSON line.
+
+Also measured (same JSON line): the batched form (64 uneven scenes, one
+persistent launch sequence captured in a HIP graph) against per-scene plain
+launches, and the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = dict(hbm_gbs=8000.0, fp32_tflops=157.3, fp64_tflops=78.6)
+PHASES = ["plan", "emit", "bin", "sort", "ranges", "blend_fwd", "blend_bwd", "adj_gauss", "adj_bound", "fold"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    return ap.parse_args()
+
+
+class Step:
+    """Pre-sized render state + the device-side L2 gradient of one workload."""
+
+    def __init__(self, batch, params, target, persistent=False, ctx=None):
+        import torch
+        from paper_2606_31764_amd.render import Renderer, param_tensors
+        self.torch = torch
+        self.r = Renderer(batch, params, persistent=persistent, ctx=ctx)
+        self.t = param_tensors(batch)
+        self.target = torch.as_tensor(np.asarray(target, np.float32), device="cuda")
+        self.dL = torch.empty_like(self.target)
+        self.loss = torch.zeros(1, device="cuda")
+        self.r.run_forward(self.t)                      # sizes every buffer (synchronising)
+        cnt = self.r.read_counters()
+        self.G, self.pairs = cnt[0], cnt[1]
+
+    def run(self):
+        """One step, no host synchronisation."""
+        r, c = self.r, self.r.ctx
+        r.sample(self.t, sync=False)
+        r.bin(self.t, sync=False)
+        img = r.forward(self.t)
+        c.check(c.lib.nsplat_l2_grad(c.h, ctypes.c_void_p(img.data_ptr()), ctypes.c_void_p(self.target.data_ptr()),
+                                     ctypes.c_void_p(self.dL.data_ptr()), ctypes.c_void_p(self.loss.data_ptr()),
+                                     img.numel(), ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)))
+        return r.backward(self.t, self.dL)
+
+
+def timing_on(ctx, on):
+    ctx.check(ctx.lib.nsplat_timing(ctx.h, int(on)))
+
+
+def timing_read(ctx):
+    ms = (ctypes.c_double * 10)()
+    n = (ctypes.c_int64 * 10)()
+    ctx.check(ctx.lib.nsplat_timing_read(ctx.h, ms, n))
+    return {PHASES[i]: (ms[i], n[i]) for i in range(10)}
+
+
+def blend_work(step, tile):
+    """Algorithmic work of one forward blend launch, counted with torch on the
+    GPU from the launch's own tile lists and stopping positions: evaluated
+    (pixel, Gaussian) pairs and in-support pairs."""
+    import torch
+    r = step.r
+    G = step.G
+    raw = r.gauss[:G]
+    u8 = raw.view(torch.uint8).view(G, 32)
+    mx, my = raw[:, 0], raw[:, 1]
+    sigma = u8[:, 16:20].contiguous().view(torch.float32).view(G).double()
+    ranges, idx = r.ranges, r.idx
+    H, W = int(r.meta.hw_host[0][0]), int(r.meta.hw_host[0][1])
+    tx_n = (W + tile - 1) // tile
+    n_tiles = tx_n * ((H + tile - 1) // tile)
+    rg = ranges[:n_tiles].long()
+    lens = rg[:, 1] - rg[:, 0]
+    P = int(lens.sum().item())
+    tile_of = torch.repeat_interleave(torch.arange(n_tiles, device="cuda"), lens)
+    pos = torch.arange(P, device="cuda")
+    gidx = idx[:P].long()
+    stop = r.n_last.view(H, W).long()
+    ev = 0
+    hit = 0
+    ks = r.params.k_sigma
+    for ly in range(tile):
+        for lx in range(tile):
+            x = (tile_of % tx_n) * tile + lx
+            y = (tile_of // tx_n) * tile + ly
+            ok = (x < W) & (y < H)
+            xs, ys = x.clamp(max=W - 1), y.clamp(max=H - 1)
+            st = stop[ys, xs]
+            e = ok & (pos >= st)
+            dx = xs.double() + 0.5 - mx[gidx]
+            dy = ys.double() + 0.5 - my[gidx]
+            h = e & (dx * dx + dy * dy <= (ks * sigma[gidx]) ** 2)
+            ev += int(e.sum().item())
+            hit += int(h.sum().item())
+    return ev, hit
+
+
+# FP32 operations per pair in the forward blend loop (a fused multiply-add counts 2):
+# distance test 2 sub + mul + fma(2) + cmp = 6; in support: mul, exp2, mul, min,
+# mul (alpha T), 3 fma (6), sub, mul, cmp = 15.
+FWD_TEST_FLOPS, FWD_HIT_FLOPS = 6, 15
+
+
+def bench_main(args):
+    import torch
+    from paper_2606_31764_amd import synth
+    from paper_2606_31764_amd.render import Params, Renderer, param_tensors
+
+    torch.cuda.init()
+    b = synth.config3()
+    p = Params().replace(h=1.0, tile=args.tile, batch=args.batch)
+    log("workload: 256 filled paths, 512x512, h=1")
+    # target: the same generator's ground truth, perturbed (P + N(0, 2^2), ...)
+    tr = Renderer(synth.perturbed(b, seed=3999), p)
+    target = tr.run_forward(param_tensors(synth.perturbed(b, seed=3999))).clone().cpu().numpy()
+    del tr
+    st = Step(b, p, target)
+    log("G = %d, pairs = %d" % (st.G, st.pairs))
+    for _ in range(args.warmup):
+        st.run()
+    torch.cuda.synchronize()
+    ctx = st.r.ctx
+    timing_on(ctx, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        st.run()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    phases = timing_read(ctx)
+    timing_on(ctx, False)
+    ms_step = total_ms / args.steps
+    log("ms/step %.4f" % ms_step)
+    for k, (ms, n) in phases.items():
+        if n:
+            log("  %-10s %8.4f ms/launch  (%d launches)" % (k, ms / n, n))
+    # dominant single-kernel phase
+    single = ["emit", "blend_fwd", "blend_bwd", "adj_gauss", "adj_bound"]
+    dom = max(single, key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0] / max(phases[dom][1], 1)
+    roof = roofline(st, dom, dom_ms, p)
+    out = dict(metric="fwd+bwd Gaussians/s (512x512, ~1M splats)", value=st.G / (ms_step * 1e-3),
+               unit="Gaussians/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 (FP64 curve evaluation)",
+               data="synthetic",
+               config=dict(workload="256 filled closed NURBS paths (p 2/3, 6-24 key points, radii 5-80 px), "
+                                    "512x512 RGB, fill grid h=1, L2 loss vs perturbed target",
+                           gaussians=st.G, pairs=st.pairs, tile=p.tile, batch=p.batch),
+               phases_ms={k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
+               roofline=roof)
+    if not args.no_batched:
+        out["batched"] = bench_batched(args)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(b, p, target)
+    return out
+
+
+def roofline(st, dom, dom_ms, p):
+    """Roofline entry of the dominant kernel (algorithmic work / measured time)."""
+    if dom in ("blend_fwd",):
+        ev, hit = blend_work(st, p.tile)
+        flops = FWD_TEST_FLOPS * ev + FWD_HIT_FLOPS * hit
+        ach = flops / (dom_ms * 1e-3) / 1e12
+        return dict(kernel="k_blend_fwd", bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
+                    frac=ach / PEAK["fp32_tflops"], traffic=None, evaluated_pairs=ev, in_support_pairs=hit,
+                    ms_per_launch=dom_ms)
+    if dom == "blend_bwd":
+        ev, hit = blend_work(st, p.tile)
+        # reverse pass: same distance test; per in-support pair ~40 FP32 ops plus 7 x 6 wavefront
+        # reduction adds per Gaussian and wavefront
+        flops = FWD_TEST_FLOPS * ev + 40 * hit
+        ach = flops / (dom_ms * 1e-3) / 1e12
+        return dict(kernel="k_blend_bwd", bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
+                    frac=ach / PEAK["fp32_tflops"], traffic=None, evaluated_pairs=ev, in_support_pairs=hit,
+                    ms_per_launch=dom_ms)
+    if dom == "emit":
+        # fill Gaussians: one FP64 segment test (~24 flops) per boundary segment per lattice point
+        plan = st.r.plan_np()
+        flags = st.r.meta.flags.cpu().numpy()
+        fill = (flags & 2) != 0
+        seg_tests = int((plan[fill, 0].astype(np.int64) * plan[fill, 1]).sum())
+        flops = 24.0 * seg_tests
+        ach = flops / (dom_ms * 1e-3) / 1e12
+        return dict(kernel="k_emit", bound="alu", achieved=ach, peak=PEAK["fp64_tflops"], unit="TFLOP/s",
+                    frac=ach / PEAK["fp64_tflops"], traffic=None, segment_tests=seg_tests, ms_per_launch=dom_ms)
+    return dict(kernel=dom, bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None,
+                ms_per_launch=dom_ms)
+
+
+def bench_batched(args):
+    """64 uneven scenes: per-scene plain launches vs one batched persistent
+    launch sequence replayed from a HIP graph."""
+    import torch
+    from paper_2606_31764_amd import synth
+    from paper_2606_31764_amd.render import Context, Params
+    b5, kinds = synth.config5()
+    p = Params().replace(**synth.CONFIG_PARAMS[5])
+    ctx = Context(0)
+    log("batched: %d scenes, %d curves" % (b5.n_scenes, b5.n_curves))
+    # targets: each scene's perturbed ground truth, rendered once by the plain path
+    pert = synth.perturbed(b5, seed=5999)
+    scenes = [b5.select_scene(s) for s in range(b5.n_scenes)]
+    plain = []
+    tgt_all = []
+    for s in range(b5.n_scenes):
+        from paper_2606_31764_amd.render import Renderer, param_tensors
+        ps = pert.select_scene(s)
+        tr = Renderer(ps, p, ctx=ctx)
+        tg = tr.run_forward(param_tensors(ps)).clone()
+        tgt_all.append(tg)
+        del tr
+        plain.append(Step(scenes[s], p, tg.cpu().numpy(), ctx=ctx))
+    G_plain = sum(s.G for s in plain)
+    target = torch.cat(tgt_all).cpu().numpy()
+    bat = Step(b5, p, target, persistent=True, ctx=ctx)
+    log("batched G = %d (plain sum %d), pairs = %d" % (bat.G, G_plain, bat.pairs))
+    K = args.batched_steps
+    for _ in range(2):
+        for s in plain:
+            s.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        for s in plain:
+            s.run()
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / K
+    # capture the batched step
+    s_cap = torch.cuda.Stream()
+    s_cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_cap):
+        for _ in range(2):
+            bat.run()
+    torch.cuda.current_stream().wait_stream(s_cap)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        grads = bat.run()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    bat_ms = e0.elapsed_time(e1) / K
+    # the replayed graph must reproduce the eager step
+    eager = [x.clone() for x in bat.run()]
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    same = all(float((a - b_).abs().max()) <= 1e-4 * float(a.abs().max() + 1e-6) for a, b_ in zip(eager, grads))
+    res = dict(scenes=b5.n_scenes, gaussians=bat.G, plain_ms_per_step=plain_ms, batched_ms_per_step=bat_ms,
+               plain_gaussians_per_s=G_plain / (plain_ms * 1e-3), batched_gaussians_per_s=bat.G / (bat_ms * 1e-3),
+               speedup=plain_ms / bat_ms, graph_replay_matches_eager=bool(same))
+    log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
+    return res
+
+
+def cpu_baseline(b, p, target):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    import oracle
+    op = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
+                                                        "fill_pad", "h", "alpha_max", "eps_T")}
+    op["kappa"] = int(p.kappa)
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    g = oracle.gaussians(b, op)
+    t_sample = time.perf_counter() - t0
+    G = len(g["sigma"])
+    H, W = 512, 512
+    rows = 16
+    y0 = 254
+    pix = np.array([[0, y, x] for y in range(y0, y0 + rows) for x in range(W)], np.int32)
+    t0 = time.perf_counter()
+    img, T = oracle.composite(b, g, op, pixels=pix)
+    t_fwd = time.perf_counter() - t0
+    up = 2.0 * (img - target.reshape(3, H, W)[:, y0:y0 + rows, :].transpose(1, 2, 0).reshape(-1, 3))
+    t0 = time.perf_counter()
+    _, _, adj = oracle.composite(b, g, op, pixels=pix, upstream=up)
+    t_bwd_px = time.perf_counter() - t0
+    # parameter gradients for a sample of curves
+    nc = 32
+    seeds = []
+    for c in range(nc):
+        k0, k1 = b.key_off[c], b.key_off[c + 1]
+        t0_, t1_ = b.tau_off[c], b.tau_off[c + 1]
+        for k in range(k1 - k0):
+            for kind in (1, 2, 3):
+                seeds.append((c, kind, k))
+        for t in range(t1_ - t0_):
+            seeds.append((c, 5, t))
+        seeds.append((c, 6, 0))
+    t0 = time.perf_counter()
+    oracle.param_grad_seeds(b, g, adj, np.array(seeds, np.int32), op)
+    t_grad = time.perf_counter() - t0
+    est = t_sample + (t_fwd + t_bwd_px) * (H / rows) + t_grad * (b.n_curves / nc)
+    log("cpu oracle: sample %.2fs, %d-row composite %.2fs + adjoint %.2fs, %d-curve grads %.2fs -> est %.1fs"
+        % (t_sample, rows, t_fwd, t_bwd_px, nc, t_grad, est))
+    return dict(value=G / est, unit="Gaussians/s", cores=threads, kind="oracle",
+                sample="all %d Gaussians sampled; composite + compositing adjoint on %d of 512 rows (x%d); "
+                       "parameter gradients of %d of 256 curves (x%d); measured %.1f s, extrapolated to %.1f s "
+                       "per step" % (G, rows, H // rows, nc, b.n_curves // nc,
+                                     t_sample + t_fwd + t_bwd_px + t_grad, est))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the render path of this repository runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not a measured path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    out = bench_main(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

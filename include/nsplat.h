@@ -68,6 +68,19 @@ extern "C" {
 #define NSPLAT_STATUS_BOUND_CAP 4   /* boundary-point capacity exceeded       */
 #define NSPLAT_STATUS_DATA 8        /* invalid curve data (see above)         */
 
+/* Timed phases (nsplat_timing_read); each is one kernel unless noted. */
+#define NSPLAT_T_PLAN 0        /* knots, arc length, counts, boundary, scans (5 kernels) */
+#define NSPLAT_T_EMIT 1        /* Gaussian records                              */
+#define NSPLAT_T_BIN 2         /* tile counts, their scan, pair emission        */
+#define NSPLAT_T_SORT 3        /* all radix passes                              */
+#define NSPLAT_T_RANGES 4      /* tile ranges                                   */
+#define NSPLAT_T_BLEND_FWD 5   /* forward compositing                           */
+#define NSPLAT_T_BLEND_BWD 6   /* compositing adjoint                           */
+#define NSPLAT_T_ADJ_GAUSS 7   /* per-Gaussian sample adjoint                   */
+#define NSPLAT_T_ADJ_BOUND 8   /* boundary-point adjoint                        */
+#define NSPLAT_T_FOLD 9        /* zeroing and the fold to key points / tau      */
+#define NSPLAT_NUM_TIMERS 10
+
 /* plan[] row layout (dev int32[n_curves][8]) */
 #define NSPLAT_PLAN_COUNT 0   /* Gaussians of the curve                        */
 #define NSPLAT_PLAN_NSAMP 1   /* contour samples M (Sec. 3.2) or boundary points (Sec. 3.3) */
@@ -201,7 +214,8 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes
 /* Eq. 8-9.  Per pixel, front to back (descending Gaussian index):
  * alpha = min(alpha_max, o exp(-|x - mu|^2 / (2 sigma^2))) for |x - mu| <=
  * k_sigma sigma, colour += c alpha T, T *= 1 - alpha, stop once T < eps_T;
- * image = colour + T bg.  image is per scene [channels][H][W], concatenated
+ * image = colour + T bg.  Uses the tile lists and scene table built by the
+ * last nsplat_bin on these buffers (same params.tile).  image is per scene [channels][H][W], concatenated
  * over scenes; T_final and n_last are per scene [H][W]: the final
  * transmittance and the idx position where the pixel stopped.
  * persistent != 0 runs one resident grid that pulls tiles from a device work
@@ -234,6 +248,16 @@ int nsplat_anneal_h(nsplat_ctx* ctx, float* h_dev, int32_t* step_dev, int32_t st
  * i < n, and sum((a - b)^2) added into *loss (dev, FP32). */
 int nsplat_l2_grad(nsplat_ctx* ctx, const float* a, const float* b, float* out, float* loss, int64_t n,
                    void* stream);
+
+/* Per-phase timing.  nsplat_timing(ctx, 1) starts recording a HIP event pair
+ * around every NSPLAT_T_* phase the library launches (on that call's stream)
+ * and clears the sums; nsplat_timing(ctx, 0) stops.  nsplat_timing_read waits
+ * for the recorded events, adds their elapsed times to ms[NSPLAT_NUM_TIMERS]
+ * and launch counts to count[NSPLAT_NUM_TIMERS] (host arrays, overwritten
+ * with the sums since the last enable) and recycles the events.  Not for use
+ * under graph capture. */
+int nsplat_timing(nsplat_ctx* ctx, int enable);
+int nsplat_timing_read(nsplat_ctx* ctx, double* ms, int64_t* count);
 
 /* Copies the counters to host memory and waits for them (synchronising). */
 int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bufs, int32_t* host_out, void* stream);

@@ -1,14 +1,17 @@
 // Second half of nsplat_backward: per-Gaussian adjoints -> curve parameters.
 //
-//   k_adj_gauss     one lane per Gaussian.  Strokes: dL/d(mu, sigma) ->
+//   k_adj_stroke    one lane per stroke Gaussian: dL/d(mu, sigma) ->
 //                   dL/d(x, y, s) of C(u_j) (sigma = s / rho, Eq. 5) -> reverse
 //                   mode through the rational point (Eq. 1) and the Cox-de Boor
 //                   triangle: control points, weights, widths, the 2p knots of
 //                   the span, and dL/du_j -> the domain ends u_p, u_{m-p}
-//                   (u_j is uniform in the domain).  Fills: dL/do_j -> curve
-//                   opacity and, through the sigmoid and the SDF (Eq. 7, S1-S3,
-//                   sign detached, nearest segment), the two end points of the
+//                   (u_j is uniform in the domain).
+//   k_adj_fill      one lane per fill Gaussian: dL/do_j -> curve opacity and,
+//                   through the sigmoid and the SDF (Eq. 7, S1-S3, sign
+//                   detached, nearest segment), the two end points of the
 //                   nearest boundary segment.
+//   (Colour gradients, and the opacity gradient of stroke curves, are
+//   accumulated per curve by the compositing adjoint.)
 //   k_adj_boundary  one lane per boundary point: the same point adjoint.
 //   Both reduce within the wavefront by (curve, span) segment before the FP64
 //   global atomics.
@@ -215,16 +218,16 @@ __device__ inline int curve_of(const int32_t* goff, int n, int64_t g) {
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_adj_gauss(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
-                                                   const int32_t* counters, const Gauss* __restrict__ gs) {
+// Stroke Gaussians: dL/d(mu, sigma) -> the curve point adjoint at u_j.
+__global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_params pr, Work w,
+                                                    const int32_t* plan, const int32_t* counters,
+                                                    const Gauss* __restrict__ gs) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const int lane = __lane_id();
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int C = cv.channels;
   for (int64_t base = wave0; base < G; base += stride) {
     const int64_t g = base + lane;
-    const bool active = g < G;
     int64_t kspan = -1 - lane, kcur = -1 - lane;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     PtAdj pa;
@@ -232,18 +235,15 @@ __global__ __launch_bounds__(256) void k_adj_gauss(nsplat_curves cv, nsplat_para
     CurveView v;
     v.p = 0;
     bool stroke = false;
-    if (active) {
+    if (g < G) {
       const Gauss r = gs[g];
       c = r.curve;
-      v = curve_view(cv, w.knots, c);
-      const float* gg = w.ggrad + g * 8;
-      for (int ch = 0; ch < C; ++ch) cur[1 + ch] = (double)gg[4 + ch];
-      kcur = c;
-      const int32_t* row = plan + (int64_t)P_STRIDE * c;
-      if (!v.filled()) {
+      if (!(cv.flags[c] & NSPLAT_FILLED)) {
         stroke = true;
-        cur[0] = (double)gg[3];
-        const double ab[3] = {(double)gg[0], (double)gg[1], (double)gg[2] / (double)pr.rho};
+        v = curve_view(cv, w.knots, c);
+        const float* gg = w.ggrad + g * GG;
+        const double ab[3] = {(double)gg[0], (double)gg[1], (double)gg[2] / (double)pr.rho};  // sigma = s / rho
+        const int32_t* row = plan + (int64_t)P_STRIDE * c;
         const int M = row[P_NSAMP];
         int j = v.closed() ? r.local : r.local - pr.kappa;
         j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
@@ -251,66 +251,10 @@ __global__ __launch_bounds__(256) void k_adj_gauss(nsplat_curves cv, nsplat_para
         const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), &dt);
         span = find_span(v.U, v.p, v.m, u);
         point_adjoint(cv, v, u, span, ab, pa);
-        cur[4] = pa.ubar * (1.0 - dt);
+        cur[4] = pa.ubar * (1.0 - dt);  // u_j = u_p + t_j (u_{m-p} - u_p)
         cur[5] = pa.ubar * dt;
         kspan = (int64_t)v.t0 + (int64_t)c * KNOT_PAD + span;
-      } else {
-        // o_j = o sigmoid(z), z = gamma / h * sgn * d(q)
-        const double dO = (double)gg[3];
-        const double o = (double)cv.opacity[c];
-        const double h = (double)read_h(pr);
-        const int nx = row[P_NX];
-        const int iy = r.local / nx, ix = r.local - iy * nx;
-        const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
-        const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
-        const double2* bp = w.bpts + row[P_BOFF];
-        const int nb = row[P_NSAMP];
-        double best = INFINITY, tb = 0.0;
-        int ib = 0, wn = 0;
-        double2 A = bp[0];
-        for (int i = 0; i < nb; ++i) {
-          const double2 Bq = bp[i + 1 < nb ? i + 1 : 0];
-          const double ex = Bq.x - A.x, ey = Bq.y - A.y;
-          const double ee = ex * ex + ey * ey;
-          const double rx = qx - A.x, ry = qy - A.y;
-          double t = 0.0;
-          if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
-          t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-          const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
-          const double d2 = px * px + py * py;
-          if (d2 < best) {
-            best = d2;
-            ib = i;
-            tb = t;
-          }
-          const double crs = ex * ry - rx * ey;
-          if (A.y <= qy) {
-            if (Bq.y > qy && crs > 0.0) ++wn;
-          } else {
-            if (Bq.y <= qy && crs < 0.0) --wn;
-          }
-          A = Bq;
-        }
-        const double sgn = wn >= 1 ? 1.0 : -1.0;
-        const double d = sqrt(best);
-        const double gh = (double)pr.gamma / h;
-        const double z = gh * (sgn * d);
-        const double sz = 1.0 / (1.0 + exp(-z));
-        cur[0] = dO * sz;
-        const double ds = sz * (1.0 - sz);
-        if (d > 0.0 && dO != 0.0 && ds > 1e-18) {
-          const double dd = dO * o * ds * gh * sgn;  // dL/dd
-          const double2 a = bp[ib], b = bp[ib + 1 < nb ? ib + 1 : 0];
-          const double prx = a.x + tb * (b.x - a.x), pry = a.y + tb * (b.y - a.y);
-          const double nxv = (qx - prx) / d, nyv = (qy - pry) / d;
-          // d(d)/da = -(1 - t) n, d(d)/db = -t n (envelope at the projection)
-          double2* gb = w.gb + row[P_BOFF];
-          const int jb = ib + 1 < nb ? ib + 1 : 0;
-          unsafeAtomicAdd(&gb[ib].x, -dd * (1.0 - tb) * nxv);
-          unsafeAtomicAdd(&gb[ib].y, -dd * (1.0 - tb) * nyv);
-          unsafeAtomicAdd(&gb[jb].x, -dd * tb * nxv);
-          unsafeAtomicAdd(&gb[jb].y, -dd * tb * nyv);
-        }
+        kcur = c;
       }
     }
     if (!stroke) {
@@ -323,7 +267,74 @@ __global__ __launch_bounds__(256) void k_adj_gauss(nsplat_curves cv, nsplat_para
     }
     const bool any = __ballot(stroke) != 0ull;
     accumulate_points(w, kspan, c, v, span, pa, any);
-    accumulate_curve(w, kcur, c, v, cur);
+    if (any) accumulate_curve(w, kcur, c, v, cur);
+  }
+}
+
+// Fill Gaussians: o_j = o sigmoid(z), z = gamma / h * sgn * d(q) with the
+// nearest segment and the sign recorded at emission.  dL/do_j -> curve
+// opacity, and dL/dd -> the segment's end points (d(d)/da = -(1 - t) n,
+// d(d)/db = -t n at the projection, n the unit vector from it to q).
+__global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
+                                                  const int32_t* counters, const Gauss* __restrict__ gs) {
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const int lane = __lane_id();
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const double h = (double)read_h(pr);
+  const double gh = (double)pr.gamma / h;
+  for (int64_t base = wave0; base < G; base += stride) {
+    const int64_t g = base + lane;
+    int64_t kcur = -1 - lane;
+    double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int c = 0;
+    CurveView v;
+    v.p = 0;
+    bool fill = false;
+    if (g < G) {
+      const Gauss r = gs[g];
+      c = r.curve;
+      if (cv.flags[c] & NSPLAT_FILLED) {
+        fill = true;
+        kcur = c;
+        v = curve_view(cv, w.knots, c);
+        const double dO = (double)w.ggrad[g * GG + 3];
+        const int32_t* row = plan + (int64_t)P_STRIDE * c;
+        const int nx = row[P_NX];
+        const int iy = r.local / nx, ix = r.local - iy * nx;
+        const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
+        const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
+        const int nb = row[P_NSAMP];
+        const int32_t ax = w.aux[g];
+        const int ib = ax & 0x7fffffff;
+        const double sgn = ax < 0 ? -1.0 : 1.0;
+        const double2* bp = w.bpts + row[P_BOFF];
+        const int jb = ib + 1 < nb ? ib + 1 : 0;
+        const double2 A = bp[ib], Bq = bp[jb];
+        const double ex = Bq.x - A.x, ey = Bq.y - A.y;
+        const double ee = ex * ex + ey * ey;
+        const double rx = qx - A.x, ry = qy - A.y;
+        double t = 0.0;
+        if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+        const double d = sqrt(px * px + py * py);
+        const double z = gh * (sgn * d);
+        const double sz = 1.0 / (1.0 + exp(-z));
+        cur[0] = dO * sz;
+        const double ds = sz * (1.0 - sz);
+        if (d > 0.0 && dO != 0.0 && ds > 1e-18) {
+          const double dd = dO * (double)cv.opacity[c] * ds * gh * sgn;  // dL/dd
+          const double nxv = -px / d, nyv = -py / d;
+          double2* gb = w.gb + row[P_BOFF];
+          unsafeAtomicAdd(&gb[ib].x, -dd * (1.0 - t) * nxv);
+          unsafeAtomicAdd(&gb[ib].y, -dd * (1.0 - t) * nyv);
+          unsafeAtomicAdd(&gb[jb].x, -dd * t * nxv);
+          unsafeAtomicAdd(&gb[jb].y, -dd * t * nyv);
+        }
+      }
+    }
+    if (__ballot(fill) != 0ull) accumulate_curve(w, kcur, c, v, cur);
   }
 }
 
@@ -451,11 +462,12 @@ __global__ void k_zero_dev(float* p, const int32_t* count, int64_t mult, int64_t
 }  // namespace
 
 hipError_t launch_zero_grads(const Launch& L) {
+  Phase ph(L, NSPLAT_T_FOLD);
   const nsplat_curves& cv = *L.cv;
   const int64_t ncp = (int64_t)cv.n_keys + (int64_t)cv.n_curves * CP_PAD;
   const int64_t nkn = (int64_t)cv.n_taus + (int64_t)cv.n_curves * KNOT_PAD;
-  hipLaunchKernelGGL(k_zero_dev, dim3(grid_for(L.bf->caps.gauss * 8, 256, 8192)), dim3(256), 0, L.stream,
-                     L.w.ggrad, L.bf->counters + NSPLAT_CNT_GAUSS, (int64_t)8, (int64_t)L.bf->caps.gauss);
+  hipLaunchKernelGGL(k_zero_dev, dim3(grid_for(L.bf->caps.gauss * GG, 256, 8192)), dim3(256), 0, L.stream,
+                     L.w.ggrad, L.bf->counters + NSPLAT_CNT_GAUSS, (int64_t)GG, (int64_t)L.bf->caps.gauss);
   hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(4 * ncp, 256, 4096)), dim3(256), 0, L.stream, L.w.gcp, 4 * ncp);
   hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(nkn, 256, 4096)), dim3(256), 0, L.stream, L.w.gknot, nkn);
   hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(4 * cv.n_curves, 256, 4096)), dim3(256), 0, L.stream, L.w.gcurve,
@@ -467,11 +479,19 @@ hipError_t launch_zero_grads(const Launch& L) {
 }
 
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g) {
-  hipLaunchKernelGGL(k_adj_gauss, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
-                     *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
-  if (L.bf->caps.boundary > 0)
+  {
+    Phase ph(L, NSPLAT_T_ADJ_GAUSS);
+    hipLaunchKernelGGL(k_adj_stroke, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                       *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                       *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+  }
+  if (L.bf->caps.boundary > 0) {
+    Phase ph(L, NSPLAT_T_ADJ_BOUND);
     hipLaunchKernelGGL(k_adj_boundary, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
                        *L.cv, L.w, L.bf->plan, L.bf->counters);
+  }
+  Phase ph(L, NSPLAT_T_FOLD);
   hipLaunchKernelGGL(k_fold, dim3(grid_for(L.cv->n_curves, 64, 1 << 20)), dim3(64), 0, L.stream, *L.cv, L.w, *g);
   return hipGetLastError();
 }

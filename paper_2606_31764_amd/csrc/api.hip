@@ -15,6 +15,7 @@ struct nsplat_ctx {
   int device = 0;
   int n_cu = 256;
   std::string err;
+  nsp::Timer timer;
 };
 
 namespace nsp {
@@ -29,7 +30,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
   const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
-  const size_t sizes[17] = {
+  const size_t sizes[18] = {
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
       sizeof(double) * (size_t)N,                          // L
       sizeof(int32_t) * (size_t)(N + 1),                   // goff
@@ -41,15 +42,16 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // vals1
       sizeof(uint32_t) * (size_t)(256 * std::max<int64_t>(lay.sort_blocks, 1)),  // hist
       sizeof(uint32_t) * (size_t)(lay.scan_blocks + 1),    // scan_tmp
-      sizeof(float) * 8 * (size_t)std::max<int64_t>(gcap, 1),  // ggrad
+      sizeof(float) * GG * (size_t)std::max<int64_t>(gcap, 1),  // ggrad
       sizeof(double) * 4 * (size_t)(K + N * CP_PAD),       // gcp
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // gknot
       sizeof(double) * 4 * (size_t)N,                      // gcurve
       sizeof(double2) * (size_t)std::max<int64_t>(bcap, 1),  // gb
       sizeof(int32_t) * 64,                                // queue
+      sizeof(int32_t) * (size_t)std::max<int64_t>(gcap, 1),  // aux
   };
   size_t off = 0;
-  for (int i = 0; i < 17; ++i) {
+  for (int i = 0; i < 18; ++i) {
     lay.off[i] = off;
     off += align256(sizes[i]);
   }
@@ -77,7 +79,42 @@ Work carve(void* ws, const Layout& lay) {
   w.gcurve = (double*)(b + lay.off[14]);
   w.gb = (double2*)(b + lay.off[15]);
   w.queue = (int32_t*)(b + lay.off[16]);
+  w.aux = (int32_t*)(b + lay.off[17]);
   return w;
+}
+
+static hipEvent_t timer_event(Timer* t) {
+  if (t->used == t->cap) {
+    const int ncap = t->cap ? 2 * t->cap : 256;
+    hipEvent_t* np = new hipEvent_t[ncap];
+    for (int i = 0; i < t->cap; ++i) np[i] = t->pool[i];
+    for (int i = t->cap; i < ncap; ++i)
+      if (hipEventCreate(&np[i]) != hipSuccess) np[i] = nullptr;
+    delete[] t->pool;
+    t->pool = np;
+    t->cap = ncap;
+  }
+  return t->pool[t->used++];
+}
+
+void timer_begin(Timer* t, int id, hipStream_t s) {
+  if (t->n_spans >= 4096) return;
+  const int e = t->used;
+  hipEvent_t ev = timer_event(t);
+  if (ev && hipEventRecord(ev, s) == hipSuccess) t->open_ev[id] = e;
+  else t->open_ev[id] = -1;
+}
+
+void timer_end(Timer* t, int id, hipStream_t s) {
+  if (t->open_ev[id] < 0 || t->n_spans >= 4096) return;
+  const int e = t->used;
+  hipEvent_t ev = timer_event(t);
+  if (!ev || hipEventRecord(ev, s) != hipSuccess) return;
+  t->span_id[t->n_spans] = id;
+  t->span_ev[t->n_spans][0] = t->open_ev[id];
+  t->span_ev[t->n_spans][1] = e;
+  ++t->n_spans;
+  t->open_ev[id] = -1;
 }
 
 }  // namespace nsp
@@ -185,6 +222,7 @@ int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, c
   L->stream = (hipStream_t)stream;
   L->n_tiles = nsplat_num_tiles(sc, pr->tile);
   L->n_cu = ctx->n_cu;
+  L->tm = ctx->timer.on ? &ctx->timer : nullptr;
   return NSPLAT_OK;
 }
 
@@ -263,8 +301,7 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!image || !T_final || !n_last) return fail(ctx, NSPLAT_EINVAL, "image / T_final / n_last is NULL");
-  hipError_t h = launch_scene_setup(L);
-  if (h == hipSuccess) h = launch_blend_fwd(L, image, T_final, n_last, persistent);
+  hipError_t h = launch_blend_fwd(L, image, T_final, n_last, persistent);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_forward");
   return NSPLAT_OK;
 }
@@ -279,8 +316,7 @@ int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
   if (cv->n_curves > 0 && (!gr->key_xy || !gr->key_w || !gr->key_s || !gr->color || !gr->opacity ||
                            (cv->n_taus > 0 && !gr->tau)))
     return fail(ctx, NSPLAT_EINVAL, "a gradient pointer is NULL");
-  hipError_t h = launch_scene_setup(L);
-  if (h == hipSuccess) h = launch_zero_grads(L);
+  hipError_t h = launch_zero_grads(L);
   if (h == hipSuccess) h = launch_blend_bwd(L, dL, T_final, n_last, persistent);
   if (h == hipSuccess && cv->n_curves > 0) h = launch_adjoint(L, gr);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_backward");
@@ -303,6 +339,40 @@ int nsplat_l2_grad(nsplat_ctx* ctx, const float* a, const float* b, float* out, 
   if (n < 0 || (n > 0 && (!a || !b || !out))) return fail(ctx, NSPLAT_EINVAL, "bad arguments to nsplat_l2_grad");
   hipError_t h = launch_l2(a, b, out, loss, n, (hipStream_t)stream);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_l2_grad");
+  return NSPLAT_OK;
+}
+
+int nsplat_timing(nsplat_ctx* ctx, int enable) {
+  if (!ctx) return NSPLAT_EINVAL;
+  Timer& t = ctx->timer;
+  t.on = enable != 0;
+  t.used = 0;
+  t.n_spans = 0;
+  for (int i = 0; i < NSPLAT_NUM_TIMERS; ++i) {
+    t.ms[i] = 0.0;
+    t.count[i] = 0;
+    t.open_ev[i] = -1;
+  }
+  return NSPLAT_OK;
+}
+
+int nsplat_timing_read(nsplat_ctx* ctx, double* ms, int64_t* count) {
+  if (!ctx) return NSPLAT_EINVAL;
+  Timer& t = ctx->timer;
+  for (int k = 0; k < t.n_spans; ++k) {
+    float x = 0.f;
+    hipEvent_t b = t.pool[t.span_ev[k][1]];
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&x, t.pool[t.span_ev[k][0]], b) != hipSuccess)
+      return fail(ctx, NSPLAT_EHIP, "nsplat_timing_read: event query failed");
+    t.ms[t.span_id[k]] += (double)x;
+    t.count[t.span_id[k]] += 1;
+  }
+  t.n_spans = 0;
+  t.used = 0;
+  for (int i = 0; i < NSPLAT_NUM_TIMERS; ++i) {
+    if (ms) ms[i] = t.ms[i];
+    if (count) count[i] = t.count[i];
+  }
   return NSPLAT_OK;
 }
 
@@ -361,8 +431,8 @@ int nsplat_autotune(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
         *best_batch = batches[bi];
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc == NSPLAT_EHIP && ctx->err.empty()) ctx->err = "autotune: HIP event error";
   return rc;
 }

@@ -188,10 +188,6 @@ hipError_t launch_bin(const Launch& L) {
   int32_t* cnt = L.bf->counters;
   const Gauss* gs = (const Gauss*)L.bf->gauss;
   const int gg = grid_for(gcap, 256, 8192);
-  hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt);
-  hipError_t e = launch_scan(L.w.gcnt, cnt + NSPLAT_CNT_GAUSS, gcap, L.w.gcnt + gcap, L.w.scan_tmp, L.stream);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, L.stream, cnt, L.w.gcnt + gcap, pcap);
   // number of key bits and radix passes (up to 8 bits each)
   int key_bits = 0;
   while (key_bits < 31 && ((int64_t)1 << key_bits) < L.n_tiles) ++key_bits;
@@ -201,29 +197,44 @@ hipError_t launch_bin(const Launch& L) {
   // the last pass must land in (keys0, idx)
   uint32_t* ek = (passes % 2) ? L.w.keys1 : L.w.keys0;
   uint32_t* ev = (passes % 2) ? L.w.vals1 : idx;
-  hipLaunchKernelGGL(k_bin_emit, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt, ek, ev,
-                     pcap);
-  const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
-  uint32_t *kin = ek, *vin = ev;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * digit;
-    const int bits = (key_bits - shift) < digit ? (key_bits - shift) : digit;
-    uint32_t* kout = (kin == L.w.keys0) ? L.w.keys1 : L.w.keys0;
-    uint32_t* vout = (vin == idx) ? L.w.vals1 : idx;
-    if (sb > 0) {
-      hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, cnt, shift, bits, L.w.hist);
-      e = launch_scan(L.w.hist, nullptr, (int64_t)(1 << bits) * sb, nullptr, L.w.scan_tmp, L.stream);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout, cnt,
-                         shift, bits, L.w.hist);
-    }
-    kin = kout;
-    vin = vout;
+  hipError_t e;
+  {
+    Phase ph(L, NSPLAT_T_BIN);
+    hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt);
+    e = launch_scan(L.w.gcnt, cnt + NSPLAT_CNT_GAUSS, gcap, L.w.gcnt + gcap, L.w.scan_tmp, L.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, L.stream, cnt, L.w.gcnt + gcap, pcap);
+    hipLaunchKernelGGL(k_bin_emit, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt, ek, ev,
+                       pcap);
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.n_tiles, 256, 4096)), dim3(256), 0, L.stream,
-                     L.bf->ranges, 0, 2 * L.n_tiles);
-  hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
-                     L.bf->ranges);
+  {
+    Phase ph(L, NSPLAT_T_SORT);
+    const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
+    uint32_t *kin = ek, *vin = ev;
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * digit;
+      const int bits = (key_bits - shift) < digit ? (key_bits - shift) : digit;
+      uint32_t* kout = (kin == L.w.keys0) ? L.w.keys1 : L.w.keys0;
+      uint32_t* vout = (vin == idx) ? L.w.vals1 : idx;
+      if (sb > 0) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, cnt, shift, bits,
+                           L.w.hist);
+        e = launch_scan(L.w.hist, nullptr, (int64_t)(1 << bits) * sb, nullptr, L.w.scan_tmp, L.stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout, cnt,
+                           shift, bits, L.w.hist);
+      }
+      kin = kout;
+      vin = vout;
+    }
+  }
+  {
+    Phase ph(L, NSPLAT_T_RANGES);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.n_tiles, 256, 4096)), dim3(256), 0, L.stream,
+                       L.bf->ranges, 0, 2 * L.n_tiles);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
+                       L.bf->ranges);
+  }
   return hipGetLastError();
 }
 

@@ -48,16 +48,19 @@ struct Work {
   uint32_t* vals1;     // [caps.pairs]
   uint32_t* hist;      // [256 * sort_blocks]
   uint32_t* scan_tmp;  // [scan_blocks + 1]
-  float* ggrad;        // [caps.gauss][8] per-Gaussian adjoints
+  float* ggrad;        // [caps.gauss][4] per-Gaussian adjoints (d/dmx, d/dmy, d/dsigma, d/dopacity)
   double* gcp;         // [(n_keys + n_curves * CP_PAD)][4] control-point adjoints (x, y, w, s)
   double* gknot;       // [n_taus + n_curves * KNOT_PAD]
   double* gcurve;      // [n_curves][4] (opacity, colour 0..2)
   double2* gb;         // [caps.boundary] boundary-point adjoints
   int32_t* queue;      // [4] work-queue counters of the persistent kernels
+  int32_t* aux;        // [caps.gauss] fill Gaussians: nearest boundary segment, sign in bit 31
 };
 
+constexpr int GG = 4;  // floats per Gaussian in Work::ggrad
+
 struct Layout {
-  size_t off[17];
+  size_t off[18];
   size_t total;
   int64_t sort_blocks, scan_blocks;
 };
@@ -231,7 +234,24 @@ __device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) 
 // ---------------------------------------------------------------------------
 // Launch helpers (host side), one per kernel family.
 // ---------------------------------------------------------------------------
+// Optional per-phase timing with HIP events (nsplat_timing): each phase is
+// bracketed by two events on the launch stream; sums are read back on demand.
+struct Timer {
+  bool on = false;
+  hipEvent_t* pool = nullptr;
+  int cap = 0, used = 0;
+  int span_id[4096];
+  int span_ev[4096][2];
+  int n_spans = 0;
+  int open_ev[NSPLAT_NUM_TIMERS];
+  double ms[NSPLAT_NUM_TIMERS];
+  int64_t count[NSPLAT_NUM_TIMERS];
+};
+void timer_begin(Timer* t, int id, hipStream_t s);
+void timer_end(Timer* t, int id, hipStream_t s);
+
 struct Launch {
+  Timer* tm = nullptr;
   const nsplat_curves* cv;
   const nsplat_scenes* sc;
   const nsplat_params* pr;
@@ -256,6 +276,14 @@ hipError_t launch_scan(uint32_t* data, const int32_t* n_dev, int64_t n_cap, uint
 hipError_t launch_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t total, float hmax, float hmin,
                          float tb, float te, hipStream_t s);
 hipError_t launch_l2(const float* a, const float* b, float* out, float* loss, int64_t n, hipStream_t s);
+
+struct Phase {
+  Timer* t;
+  int id;
+  hipStream_t s;
+  Phase(const Launch& L, int i) : t(L.tm), id(i), s(L.stream) { if (t && t->on) timer_begin(t, id, s); }
+  ~Phase() { if (t && t->on) timer_end(t, id, s); }
+};
 
 inline int grid_for(int64_t n, int threads, int max_blocks) {
   int64_t b = (n + threads - 1) / threads;

@@ -351,6 +351,7 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       r.my = qy;
       r.sigma = (float)((double)pr.eta * h / (double)pr.rho);  // Eq. 6
       r.opacity = (float)(o * (1.0 / (1.0 + exp(-z))));        // Eq. 7
+      w.aux[g] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
     }
     out[g] = r;
   }
@@ -367,6 +368,8 @@ hipError_t launch_sample(const Launch& L, int frozen) {
   const int n = L.cv->n_curves;
   int32_t* plan = L.bf->plan;
   int32_t* cnt = L.bf->counters;
+  {
+  Phase ph(L, NSPLAT_T_PLAN);
   hipLaunchKernelGGL(k_curve_prep, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan, cnt, frozen,
                      L.sc->n_scenes);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
@@ -375,6 +378,8 @@ hipError_t launch_sample(const Launch& L, int frozen) {
                      (int64_t)L.bf->caps.boundary, frozen);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 1,
                      (int64_t)L.bf->caps.gauss);
+  }
+  Phase ph(L, NSPLAT_T_EMIT);
   hipLaunchKernelGGL(k_emit, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv, *L.pr,
                      L.w, plan, cnt, (Gauss*)L.bf->gauss);
   return hipGetLastError();
