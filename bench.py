@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -180,6 +182,13 @@ def bench_main(args):
                            gaussians=st.G, pairs=st.pairs, tile=p.tile, batch=p.batch),
                phases_ms={k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
                roofline=roof)
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_batched:
         out["batched"] = bench_batched(args)
     if not args.no_cpu:

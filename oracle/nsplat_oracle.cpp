@@ -370,9 +370,12 @@ struct Gauss { T mx, my, sigma, opacity; };
 // Gaussians of curve c for a given plan row, in emission order: open strokes
 // [kappa copies of sample 0, samples 0..M-1, kappa copies of sample M-1];
 // closed strokes samples 0..M-1; fills the lattice window row by row.
+// If `need` is given, lattice Gaussians j with need[j] == false are left at
+// zero (their terms of a sum that weights them by a zero adjoint vanish).
 template <class T>
 void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* pr, int c,
-                     const int32_t* plan_row, int seed_kind, int seed_index, std::vector<Gauss<T>>& out) {
+                     const int32_t* plan_row, int seed_kind, int seed_index, std::vector<Gauss<T>>& out,
+                     const std::vector<char>* need = nullptr) {
   const Curve<T> cv = build_curve<T>(in, c, seed_kind, seed_index);
   const T o = lift<T>(in->opacity[c], seed_kind == S_OPACITY);
   const int count = plan_row[P_COUNT], ns = plan_row[P_NSAMP];
@@ -396,6 +399,10 @@ void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* 
     const T sig = T(pr->eta * h / pr->rho);                         // Eq. 6
     for (int iy = 0; iy < plan_row[P_NY]; ++iy)
       for (int ix = 0; ix < plan_row[P_NX]; ++ix) {
+        if (need && !(*need)[out.size()]) {
+          out.push_back(Gauss<T>{T(0.0), T(0.0), T(0.0), T(0.0)});
+          continue;
+        }
         const double qx = (plan_row[P_IX0] + ix + 0.5) * h, qy = (plan_row[P_IY0] + iy + 0.5) * h;
         const T z = T(pr->gamma / h) * sdf(qx, qy, bx, by);
         out.push_back(Gauss<T>{T(qx), T(qy), sig, o * sigmoid(z)});   // Eq. 7
@@ -681,8 +688,13 @@ static double param_grad_one(const or_curves* in, const or_scenes* sc, const or_
     for (int j = 0; j < row[P_COUNT]; ++j) s += adj[7 * (g0 + j) + 4 + (kind - 7)];
     return s;
   }
+  std::vector<char> need(row[P_COUNT]);
+  for (int j = 0; j < row[P_COUNT]; ++j) {
+    const double* a = adj + 7 * (g0 + j);
+    need[j] = (a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0 || a[3] != 0.0);
+  }
   std::vector<Gauss<Dual>> gs;
-  curve_gaussians<Dual>(in, sc, pr, c, row, kind, index, gs);
+  curve_gaussians<Dual>(in, sc, pr, c, row, kind, index, gs, &need);
   double s = 0.0;
   for (size_t j = 0; j < gs.size(); ++j) {
     const double* a = adj + 7 * (g0 + j);

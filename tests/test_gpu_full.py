@@ -1,0 +1,148 @@
+"""Parity at the full workload sizes (512^2 fills with ~0.9M Gaussians; 1024^2
+long splines with ~1.8M Gaussians), in the launch configuration the benchmark
+times: plans, records and tile lists in full; images on sampled pixels the
+oracle composites one by one; gradients for a sparse upstream gradient (a few
+pixels) on sampled parameter components; and invariance identities of the
+full dense gradient that hold at any size."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import IMG_TOL, oracle_params
+from paper_2606_31764_amd import synth
+from paper_2606_31764_amd.render import Params
+
+pytestmark = pytest.mark.gpu
+
+FULL = {
+    "c3": (lambda: synth.config3(), Params().replace(h=1.0)),
+    "c4": (lambda: synth.config4(), Params().replace(delta_c=10.0)),
+}
+
+
+@pytest.fixture(scope="module")
+def runs():
+    return {}
+
+
+def _run(runs, name):
+    if name not in runs:
+        import torch
+        from paper_2606_31764_amd.render import Renderer, param_tensors
+        b = FULL[name][0]()
+        p = FULL[name][1]
+        r = Renderer(b, p)
+        t = param_tensors(b)
+        img = r.run_forward(t).clone()
+        torch.cuda.synchronize()
+        runs[name] = dict(b=b, p=p, r=r, t=t, img=img, g=r.gaussians(), plan=r.plan_np(), tiles=r.tiles(),
+                          ref=oracle.gaussians(b, oracle_params(p)))
+        print(name, "G =", len(runs[name]["g"]["sigma"]), flush=True)
+    return runs[name]
+
+
+def _pixels(b, n, seed):
+    rng = np.random.default_rng(seed)
+    H, W = b.hw[0]
+    return np.stack([np.zeros(n, int), rng.integers(0, H, n), rng.integers(0, W, n)], 1)
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_plan_records_and_bins(runs, name):
+    R = _run(runs, name)
+    ref, g = R["ref"], R["g"]
+    np.testing.assert_array_equal(R["plan"][:, :7], ref["plan"][:, :7])
+    assert len(g["sigma"]) == len(ref["sigma"])
+    np.testing.assert_array_equal(g["curve"], ref["curve"])
+    np.testing.assert_array_equal(g["local"], ref["local"])
+    assert np.abs(g["mu"] - ref["mu"]).max() < 1e-9
+    assert np.abs(g["opacity"] - ref["opacity"]).max() < 2e-7
+    ranges, idx = oracle.bin_gaussians(R["b"], ref, tile=R["p"].tile, k_sigma=R["p"].k_sigma)
+    np.testing.assert_array_equal(R["tiles"][0], ranges)
+    np.testing.assert_array_equal(R["tiles"][1], idx)
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_image_sampled_pixels(runs, name):
+    R = _run(runs, name)
+    b = R["b"]
+    pix = _pixels(b, 96, 7)
+    # add pixels inside the busiest tile
+    H, W = b.hw[0]
+    C = b.channels
+    vals, T = oracle.composite(b, R["ref"], oracle_params(R["p"]), pixels=pix)
+    img = R["img"].cpu().numpy().reshape(C, H, W)
+    got = img[:, pix[:, 1], pix[:, 2]].T
+    err = np.abs(got - vals).max()
+    print(name, "sampled-pixel max abs err", err, flush=True)
+    assert err <= IMG_TOL
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_sparse_gradient_sampled_components(runs, name):
+    import torch
+    R = _run(runs, name)
+    b, r, t, p = R["b"], R["r"], R["t"], R["p"]
+    op = oracle_params(p)
+    C = b.channels
+    H, W = b.hw[0]
+    pix = _pixels(b, 24, 11)
+    rng = np.random.default_rng(12)
+    up = rng.normal(0.0, 1.0, (len(pix), C)).astype(np.float32)
+    dense = np.zeros((C, H, W), np.float32)
+    dense[:, pix[:, 1], pix[:, 2]] = up.T
+    grads = r.backward(t, torch.as_tensor(dense.reshape(-1), device="cuda"))
+    torch.cuda.synchronize()
+    names = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+    gg = {n: x.cpu().numpy().astype(np.float64) for n, x in zip(names, grads)}
+    _, _, adj = oracle.composite(b, R["ref"], op, pixels=pix, upstream=up.astype(np.float64))
+    # curves whose Gaussians received an adjoint
+    touched = np.unique(R["ref"]["curve"][np.any(adj != 0, axis=1)])
+    assert len(touched) > 0
+    seeds, where = [], []
+    for c in touched[:6]:
+        k0, k1 = b.key_off[c], b.key_off[c + 1]
+        t0, t1 = b.tau_off[c], b.tau_off[c + 1]
+        for k in rng.choice(k1 - k0, min(4, k1 - k0), replace=False):
+            seeds += [(c, 1, k), (c, 2, k), (c, 3, k)]
+            where += [("key_xy", 2 * (k0 + k)), ("key_xy", 2 * (k0 + k) + 1), ("key_w", k0 + k)]
+            if not (b.flags[c] & synth.FILLED):
+                seeds.append((c, 4, k))
+                where.append(("key_s", k0 + k))
+        for tt in rng.choice(t1 - t0, min(3, t1 - t0), replace=False):
+            seeds.append((c, 5, tt))
+            where.append(("tau", t0 + tt))
+        seeds.append((c, 6, 0))
+        where.append(("opacity", c))
+        seeds.append((c, 7, 0))
+        where.append(("color", C * c))
+    ref = oracle.param_grad_seeds(b, R["ref"], adj, np.array(seeds, np.int32), op)
+    got = np.array([gg[n].reshape(-1)[i] for n, i in where])
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    print(name, "sparse-gradient max abs err", err, "scale", scale, flush=True)
+    assert err <= 1e-4 * scale + 1e-6
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_dense_gradient_invariances(runs, name):
+    """sum_i w_i dL/dw_i = 0 and sum_j tau_j dL/dtau_j = 0 per curve (projective
+    weight invariance; samples are uniform in u, so a knot scale changes nothing)."""
+    import torch
+    R = _run(runs, name)
+    b, r, t = R["b"], R["r"], R["t"]
+    target = torch.zeros_like(R["img"]) + 0.5
+    grads = r.backward(t, 2.0 * (R["img"] - target))
+    torch.cuda.synchronize()
+    gw, gt = grads[1].cpu().numpy().astype(np.float64), grads[3].cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for c in range(b.n_curves):
+        k0, k1 = b.key_off[c], b.key_off[c + 1]
+        t0, t1 = b.tau_off[c], b.tau_off[c + 1]
+        tw = b.key_w[k0:k1] * gw[k0:k1]
+        tt = b.tau[t0:t1] * gt[t0:t1]
+        worst = max(worst, abs(tw.sum()) / (np.abs(tw).sum() + 1e-6), abs(tt.sum()) / (np.abs(tt).sum() + 1e-6))
+    print(name, "worst relative Euler residual", worst, flush=True)
+    assert worst < 1e-3
