@@ -308,6 +308,7 @@ def cpu_baseline(b, p, target):
     op = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
                                                         "fill_pad", "h", "alpha_max", "eps_T")}
     op["kappa"] = int(p.kappa)
+    op["cutoff"] = float(p.k_sigma)
     threads = oracle.num_threads()
     t0 = time.perf_counter()
     g = oracle.gaussians(b, op)

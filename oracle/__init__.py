@@ -24,10 +24,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nsplat_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-# Table S1 defaults, plus the readings the paper leaves open (alpha clamp,
-# termination threshold, fill padding).  cutoff <= 0: no support cutoff.
+# Table S1 defaults, plus the readings the paper leaves open: alpha clamp,
+# termination threshold, fill padding, and the support radius (alpha = 0 beyond
+# cutoff * sigma; Eq. 9 itself has infinite support, cutoff <= 0 restores it).
 DEFAULTS = dict(delta_c=10.0, delta_b=0.5, rho=2.0, eta=1.5, gamma=5.0, nl_factor=3.0,
-                fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=0.0, kappa=4)
+                fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=6.0, kappa=4)
 
 P_COUNT, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_FLAG = range(8)
 KIND = dict(key_x=1, key_y=2, key_w=3, key_s=4, tau=5, opacity=6, color0=7, color1=8, color2=9)

@@ -170,13 +170,14 @@ template <class T> double dom_hi(const Curve<T>& cv) { return val(cv.U[cv.m - cv
 template <class T>
 int find_span(const Curve<T>& cv, double u) {
   const int lo = cv.p, hi = cv.m - cv.p - 1;
-  std::vector<double> Uv(cv.U.size());
-  for (size_t k = 0; k < cv.U.size(); ++k) Uv[k] = val(cv.U[k]);
-  int i = (int)(std::upper_bound(Uv.begin(), Uv.end(), u) - Uv.begin()) - 1;
+  const auto& U = cv.U;
+  // first index with U[k] > u, minus one: the largest k with U[k] <= u
+  int i = (int)(std::upper_bound(U.begin(), U.end(), u,
+                                 [](double x, const T& k) { return x < val(k); }) - U.begin()) - 1;
   if (i > hi) i = hi;
   if (i < lo) i = lo;
-  while (i > lo && !(Uv[i] < Uv[i + 1])) --i;      // step back over empty spans
-  while (i < hi && !(Uv[i] < Uv[i + 1])) ++i;
+  while (i > lo && !(val(U[i]) < val(U[i + 1]))) --i;      // step back over empty spans
+  while (i < hi && !(val(U[i]) < val(U[i + 1]))) ++i;
   return i;
 }
 
@@ -216,8 +217,8 @@ void curve_point(const Curve<T>& cv, const T& u, int span, T out[3], bool full =
 
 // Eq. 2: C'(u) = (W sum N' w P - S sum N' w) / W^2, with N' the u-derivative
 // of the Cox-de Boor recursion (taken with a dual number seeded on u).
-void curve_deriv(const Curve<double>& cv, double u, int span, double out[3], bool full = false) {
-  std::vector<Dual> U(cv.U.begin(), cv.U.end());
+void curve_deriv(const Curve<double>& cv, const std::vector<Dual>& U, double u, int span, double out[3],
+                 bool full = false) {
   const Dual ud(u, 1.0);
   double S[3] = {0, 0, 0}, Sd[3] = {0, 0, 0}, Wt = 0, Wd = 0;
   const int i0 = full ? 0 : span - cv.p, i1 = full ? cv.ncp - 1 : span;
@@ -238,11 +239,12 @@ void curve_deriv(const Curve<double>& cv, double u, int span, double out[3], boo
 double arc_length(const Curve<double>& cv, int n_L) {
   const double a = dom_lo(cv), b = dom_hi(cv);
   const double du = (b - a) / n_L;
+  const std::vector<Dual> Ud(cv.U.begin(), cv.U.end());  // knots as constants for the u-derivative
   double L = 0.0;
   for (int j = 1; j <= n_L; ++j) {
     const double u = a + (j - 0.5) * du;
     double d[3];
-    curve_deriv(cv, u, find_span(cv, u), d);
+    curve_deriv(cv, Ud, u, find_span(cv, u), d);
     L += std::sqrt(d[0] * d[0] + d[1] * d[1]) * du;
   }
   return L;
@@ -782,7 +784,7 @@ int or_curve_eval(int p, int closed, int nk, int nt, const double* key_xy, const
     const int span = find_span(cv, u);
     double pt[3], d[3];
     curve_point(cv, u, span, pt, full != 0);
-    curve_deriv(cv, u, span, d, full != 0);
+    curve_deriv(cv, std::vector<Dual>(cv.U.begin(), cv.U.end()), u, span, d, full != 0);
     for (int k = 0; k < 3; ++k) { out[6 * i + k] = pt[k]; out[6 * i + 3 + k] = d[k]; }
   }
   return 0;

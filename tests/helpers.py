@@ -16,6 +16,7 @@ def oracle_params(p):
     d = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
                                                        "fill_pad", "h", "alpha_max", "eps_T")}
     d["kappa"] = int(p.kappa)
+    d["cutoff"] = float(p.k_sigma)
     return d
 
 

@@ -1,0 +1,180 @@
+"""The batched form (many uneven scenes in one launch sequence, persistent
+work queue, HIP-graph replay, device-side annealing) against the per-scene
+plain path, and the autotuner."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import IMG_TOL, PARAM_NAMES, grad_close, oracle_params
+from paper_2606_31764_amd import synth
+from paper_2606_31764_amd.render import Params
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(seed=7000):
+    rng = np.random.default_rng(seed)
+    scenes = []
+    for s in range(6):
+        kind = s % 3
+        side = int(rng.choice([40, 56, 72, 96]))
+        if kind == 0:
+            scenes.append(synth._assemble(synth.strokes(seed + s, n_curves=4, size=side, step=6.0), [[side, side]],
+                                          [[1.0, 1.0, 1.0]], 3))
+        elif kind == 1:
+            scenes.append(synth._assemble(synth.fills(seed + s, n_paths=5, size=side, radius=(4.0, 20.0)),
+                                          [[side, side]], [[1.0, 1.0, 1.0]], 3))
+        else:
+            ps = synth.long_splines(seed + s, n_curves=2, n_cp=40, size=side, channels=3)
+            scenes.append(synth._assemble(ps, [[side, side]], [[0.9, 0.9, 0.9]], 3))
+    return scenes
+
+
+def _step(r, t, target):
+    import torch
+    img = r.run_forward(t).clone()
+    grads = r.backward(t, 2.0 * (img - target))
+    torch.cuda.synchronize()
+    return img, grads
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_matches_per_scene_plain(persistent):
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    scenes = _mixed()
+    b = synth.concat(scenes)
+    p = Params().replace(delta_c=2.0, h=2.0)
+    rb = Renderer(b, p, persistent=persistent)
+    tb = param_tensors(b)
+    target = torch.full((3 * sum(int(h) * int(w) for h, w in b.hw),), 0.5, device="cuda")
+    img_b, grads_b = _step(rb, tb, target)
+    ranges_b, idx_b = rb.tiles()
+    g_off = 0
+    px_off = 0
+    tile_off = 0
+    for s, sc in enumerate(scenes):
+        r = Renderer(sc, p)
+        t = param_tensors(sc)
+        n = 3 * int(sc.hw[0][0]) * int(sc.hw[0][1])
+        img, grads = _step(r, t, target[px_off:px_off + n])
+        # images bit-identical
+        np.testing.assert_array_equal(img.cpu().numpy(), img_b[px_off:px_off + n].cpu().numpy())
+        # tile lists identical up to the scene's offsets
+        ranges, idx = r.tiles()
+        nt = len(ranges)
+        rb_s = ranges_b[tile_off:tile_off + nt].astype(np.int64)
+        nonempty = ranges[:, 1] > ranges[:, 0]
+        assert np.all((rb_s[:, 1] > rb_s[:, 0]) == nonempty)
+        for k in np.nonzero(nonempty)[0]:
+            np.testing.assert_array_equal(idx_b[rb_s[k, 0]:rb_s[k, 1]] - g_off, idx[ranges[k, 0]:ranges[k, 1]])
+        # gradients: same values up to FP32 atomic order
+        k0, k1 = b.key_off[sum(x.n_curves for x in scenes[:s])], None
+        c0 = sum(x.n_curves for x in scenes[:s])
+        ko, to = int(b.key_off[c0]), int(b.tau_off[c0])
+        sl = dict(key_xy=slice(ko, ko + len(sc.key_w)), key_w=slice(ko, ko + len(sc.key_w)),
+                  key_s=slice(ko, ko + len(sc.key_w)), tau=slice(to, to + len(sc.tau)),
+                  color=slice(c0, c0 + sc.n_curves), opacity=slice(c0, c0 + sc.n_curves))
+        gb = {nm: grads_b[i][sl[nm]].cpu().numpy().astype(np.float64) for i, nm in enumerate(PARAM_NAMES)}
+        gp = {nm: grads[i].cpu().numpy().astype(np.float64) for i, nm in enumerate(PARAM_NAMES)}
+        assert grad_close(gb, gp, rtol=1e-5, atol=1e-6) <= 1.0
+        g_off += int(r.read_counters()[0])
+        px_off += n
+        tile_off += nt
+
+
+def test_batched_against_oracle():
+    b = synth.concat(_mixed(7100))
+    p = Params().replace(delta_c=2.0, h=2.0)
+    op = oracle_params(p)
+    target = oracle.render(synth.perturbed(b, seed=4), op)[0]
+    from helpers import gpu_run
+    out = gpu_run(b, p, target=target, persistent=True)
+    img_ref, _, _ = oracle.render(b, op)
+    assert np.abs(out["image"] - img_ref).max() <= IMG_TOL
+    _, gref, _, _ = oracle.loss_and_grad(b, target, op)
+    assert grad_close(out["grads"], gref) <= 1.0
+
+
+def test_graph_replay_with_device_annealing():
+    """A captured fwd+bwd step with h read from a device scalar that a
+    captured Eq. 14 kernel anneals: every replay matches an eager step at
+    that replay's h (eager work and synchronisation between replays)."""
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=4200, n_paths=8, size=80)
+    h_dev = torch.full((1,), 4.0, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    p = Params()
+    # capacity sized at the finest step (h_min = 1)
+    sizer = Renderer(b, p.replace(h=1.0))
+    t = param_tensors(b)
+    sizer.run_forward(t)
+    cnt = sizer.read_counters()
+    caps = dict(gauss=cnt[3] + 64, pairs=cnt[4] + 256, boundary=cnt[5] + 16)
+    r = Renderer(b, p, caps=caps, h_dev=h_dev)
+    target = torch.full((3 * 80 * 80,), 0.6, device="cuda")
+    total, T_steps = 1000, 1000
+
+    def step_fn():
+        r.ctx.check(r.ctx.lib.nsplat_anneal_h(r.ctx.h, ctypes.c_void_p(h_dev.data_ptr()),
+                                              ctypes.c_void_p(step.data_ptr()), 0, T_steps, 8.0, 1.0, 0.1, 0.8,
+                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        img = r.run_forward(t, sync=False)
+        return img, r.backward(t, 2.0 * (img - target))
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step_fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    step.fill_(0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        img_g, grads_g = step_fn()
+    for k, t_step in enumerate((0, 200, 450, 700, 900)):
+        step.fill_(t_step)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        h_now = float(h_dev.item())
+        assert h_now == np.float32(oracle.anneal(t_step, T_steps, 8.0, 1.0, np.float32(0.1), np.float32(0.8)))
+        img_r = img_g.clone()
+        gr_r = [x.clone() for x in grads_g]
+        # eager reference at the same h
+        e = Renderer(b, p.replace(h=h_now))
+        img_e = e.run_forward(t).clone()
+        gr_e = e.backward(t, 2.0 * (img_e - target))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(img_r.cpu().numpy(), img_e.cpu().numpy())
+        ge = {nm: x.cpu().numpy().astype(np.float64) for nm, x in zip(PARAM_NAMES, gr_e)}
+        gg = {nm: x.cpu().numpy().astype(np.float64) for nm, x in zip(PARAM_NAMES, gr_r)}
+        assert grad_close(gg, ge, rtol=1e-5, atol=1e-6) <= 1.0
+        # and some unrelated eager work between replays
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+
+
+def test_autotune_returns_a_valid_config():
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=4300, n_paths=12, size=96)
+    p = Params().replace(h=2.0)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    # size pair buffers for the smallest tile (most pairs)
+    r.run_forward(t, params=p.replace(tile=8))
+    img = r.run_forward(t).clone()
+    dL = 2.0 * (img - 0.5)
+    tile, batch, times = r.autotune(t, dL)
+    assert tile in (8, 16, 32) and batch in (32, 64, 128, 256)
+    assert all(x > 0 for x in times)
+    r2 = Renderer(b, p.replace(tile=tile, batch=batch))
+    img2 = r2.run_forward(t).clone()
+    torch.cuda.synchronize()
+    assert np.abs(img2.cpu().numpy() - img.cpu().numpy()).max() < 2e-6

@@ -1,0 +1,191 @@
+"""Edge cases of the GPU path, each against the oracle or an exact property."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import IMG_TOL, grad_close, grad_report, gpu_run, oracle_params
+from paper_2606_31764_amd import synth
+from paper_2606_31764_amd.render import Params
+
+pytestmark = pytest.mark.gpu
+
+R2 = math.sqrt(2.0) / 2.0
+
+
+def _batch(parts, hw=(48, 40), bg=(1.0, 1.0, 1.0), channels=3):
+    return synth._assemble(parts, [list(hw)], [list(bg)], channels)
+
+
+def _part(xy, p=3, closed=False, filled=False, w=None, s=None, tau=None, color=(0.2, 0.4, 0.6), o=0.8, seed=0):
+    rng = np.random.default_rng(seed)
+    xy = np.asarray(xy, float)
+    nk = len(xy)
+    nt = nk if closed else nk - p
+    return dict(scene=0, degree=p, flags=(synth.CLOSED if closed else 0) | (synth.FILLED if filled else 0),
+                key_xy=xy, key_w=rng.uniform(0.5, 2.0, nk) if w is None else np.asarray(w, float),
+                key_s=rng.uniform(1.0, 3.0, nk) if s is None else np.asarray(s, float),
+                tau=rng.uniform(0.5, 1.5, nt) if tau is None else np.asarray(tau, float), color=color, opacity=o)
+
+
+def _full_parity(b, p, target_seed=5):
+    op = oracle_params(p)
+    tb = synth.perturbed(b, seed=target_seed)
+    target = oracle.render(tb, op)[0]
+    out = gpu_run(b, p, target=target)
+    ref_g = oracle.gaussians(b, op)
+    np.testing.assert_array_equal(out["plan"][:, :7], ref_g["plan"][:, :7])
+    img_ref, _, _ = oracle.render(b, op)
+    assert np.abs(out["image"] - img_ref).max() <= IMG_TOL
+    _, gref, _, _ = oracle.loss_and_grad(b, target, op)
+    worst = grad_close(out["grads"], gref)
+    assert worst <= 1.0, grad_report(out["grads"], gref)
+    return out
+
+
+def test_no_curves_gives_background():
+    b = synth._assemble([], [[20, 30]], [[0.25, 0.5, 0.75]], 3)
+    out = gpu_run(b, Params(), target=np.zeros(3 * 20 * 30, np.float32))
+    img = out["image"].reshape(3, 20, 30)
+    for c, v in enumerate((0.25, 0.5, 0.75)):
+        assert np.all(img[c] == np.float32(v))
+    assert out["counters"][0] == 0 and out["counters"][1] == 0
+    assert all(g.size == 0 for g in out["grads"].values())
+
+
+def test_scene_without_curves_inside_a_batch():
+    b1 = synth.config2(seed=2601, n_curves=3, size=40)
+    empty = synth._assemble([], [[24, 24]], [[1.0, 1.0, 1.0]], 3)
+    b = synth.concat([b1, empty, synth.config2(seed=2602, n_curves=2, size=36)])
+    p = Params().replace(delta_c=2.0)
+    op = oracle_params(p)
+    out = gpu_run(b, p, backward=False)
+    img_ref, _, _ = oracle.render(b, op)
+    assert np.abs(out["image"] - img_ref).max() <= IMG_TOL
+    off = 3 * 40 * 40
+    assert np.all(out["image"][off:off + 3 * 24 * 24] == 1.0)
+
+
+def test_curve_outside_the_canvas():
+    b = _batch([_part([[200, 200], [210, 205], [220, 200], [230, 210]])])
+    out = gpu_run(b, Params(), target=np.zeros(3 * 48 * 40, np.float32))
+    assert out["counters"][1] == 0
+    assert np.all(out["image"] == 1.0)
+    for n, g in out["grads"].items():
+        assert np.all(g == 0.0), n
+
+
+def test_degenerate_point_curve():
+    b = _batch([_part([[20.3, 17.6]] * 5, p=3)])
+    out = _full_parity(b, Params().replace(delta_c=2.0))
+    assert out["plan"][0, 1] == 2          # M = max(2, ceil(0))
+
+
+def test_repeated_knots_nine_point_circle_stroke():
+    c, r = np.array([24.0, 20.0]), 12.0
+    P = c + r * np.array([(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1), (1, 0)], float)
+    w = [1, R2, 1, R2, 1, R2, 1, R2, 1]
+    b = _batch([_part(P, p=2, w=w, s=np.full(9, 2.0), tau=[0.25, 0, 0.25, 0, 0.25, 0, 0.25])])
+    p = Params().replace(delta_c=2.0)
+    out = _full_parity(b, p)
+    mu = out["gauss"]["mu"]
+    ref = oracle.gaussians(b, oracle_params(p))["mu"]
+    assert np.abs(mu - ref).max() < 1e-9
+    # FP32-stored weights (sqrt(2)/2 rounded) keep the circle to ~1e-7 of r
+    assert np.abs(np.hypot(mu[:, 0] - c[0], mu[:, 1] - c[1]) - r).max() < 1e-6
+
+
+def test_all_degrees_open_and_closed_strokes():
+    rng = np.random.default_rng(3)
+    parts = []
+    for p in range(1, 6):
+        parts.append(_part(rng.uniform(5, 43, (p + 4, 2)), p=p, seed=p, color=rng.uniform(0, 1, 3)))
+        parts.append(_part(rng.uniform(5, 43, (p + 3, 2)), p=p, closed=True, seed=10 + p,
+                           color=rng.uniform(0, 1, 3)))
+    b = _batch(parts, hw=(48, 48))
+    _full_parity(b, Params().replace(delta_c=2.0))
+
+
+def test_invalid_curves_set_status_and_are_skipped():
+    good = _part([[5, 5], [20, 30], [35, 10], [40, 40]], p=3)
+    bad = [
+        dict(_part([[5, 5], [20, 30], [35, 10], [40, 40]], p=3), degree=6),   # degree too high
+        _part([[5, 5], [20, 30]], p=3, tau=[1.0]),                            # too few key points
+        _part([[5, 5], [20, 30], [35, 10], [40, 40]], p=3, filled=True),      # filled but open
+    ]
+    for b_ in bad:
+        b_["tau"] = np.asarray(b_["tau"], float)
+    b = _batch([good] + bad)
+    out = gpu_run(b, Params().replace(delta_c=2.0), backward=False)
+    assert out["counters"][2] & 8           # NSPLAT_STATUS_DATA
+    assert np.all(out["plan"][1:, 0] == 0)
+    ref = gpu_run(_batch([good]), Params().replace(delta_c=2.0), backward=False)
+    np.testing.assert_array_equal(out["image"], ref["image"])
+
+
+def test_capacity_growth_gives_same_result():
+    b = synth.config3(seed=3700, n_paths=5, size=64)
+    p = Params().replace(h=2.0)
+    a = gpu_run(b, p, backward=False, caps=dict(gauss=16, pairs=16, boundary=8))
+    c = gpu_run(b, p, backward=False, caps=dict(gauss=1 << 16, pairs=1 << 18, boundary=1 << 12))
+    np.testing.assert_array_equal(a["image"], c["image"])
+    np.testing.assert_array_equal(a["idx"], c["idx"])
+
+
+def test_frozen_plan_keeps_counts():
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=3800, n_paths=4, size=64)
+    p = Params().replace(h=2.0)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    r.run_forward(t)
+    plan0 = r.plan_np().copy()
+    b2 = b.copy()
+    b2.key_xy = b.key_xy * 1.03          # would change arc lengths and windows
+    t2 = param_tensors(b2)
+    r.run_forward(t2, frozen=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.plan_np()[:, :7], plan0[:, :7])
+    ref = oracle.gaussians(b2, oracle_params(p), frozen_plan=plan0)
+    g = r.gaussians()
+    assert np.abs(g["mu"] - ref["mu"]).max() < 1e-9
+    assert np.abs(g["opacity"] - ref["opacity"]).max() < 2e-7
+
+
+def test_device_annealing_matches_eq14():
+    import ctypes
+    import torch
+    from paper_2606_31764_amd.render import Context
+    ctx = Context(0)
+    h = torch.zeros(1, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vals = []
+    for t in range(0, 1001, 50):
+        ctx.check(ctx.lib.nsplat_anneal_h(ctx.h, ctypes.c_void_p(h.data_ptr()), None, t, 1000, 8.0, 1.0, 0.1, 0.8,
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        vals.append((t, float(h.item())))
+    for t, v in vals:
+        assert v == np.float32(oracle.anneal(t, 1000, 8.0, 1.0, np.float32(0.1), np.float32(0.8)))
+    # device step counter form: reads and increments the counter
+    for t in range(3):
+        ctx.check(ctx.lib.nsplat_anneal_h(ctx.h, ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(step.data_ptr()), 0,
+                                          1000, 8.0, 1.0, 0.1, 0.8,
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    assert int(step.item()) == 3
+
+
+@pytest.mark.parametrize("name", ["strokes", "fills"])
+def test_tile_sizes_agree(name):
+    if name == "strokes":
+        b, p = synth.config2(seed=2700, n_curves=6, size=72), Params().replace(delta_c=2.0)
+    else:
+        b, p = synth.config3(seed=3900, n_paths=6, size=72), Params().replace(h=2.0)
+    target = oracle.render(synth.perturbed(b, seed=1), oracle_params(p))[0]
+    outs = {t: gpu_run(b, p.replace(tile=t), target=target) for t in (8, 16, 32)}
+    for t in (8, 32):
+        assert np.abs(outs[t]["image"] - outs[16]["image"]).max() < 2e-6
+        assert grad_close(outs[t]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
