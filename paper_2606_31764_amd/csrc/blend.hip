@@ -90,20 +90,25 @@ __device__ inline uint64_t lanes_below() {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-template <int C, int TILE>
+// LDS bytes per wavefront for a step of `depth` entries.
+constexpr int FWD_ENTRY_BYTES = 36;   // geometry, opacity + colour, list position
+constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
+
+template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, int persistent) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
-  __shared__ float4 s_geo[WPB][64], s_pc[WPB][64];
-  __shared__ int s_pos[WPB][64];
+  extern __shared__ __align__(16) char smem[];
+  const int depth = min(pr.batch, 64 * E);   // entries per step (E per lane; fewer lanes below 64)
   const float amax = pr.alpha_max, eps = pr.eps_T, ks = pr.k_sigma;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  float4* wgeo = s_geo[wv];
-  float4* wpc = s_pc[wv];
-  int* wpos = s_pos[wv];
+  char* mine_lds = smem + (size_t)wv * (64 * E) * FWD_ENTRY_BYTES;
+  float4* wgeo = (float4*)mine_lds;
+  float4* wpc = wgeo + 64 * E;
+  int* wpos = (int*)(wpc + 64 * E);
   const uint64_t below = lanes_below();
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
@@ -130,25 +135,38 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       done[q] = !(x0 + lx < st.W && y0 + ly < st.H);
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
-    // front to back: list positions end-1 down to start, 64 per step
-    Entry e;
+    // front to back: list positions end-1 down to start, `depth` per step
+    Entry e[E];
     int hi = end;
-    load_entry<C>(idx, gs, cv, hi - 1 - lane, hi - 1 - lane >= start, &e);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int k = u * 64 + lane;
+      load_entry<C>(idx, gs, cv, hi - 1 - k, k < depth && hi - 1 - k >= start, &e[u]);
+    }
     while (hi > start) {
-      const int mypos = hi - 1 - lane;
-      const bool ok = mypos >= start;
-      float4 geo;
-      const bool keep = ok && entry_geometry<TILE>(e.r, ox, oy, ks, quad, &geo);
-      const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int dst = __popcll(m & below);
-        wgeo[dst] = geo;
-        wpc[dst] = make_float4(e.r.opacity, e.c0, e.c1, e.c2);
-        wpos[dst] = mypos;
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int k = u * 64 + lane;
+        const int mypos = hi - 1 - k;
+        const bool ok = k < depth && mypos >= start;
+        float4 geo;
+        const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+          const int dst = cnt + __popcll(m & below);
+          wgeo[dst] = geo;
+          wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
+          wpos[dst] = mypos;
+        }
+        cnt += __popcll(m);
       }
-      const int cnt = __popcll(m);
-      hi -= 64;
-      load_entry<C>(idx, gs, cv, hi - 1 - lane, hi - 1 - lane >= start, &e);  // next step, in flight
+      hi -= depth;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {  // next step, in flight while this one is composited
+        const int k = u * 64 + lane;
+        load_entry<C>(idx, gs, cv, hi - 1 - k, k < depth && hi - 1 - k >= start, &e[u]);
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -251,7 +269,7 @@ __device__ inline void flush_curve(double* gcurve, int c, bool fill, float (&acc
 // SDF); colour gradients (and a stroke curve's opacity gradient, its o_j all
 // being o) belong to the curve, so each lane keeps running per-curve sums that
 // are flushed when the curve changes along the list or every FLUSH entries.
-template <int C, int TILE>
+template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
@@ -260,14 +278,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
-  __shared__ float4 s_geo[WPB][64], s_pc[WPB][64];
-  __shared__ int4 s_meta[WPB][64];  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
+  extern __shared__ __align__(16) char smem[];
+  const int depth = min(pr.batch, 64 * E);
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  float4* wgeo = s_geo[wv];
-  float4* wpc = s_pc[wv];
-  int4* wmeta = s_meta[wv];
+  char* mine_lds = smem + (size_t)wv * (64 * E) * BWD_ENTRY_BYTES;
+  float4* wgeo = (float4*)mine_lds;
+  float4* wpc = wgeo + 64 * E;
+  int4* wmeta = (int4*)(wpc + 64 * E);  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
   const uint64_t below = lanes_below();
   float* __restrict__ ggrad = w.ggrad;
   for (int it = 0;; ++it) {
@@ -311,25 +330,39 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     int cur = -1, since = 0;
     bool cur_fill = false;
     float accC[3] = {0.0f, 0.0f, 0.0f}, accO = 0.0f;
-    Entry e;
+    Entry e[E];
     int base = lo;
-    load_entry<C>(idx, gs, cv, base + lane, base + lane < end, &e);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int k = u * 64 + lane;
+      load_entry<C>(idx, gs, cv, base + k, k < depth && base + k < end, &e[u]);
+    }
     while (base < end) {
-      const int mypos = base + lane;
-      const bool ok = mypos < end;
-      float4 geo;
-      const bool keep = ok && entry_geometry<TILE>(e.r, ox, oy, ks, quad, &geo);
-      const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int dst = __popcll(m & below);
-        const double sg = (double)e.r.sigma;
-        wgeo[dst] = geo;
-        wpc[dst] = make_float4(e.r.opacity, e.c0, e.c1, e.c2);
-        wmeta[dst] = make_int4(e.fill ? ~e.g : e.g, e.r.curve, mypos, __float_as_int((float)(1.0 / (sg * sg * sg))));
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int k = u * 64 + lane;
+        const int mypos = base + k;
+        const bool ok = k < depth && mypos < end;
+        float4 geo;
+        const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+          const int dst = cnt + __popcll(m & below);
+          const double sg = (double)e[u].r.sigma;
+          wgeo[dst] = geo;
+          wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
+          wmeta[dst] = make_int4(e[u].fill ? ~e[u].g : e[u].g, e[u].r.curve, mypos,
+                                 __float_as_int((float)(1.0 / (sg * sg * sg))));
+        }
+        cnt += __popcll(m);
       }
-      const int cnt = __popcll(m);
-      base += 64;
-      load_entry<C>(idx, gs, cv, base + lane, base + lane < end, &e);  // next step, in flight
+      base += depth;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {  // next step, in flight while this one is processed
+        const int k = u * 64 + lane;
+        load_entry<C>(idx, gs, cv, base + k, k < depth && base + k < end, &e[u]);
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -408,44 +441,66 @@ __global__ void k_reset_queue(int32_t* q) {
 }
 
 template <class K>
-int resident_grid(K kernel, int n_blocks, int n_cu) {
+int resident_grid(K kernel, int n_blocks, int n_cu, size_t lds) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   const int g = per_cu * n_cu;
   return g < n_blocks ? g : n_blocks;
 }
 
-template <int C, int TILE>
+inline int depth_factor(int batch) { return batch <= 64 ? 1 : (batch <= 128 ? 2 : 4); }
+
+template <int C, int TILE, int E>
 hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
   const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
   if (n_items <= 0) return hipSuccess;
+  const size_t lds = (size_t)WPB * 64 * E * FWD_ENTRY_BYTES;
   int grid = (n_items + WPB - 1) / WPB;
   if (persistent) {
-    grid = resident_grid(k_blend_fwd<C, TILE>, grid, L.n_cu);
+    grid = resident_grid(k_blend_fwd<C, TILE, E>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_FWD);
-  hipLaunchKernelGGL((k_blend_fwd<C, TILE>), dim3(grid), dim3(BLOCK), 0, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_fwd<C, TILE, E>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
                      T_final, n_last, persistent);
   return hipGetLastError();
 }
 
-template <int C, int TILE>
+template <int C, int TILE, int E>
 hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
   const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
   if (n_items <= 0) return hipSuccess;
+  const size_t lds = (size_t)WPB * 64 * E * BWD_ENTRY_BYTES;
   int grid = (n_items + WPB - 1) / WPB;
   if (persistent) {
-    grid = resident_grid(k_blend_bwd<C, TILE>, grid, L.n_cu);
+    grid = resident_grid(k_blend_bwd<C, TILE, E>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_BWD);
-  hipLaunchKernelGGL((k_blend_bwd<C, TILE>), dim3(grid), dim3(BLOCK), 0, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_bwd<C, TILE, E>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, dL,
                      T_final, n_last, persistent);
   return hipGetLastError();
+}
+
+template <int C, int TILE>
+hipError_t fwd_d(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
+  switch (depth_factor(L.pr->batch)) {
+    case 1: return fwd_t<C, TILE, 1>(L, image, T_final, n_last, persistent);
+    case 2: return fwd_t<C, TILE, 2>(L, image, T_final, n_last, persistent);
+    default: return fwd_t<C, TILE, 4>(L, image, T_final, n_last, persistent);
+  }
+}
+
+template <int C, int TILE>
+hipError_t bwd_d(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
+  switch (depth_factor(L.pr->batch)) {
+    case 1: return bwd_t<C, TILE, 1>(L, dL, T_final, n_last, persistent);
+    case 2: return bwd_t<C, TILE, 2>(L, dL, T_final, n_last, persistent);
+    default: return bwd_t<C, TILE, 4>(L, dL, T_final, n_last, persistent);
+  }
 }
 
 }  // namespace
@@ -453,26 +508,26 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
 hipError_t launch_blend_fwd(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
   const int C = L.cv->channels, t = L.pr->tile;
   if (C == 1) {
-    if (t == 8) return fwd_t<1, 8>(L, image, T_final, n_last, persistent);
-    if (t == 16) return fwd_t<1, 16>(L, image, T_final, n_last, persistent);
-    return fwd_t<1, 32>(L, image, T_final, n_last, persistent);
+    if (t == 8) return fwd_d<1, 8>(L, image, T_final, n_last, persistent);
+    if (t == 16) return fwd_d<1, 16>(L, image, T_final, n_last, persistent);
+    return fwd_d<1, 32>(L, image, T_final, n_last, persistent);
   }
-  if (t == 8) return fwd_t<3, 8>(L, image, T_final, n_last, persistent);
-  if (t == 16) return fwd_t<3, 16>(L, image, T_final, n_last, persistent);
-  return fwd_t<3, 32>(L, image, T_final, n_last, persistent);
+  if (t == 8) return fwd_d<3, 8>(L, image, T_final, n_last, persistent);
+  if (t == 16) return fwd_d<3, 16>(L, image, T_final, n_last, persistent);
+  return fwd_d<3, 32>(L, image, T_final, n_last, persistent);
 }
 
 hipError_t launch_blend_bwd(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last,
                             int persistent) {
   const int C = L.cv->channels, t = L.pr->tile;
   if (C == 1) {
-    if (t == 8) return bwd_t<1, 8>(L, dL, T_final, n_last, persistent);
-    if (t == 16) return bwd_t<1, 16>(L, dL, T_final, n_last, persistent);
-    return bwd_t<1, 32>(L, dL, T_final, n_last, persistent);
+    if (t == 8) return bwd_d<1, 8>(L, dL, T_final, n_last, persistent);
+    if (t == 16) return bwd_d<1, 16>(L, dL, T_final, n_last, persistent);
+    return bwd_d<1, 32>(L, dL, T_final, n_last, persistent);
   }
-  if (t == 8) return bwd_t<3, 8>(L, dL, T_final, n_last, persistent);
-  if (t == 16) return bwd_t<3, 16>(L, dL, T_final, n_last, persistent);
-  return bwd_t<3, 32>(L, dL, T_final, n_last, persistent);
+  if (t == 8) return bwd_d<3, 8>(L, dL, T_final, n_last, persistent);
+  if (t == 16) return bwd_d<3, 16>(L, dL, T_final, n_last, persistent);
+  return bwd_d<3, 32>(L, dL, T_final, n_last, persistent);
 }
 
 }  // namespace nsp

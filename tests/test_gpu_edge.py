@@ -189,3 +189,17 @@ def test_tile_sizes_agree(name):
     for t in (8, 32):
         assert np.abs(outs[t]["image"] - outs[16]["image"]).max() < 2e-6
         assert grad_close(outs[t]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_batch_depths_agree(tile):
+    """The per-pixel order of operations does not depend on the batch depth,
+    so images are bit-identical across depths; gradients agree up to the
+    order of FP32 atomics."""
+    b, p = synth.config3(seed=3950, n_paths=8, size=88), Params().replace(h=2.0, tile=tile)
+    target = oracle.render(synth.perturbed(b, seed=2), oracle_params(p))[0]
+    outs = {d: gpu_run(b, p.replace(batch=d), target=target) for d in (32, 64, 128, 256)}
+    for d in (32, 128, 256):
+        np.testing.assert_array_equal(outs[d]["image"], outs[64]["image"])
+        np.testing.assert_array_equal(outs[d]["n_last"], outs[64]["n_last"])
+        assert grad_close(outs[d]["grads"], outs[64]["grads"], rtol=1e-5, atol=1e-7) <= 1.0
