@@ -295,9 +295,26 @@ def bench_batched(args):
     g.replay()
     torch.cuda.synchronize()
     same = all(float((a - b_).abs().max()) <= 1e-4 * float(a.abs().max() + 1e-6) for a, b_ in zip(eager, grads))
+    # diagnostic (outside the timed regions): per-phase times of one eager step of each form
+    def phase_pass(steps, runs):
+        c = steps[0].r.ctx
+        timing_on(c, True)
+        for st_ in steps:
+            for _ in range(runs):
+                st_.run()
+        torch.cuda.synchronize()
+        ph = timing_read(c)
+        timing_on(c, False)
+        return {k: v[0] / runs for k, v in ph.items()}
+    ph_plain = phase_pass(plain, 2)
+    ph_bat = phase_pass([bat], 2)
+    log("phase ms per step   plain   batched")
+    for k in PHASES:
+        log("  %-10s %8.3f %8.3f" % (k, ph_plain[k], ph_bat[k]))
     res = dict(scenes=b5.n_scenes, gaussians=bat.G, plain_ms_per_step=plain_ms, batched_ms_per_step=bat_ms,
                plain_gaussians_per_s=G_plain / (plain_ms * 1e-3), batched_gaussians_per_s=bat.G / (bat_ms * 1e-3),
-               speedup=plain_ms / bat_ms, graph_replay_matches_eager=bool(same))
+               speedup=plain_ms / bat_ms, graph_replay_matches_eager=bool(same),
+               phases_ms_plain=ph_plain, phases_ms_batched=ph_bat)
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
     return res
 
