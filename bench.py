@@ -255,6 +255,15 @@ def bench_batched(args):
     target = torch.cat(tgt_all).cpu().numpy()
     bat = Step(b5, p, target, persistent=True, ctx=ctx)
     log("batched G = %d (plain sum %d), pairs = %d" % (bat.G, G_plain, bat.pairs))
+    # autotune tile size and batch depth for the batched form (pair buffers
+    # sized for the smallest tile first)
+    bat.r.run_forward(bat.t, params=p.replace(tile=8))
+    bat.run()
+    torch.cuda.synchronize()
+    tile, depth, tune_ms = bat.r.autotune(bat.t, bat.dL)
+    log("autotune: tile %d, batch depth %d (%s)" % (tile, depth, " ".join("%.2f" % x for x in tune_ms)))
+    tuned = bat if (tile, depth) == (p.tile, p.batch) else \
+        Step(b5, p.replace(tile=tile, batch=depth), target, persistent=True, ctx=ctx)
     K = args.batched_steps
     for _ in range(2):
         for s in plain:
@@ -268,33 +277,40 @@ def bench_batched(args):
     e1.record()
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1) / K
-    # capture the batched step
-    s_cap = torch.cuda.Stream()
-    s_cap.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s_cap):
+
+    def graph_ms(st):
+        """Capture one step of st into a graph; time K replays; check a replay against an eager step."""
+        s_cap = torch.cuda.Stream()
+        s_cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_cap):
+            for _ in range(2):
+                st.run()
+        torch.cuda.current_stream().wait_stream(s_cap)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            grads = st.run()
+        torch.cuda.synchronize()
         for _ in range(2):
-            bat.run()
-    torch.cuda.current_stream().wait_stream(s_cap)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        grads = bat.run()
-    torch.cuda.synchronize()
-    for _ in range(2):
+            g.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        eager = [x.clone() for x in st.run()]
+        torch.cuda.synchronize()
         g.replay()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(K):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    bat_ms = e0.elapsed_time(e1) / K
-    # the replayed graph must reproduce the eager step
-    eager = [x.clone() for x in bat.run()]
-    torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    same = all(float((a - b_).abs().max()) <= 1e-4 * float(a.abs().max() + 1e-6) for a, b_ in zip(eager, grads))
+        torch.cuda.synchronize()
+        ok = all(float((a - b_).abs().max()) <= 1e-4 * float(a.abs().max() + 1e-6) for a, b_ in zip(eager, grads))
+        del g
+        return ms, ok
+
+    bat_ms, same = graph_ms(tuned)
+    same_cfg_ms = bat_ms if tuned is bat else graph_ms(bat)[0]
+    bat = tuned
     # diagnostic (outside the timed regions): per-phase times of one eager step of each form
     def phase_pass(steps, runs):
         c = steps[0].r.ctx
@@ -314,6 +330,8 @@ def bench_batched(args):
     res = dict(scenes=b5.n_scenes, gaussians=bat.G, plain_ms_per_step=plain_ms, batched_ms_per_step=bat_ms,
                plain_gaussians_per_s=G_plain / (plain_ms * 1e-3), batched_gaussians_per_s=bat.G / (bat_ms * 1e-3),
                speedup=plain_ms / bat_ms, graph_replay_matches_eager=bool(same),
+               tile=tile, batch_depth=depth, autotune_ms=tune_ms,
+               batched_ms_at_plain_config=same_cfg_ms, speedup_at_plain_config=plain_ms / same_cfg_ms,
                phases_ms_plain=ph_plain, phases_ms_batched=ph_bat)
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
     return res

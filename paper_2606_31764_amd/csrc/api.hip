@@ -30,7 +30,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
   const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
-  const size_t sizes[18] = {
+  const size_t sizes[N_WS] = {
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
       sizeof(double) * (size_t)N,                          // L
       sizeof(int32_t) * (size_t)(N + 1),                   // goff
@@ -49,9 +49,10 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(double2) * (size_t)std::max<int64_t>(bcap, 1),  // gb
       sizeof(int32_t) * 64,                                // queue
       sizeof(int32_t) * (size_t)std::max<int64_t>(gcap, 1),  // aux
+      sizeof(double4) * (size_t)(bcap / SDF_CHUNK + 2 * N + 2),  // cbox
   };
   size_t off = 0;
-  for (int i = 0; i < 18; ++i) {
+  for (int i = 0; i < N_WS; ++i) {
     lay.off[i] = off;
     off += align256(sizes[i]);
   }
@@ -80,6 +81,7 @@ Work carve(void* ws, const Layout& lay) {
   w.gb = (double2*)(b + lay.off[15]);
   w.queue = (int32_t*)(b + lay.off[16]);
   w.aux = (int32_t*)(b + lay.off[17]);
+  w.cbox = (double4*)(b + lay.off[18]);
   return w;
 }
 

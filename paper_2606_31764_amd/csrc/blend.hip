@@ -224,19 +224,36 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
   }
 }
 
-// Sum over the 64 lanes of a wavefront with DPP row shifts and row
-// broadcasts (no LDS traffic): inclusive sums inside each row of 16 lanes,
-// then row 0 into row 1, row 2 into row 3, and rows 0-1 into row 3; lane 63
-// ends with the total, which is returned to every lane.
-__device__ inline float wave_total(float v) {
-  int x = __float_as_int(v);
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true)));
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true)));
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true)));
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true)));
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false)));
-  x = __float_as_int(__int_as_float(x) + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false)));
-  return __int_as_float(__builtin_amdgcn_readlane(x, 63));
+// Totals over the 64 lanes of a wavefront of N per-lane values at once, with
+// DPP row shifts and row broadcasts (no LDS traffic): inclusive sums inside
+// each row of 16 lanes, then row 0 into row 1, row 2 into row 3, and rows 0-1
+// into row 3, so that lane 63 ends with the total.  The N chains are
+// interleaved so that each fills the others' data-hazard slots.  Lane i < N
+// of the result holds the total of value i (0 elsewhere), ready for one
+// N-lane atomic.
+template <int N>
+__device__ inline float wave_totals_to_lanes(const float (&v)[N]) {
+  int x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = __float_as_int(v[i]);
+#define NSP_DPP_STEP(ctrl, rmask, bc)                                                                          \
+  _Pragma("unroll") for (int i = 0; i < N; ++i) x[i] = __float_as_int(                                        \
+      __int_as_float(x[i]) + __int_as_float(__builtin_amdgcn_update_dpp(0, x[i], ctrl, rmask, 0xf, bc)));
+  NSP_DPP_STEP(0x111, 0xf, true)
+  NSP_DPP_STEP(0x112, 0xf, true)
+  NSP_DPP_STEP(0x114, 0xf, true)
+  NSP_DPP_STEP(0x118, 0xf, true)
+  NSP_DPP_STEP(0x142, 0xa, false)
+  NSP_DPP_STEP(0x143, 0xc, false)
+#undef NSP_DPP_STEP
+  const int lane = __lane_id();
+  float out = 0.0f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float t = __int_as_float(__builtin_amdgcn_readlane(x[i], 63));
+    out = lane == i ? t : out;
+  }
+  return out;
 }
 
 __device__ inline int wave_min(int v) {
@@ -249,18 +266,17 @@ __device__ inline int wave_min(int v) {
 // stroke curve) into the FP64 per-curve accumulators.
 template <int C>
 __device__ inline void flush_curve(double* gcurve, int c, bool fill, float (&accC)[3], float& accO) {
-  double* dst = gcurve + 4 * (int64_t)c;
+  float v[C + 1];
+  v[0] = fill ? 0.0f : accO;
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) {
-    const float t = wave_total(accC[ch]);
-    if (__lane_id() == 0 && t != 0.0f) unsafeAtomicAdd(dst + 1 + ch, (double)t);
+    v[1 + ch] = accC[ch];
     accC[ch] = 0.0f;
   }
-  if (!fill) {
-    const float t = wave_total(accO);
-    if (__lane_id() == 0 && t != 0.0f) unsafeAtomicAdd(dst, (double)t);
-  }
   accO = 0.0f;
+  const float t = wave_totals_to_lanes<C + 1>(v);
+  const int lane = __lane_id();
+  if (lane <= C && t != 0.0f) unsafeAtomicAdd(gcurve + 4 * (int64_t)c + lane, (double)t);
 }
 
 // Adjoint of the forward blend, back to front from each pixel's stopping
@@ -330,6 +346,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     int cur = -1, since = 0;
     bool cur_fill = false;
     float accC[3] = {0.0f, 0.0f, 0.0f}, accO = 0.0f;
+    int pend_g = -1;  // fill Gaussian whose dL/do_j awaits its reduction
+    float pend_v = 0.0f;
     Entry e[E];
     int base = lo;
 #pragma unroll
@@ -417,20 +435,31 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
           }
         }
         if (__ballot(act) == 0ull) continue;
-        float* dst = ggrad + (int64_t)(fill ? ~gsig : gsig) * GG;
         if (fill) {
-          const float t = wave_total(v[3]);
-          if (lane == 0 && t != 0.0f) unsafeAtomicAdd(dst + 3, t);
+          // fill Gaussians carry one value; two of them are reduced together
+          if (pend_g < 0) {
+            pend_g = ~gsig;
+            pend_v = v[3];
+          } else {
+            const float vv[2] = {pend_v, v[3]};
+            const float t = wave_totals_to_lanes<2>(vv);
+            const int gd = lane == 0 ? pend_g : ~gsig;
+            if (lane < 2 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)gd * GG + 3, t);
+            pend_g = -1;
+          }
         } else {
           accO += v[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const float t = wave_total(v[i]);
-            if (lane == 0 && t != 0.0f) unsafeAtomicAdd(dst + i, t);
-          }
+          const float vv[3] = {v[0], v[1], v[2]};
+          const float t = wave_totals_to_lanes<3>(vv);
+          if (lane < 3 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)gsig * GG + lane, t);
         }
       }
       __builtin_amdgcn_wave_barrier();
+    }
+    if (pend_g >= 0) {
+      const float vv[1] = {pend_v};
+      const float t = wave_totals_to_lanes<1>(vv);
+      if (lane < 1 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)pend_g * GG + 3 + lane, t);
     }
     if (cur >= 0) flush_curve<C>(w.gcurve, cur, cur_fill, accC, accO);
   }

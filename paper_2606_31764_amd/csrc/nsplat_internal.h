@@ -18,6 +18,7 @@ constexpr double LN2 = 0.69314718055994530942;
 constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
+constexpr int N_WS = 19;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -55,12 +56,20 @@ struct Work {
   double2* gb;         // [caps.boundary] boundary-point adjoints
   int32_t* queue;      // [4] work-queue counters of the persistent kernels
   int32_t* aux;        // [caps.gauss] fill Gaussians: nearest boundary segment, sign in bit 31
+  double4* cbox;       // [caps.boundary / SDF_CHUNK + 2 * n_curves + 2] fill SDF chunk boxes
 };
+
+// Boundary segments per bounding box in the fill SDF.  Curve c (first
+// boundary point boff) has a header at cbox_base(boff, c) whose x is the
+// largest coordinate magnitude of its boundary, then one box (x0, x1, y0, y1)
+// per chunk of SDF_CHUNK segments.
+constexpr int SDF_CHUNK = 8;
+__host__ __device__ inline int64_t cbox_base(int64_t boff, int c) { return boff / SDF_CHUNK + 2 * (int64_t)c; }
 
 constexpr int GG = 4;  // floats per Gaussian in Work::ggrad
 
 struct Layout {
-  size_t off[18];
+  size_t off[N_WS];
   size_t total;
   int64_t sort_blocks, scan_blocks;
 };

@@ -228,6 +228,27 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
     y0 = fmin(y0, __shfl_xor(y0, off));
     y1 = fmax(y1, __shfl_xor(y1, off));
   }
+  // Bounding box of each chunk of SDF_CHUNK segments: points k*SDF_CHUNK up to
+  // and including the chunk's end point (point 0 closes the last chunk).
+  __syncthreads();
+  {
+    const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
+    double4* box = w.cbox + cbox_base(boff, c) + 1;
+    const double2* bp = w.bpts + boff;
+    for (int k = threadIdx.x; k < K; k += PREP_THREADS) {
+      const int i0 = k * SDF_CHUNK, i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
+      double2 e = bp[i1 < nb ? i1 : 0];
+      double4 r = make_double4(e.x, e.x, e.y, e.y);
+      for (int i = i0; i < i1; ++i) {
+        e = bp[i];
+        r.x = fmin(r.x, e.x);
+        r.y = fmax(r.y, e.x);
+        r.z = fmin(r.z, e.y);
+        r.w = fmax(r.w, e.y);
+      }
+      box[k] = r;
+    }
+  }
   const int t = threadIdx.x;
   if ((t & 63) == 0) {
     red[0][t >> 6] = x0;
@@ -236,17 +257,19 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
     red[3][t >> 6] = y1;
   }
   __syncthreads();
-  if (t == 0 && !frozen) {
-    for (int i = 1; i < PREP_THREADS / 64; ++i) {
-      x0 = fmin(x0, red[0][i]);
-      x1 = fmax(x1, red[1][i]);
-      y0 = fmin(y0, red[2][i]);
-      y1 = fmax(y1, red[3][i]);
-    }
-    x0 = fmin(x0, red[0][0]);
-    x1 = fmax(x1, red[1][0]);
-    y0 = fmin(y0, red[2][0]);
-    y1 = fmax(y1, red[3][0]);
+  if (t != 0) return;
+  for (int i = 1; i < PREP_THREADS / 64; ++i) {
+    x0 = fmin(x0, red[0][i]);
+    x1 = fmax(x1, red[1][i]);
+    y0 = fmin(y0, red[2][i]);
+    y1 = fmax(y1, red[3][i]);
+  }
+  x0 = fmin(x0, red[0][0]);
+  x1 = fmax(x1, red[1][0]);
+  y0 = fmin(y0, red[2][0]);
+  y1 = fmax(y1, red[3][0]);
+  w.cbox[cbox_base(boff, c)] = make_double4(fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))), 0.0, 0.0, 0.0);
+  if (!frozen) {
     const SceneTab* st = w.scenes + cv.scene[c];
     const double h = (double)read_h(pr), pad = (double)pr.fill_pad;
     const double px = pad * (x1 - x0), py = pad * (y1 - y0);
@@ -269,33 +292,80 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
 // tie) and the sign of the exact integer winding number (crossing rule with
 // orientation tests); inside <=> winding >= 1.  Returns the argmin segment
 // and its projection parameter.
-__device__ inline double polyline_sdf(double qx, double qy, const double2* __restrict__ bp, int nb, int* arg,
-                                      double* targ, double* sgn_out) {
+//
+// The result is the one of the plain loop over all segments, computed with
+// the same arithmetic on a subset of them.  Segments come in chunks of
+// SDF_CHUNK with a bounding box each.  A chunk whose box is farther from q
+// than an upper bound on the minimum (the nearest chunk start point, or the
+// running minimum) cannot hold the argmin, with a relative margin of 1e-8
+// that covers the rounding of both sides; skipping it changes neither the
+// minimum nor the lowest index reaching it.  Its crossings are counted
+// without visiting its segments when the box lies entirely above, below,
+// left or right of q: a chain of segments right of q crosses the ray from q
+// upward as many times, net, as its end point lies above q minus its start
+// point does, and one left of q never crosses it.  The left/right decision
+// keeps a margin that makes every orientation test in the chunk exact in
+// sign, so the count equals the plain one.
+__device__ inline double polyline_sdf(double qx, double qy, const double2* __restrict__ bp,
+                                      const double4* __restrict__ box, int nb, int* arg, double* targ,
+                                      double* sgn_out) {
+  const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
+  const double scale = 1.0 + fabs(qx) + fabs(qy) + 2.0 * box[0].x;
+  box += 1;
+  double ub = INFINITY;
+  for (int k = 0; k < K; ++k) {
+    const double2 V = bp[k * SDF_CHUNK];
+    const double dx = V.x - qx, dy = V.y - qy;
+    ub = fmin(ub, dx * dx + dy * dy);
+  }
+  const double abs_margin = 1e-18 * scale * scale, mx = 1e-9 * scale;
   double best = INFINITY, tbest = 0.0;
   int ibest = 0, wn = 0;
-  double2 A = bp[0];
-  for (int i = 0; i < nb; ++i) {
-    const double2 B = bp[i + 1 < nb ? i + 1 : 0];
-    const double ex = B.x - A.x, ey = B.y - A.y;
-    const double ee = ex * ex + ey * ey;
-    const double rx = qx - A.x, ry = qy - A.y;
-    double t = 0.0;
-    if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
-    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
-    const double d2 = px * px + py * py;
-    if (d2 < best) {
-      best = d2;
-      ibest = i;
-      tbest = t;
+  for (int k = 0; k < K; ++k) {
+    const double4 b = box[k];  // x0, x1, y0, y1
+    const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
+    const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
+    const double lb = ex0 * ex0 + ey0 * ey0;
+    const double thr = fmin(ub, best);
+    bool visit = lb <= thr + 1e-8 * thr + abs_margin;
+    const int i0 = k * SDF_CHUNK;
+    const int i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
+    int wk = 0;
+    if (!visit && b.z <= qy && qy < b.w) {
+      if (b.x > qx + mx) {
+        const double2 E = bp[i1 < nb ? i1 : 0];
+        wk = (E.y > qy ? 1 : 0) - (bp[i0].y > qy ? 1 : 0);
+      } else if (!(b.y < qx - mx)) {
+        visit = true;
+      }
     }
-    const double cr = ex * ry - rx * ey;  // > 0: q left of A->B
-    if (A.y <= qy) {
-      if (B.y > qy && cr > 0.0) ++wn;
-    } else {
-      if (B.y <= qy && cr < 0.0) --wn;
+    if (visit) {
+      double2 A = bp[i0];
+      for (int i = i0; i < i1; ++i) {
+        const double2 B = bp[i + 1 < nb ? i + 1 : 0];
+        const double ex = B.x - A.x, ey = B.y - A.y;
+        const double ee = ex * ex + ey * ey;
+        const double rx = qx - A.x, ry = qy - A.y;
+        double t = 0.0;
+        if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+        const double d2 = px * px + py * py;
+        if (d2 < best) {
+          best = d2;
+          ibest = i;
+          tbest = t;
+        }
+        const double cr = ex * ry - rx * ey;  // > 0: q left of A->B
+        if (A.y <= qy) {
+          if (B.y > qy && cr > 0.0) ++wk;
+        } else {
+          if (B.y <= qy && cr < 0.0) --wk;
+        }
+        A = B;
+      }
     }
-    A = B;
+    wn += wk;
   }
   *arg = ibest;
   *targ = tbest;
@@ -345,7 +415,8 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
       int arg;
       double t, sgn;
-      const double d = polyline_sdf(qx, qy, w.bpts + row[P_BOFF], row[P_NSAMP], &arg, &t, &sgn);
+      const double d = polyline_sdf(qx, qy, w.bpts + row[P_BOFF], w.cbox + cbox_base(row[P_BOFF], c), row[P_NSAMP],
+                                    &arg, &t, &sgn);
       const double z = ((double)pr.gamma / h) * (sgn * d);
       r.mx = qx;
       r.my = qy;
