@@ -50,6 +50,8 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(int32_t) * 64,                                // queue
       sizeof(int32_t) * (size_t)std::max<int64_t>(gcap, 1),  // aux
       sizeof(double4) * (size_t)(bcap / SDF_CHUNK + 2 * N + 2),  // cbox
+      sizeof(int32_t) * (size_t)std::max<int64_t>(nsplat_num_tiles(sc, 8), 1),  // order
+      sizeof(int32_t) * 64,                                // obin
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -82,6 +84,8 @@ Work carve(void* ws, const Layout& lay) {
   w.queue = (int32_t*)(b + lay.off[16]);
   w.aux = (int32_t*)(b + lay.off[17]);
   w.cbox = (double4*)(b + lay.off[18]);
+  w.order = (int32_t*)(b + lay.off[19]);
+  w.obin = (int32_t*)(b + lay.off[20]);
   return w;
 }
 

@@ -7,6 +7,7 @@
 //                 with wavefront match-ranking), so each tile keeps ascending
 //                 Gaussian order
 //   k_tile_ranges [begin, end) of every tile's slice
+//   k_order_*     the blend kernels' tile order, longest lists first
 #include "nsplat_internal.h"
 
 namespace nsp {
@@ -181,6 +182,55 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
   }
 }
 
+// Tiles in order of decreasing list length, by power-of-two class, so that
+// the blend kernels start the long lists first and fill in with short ones.
+// Only the processing order changes (each (tile, quadrant) item writes its
+// own pixels); the order inside a class is whatever the atomics give.
+__device__ inline int len_class(const int32_t* __restrict__ ranges, int t) {
+  const int k = __clz(ranges[2 * t + 1] - ranges[2 * t]);  // 31 for one entry, smaller for longer lists
+  return k > 31 ? 31 : k;
+}
+
+__global__ __launch_bounds__(256) void k_order_count(const int32_t* __restrict__ ranges, int n_tiles,
+                                                     int32_t* obin) {
+  __shared__ int h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < n_tiles) atomicAdd(&h[len_class(ranges, t)], 1);
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x] > 0) atomicAdd(&obin[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_order_scan(int32_t* obin) {
+  const int l = threadIdx.x;
+  const int v = l < 32 ? obin[l] : 0;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    const int o = __shfl_up(incl, off);
+    if (l >= off) incl += o;
+  }
+  if (l < 32) obin[32 + l] = incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_order_scatter(const int32_t* __restrict__ ranges, int n_tiles,
+                                                       int32_t* obin, int32_t* __restrict__ order) {
+  __shared__ int h[32], base[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  int k = 0, r = 0;
+  if (t < n_tiles) {
+    k = len_class(ranges, t);
+    r = atomicAdd(&h[k], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x] > 0) base[threadIdx.x] = atomicAdd(&obin[32 + threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < n_tiles) order[base[k] + r] = t;
+}
+
 }  // namespace
 
 hipError_t launch_bin(const Launch& L) {
@@ -234,6 +284,13 @@ hipError_t launch_bin(const Launch& L) {
                        L.bf->ranges, 0, 2 * L.n_tiles);
     hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
                        L.bf->ranges);
+    const int nt = (int)L.n_tiles, ob = (nt + 255) / 256;
+    if (nt > 0) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
+      hipLaunchKernelGGL(k_order_count, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin);
+      hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, L.stream, L.w.obin);
+      hipLaunchKernelGGL(k_order_scatter, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin, L.w.order);
+    }
   }
   return hipGetLastError();
 }

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
     if (item >= n_items) break;
-    const int tile = item / Cfg::QUADS, quad = item - tile * Cfg::QUADS;
+    const int tq = item / Cfg::QUADS, quad = item - tq * Cfg::QUADS;
+    const int tile = w.order[tq];
     const int s = scene_of_tile(w.scenes, n_scenes, tile);
     const SceneTab st = w.scenes[s];
     const int lt = tile - st.tile_off;
@@ -308,7 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
     if (item >= n_items) break;
-    const int tile = item / Cfg::QUADS, quad = item - tile * Cfg::QUADS;
+    const int tq = item / Cfg::QUADS, quad = item - tq * Cfg::QUADS;
+    const int tile = w.order[tq];
     const int s = scene_of_tile(w.scenes, n_scenes, tile);
     const SceneTab st = w.scenes[s];
     const int lt = tile - st.tile_off;

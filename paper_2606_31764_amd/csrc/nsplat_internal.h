@@ -18,7 +18,7 @@ constexpr double LN2 = 0.69314718055994530942;
 constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 19;                // workspace entries
+constexpr int N_WS = 21;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -57,6 +57,8 @@ struct Work {
   int32_t* queue;      // [4] work-queue counters of the persistent kernels
   int32_t* aux;        // [caps.gauss] fill Gaussians: nearest boundary segment, sign in bit 31
   double4* cbox;       // [caps.boundary / SDF_CHUNK + 2 * n_curves + 2] fill SDF chunk boxes
+  int32_t* order;      // [tiles at the smallest tile size] tiles by decreasing list length
+  int32_t* obin;       // [64] list-length class counts, then their offsets
 };
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
