@@ -119,8 +119,12 @@ __global__ void k_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t 
   if (step_dev) *step_dev = t + 1;
 }
 
-__global__ void k_l2(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out,
-                     float* loss, int64_t n) {
+// One atomic per block: same-address float atomics serialise in L2, so the
+// loss partials are reduced across the block first (and the grid is kept
+// to a few hundred blocks, each thread taking many elements).
+__global__ __launch_bounds__(256) void k_l2(const float* __restrict__ a, const float* __restrict__ b,
+                                            float* __restrict__ out, float* loss, int64_t n) {
+  __shared__ float red[4];
   float s = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float d = a[i] - b[i];
@@ -130,7 +134,9 @@ __global__ void k_l2(const float* __restrict__ a, const float* __restrict__ b, f
   if (loss) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    if (__lane_id() == 0) unsafeAtomicAdd(loss, s);
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, (red[0] + red[1]) + (red[2] + red[3]));
   }
 }
 
@@ -160,7 +166,7 @@ hipError_t launch_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t 
 
 hipError_t launch_l2(const float* a, const float* b, float* out, float* loss, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_l2, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, a, b, out, loss, n);
+  hipLaunchKernelGGL(k_l2, dim3(grid_for((n + 15) / 16, 256, 512)), dim3(256), 0, s, a, b, out, loss, n);
   return hipGetLastError();
 }
 
