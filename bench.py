@@ -36,7 +36,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -89,7 +89,8 @@ def timing_read(ctx):
 def blend_work(step, tile):
     """Algorithmic work of one forward blend launch, counted with torch on the
     GPU from the launch's own tile lists and stopping positions: evaluated
-    (pixel, Gaussian) pairs and in-support pairs."""
+    (pixel, Gaussian) pairs, in-support pairs, and in-support pairs of fill
+    Gaussians."""
     import torch
     r = step.r
     G = step.G
@@ -108,8 +109,11 @@ def blend_work(step, tile):
     pos = torch.arange(P, device="cuda")
     gidx = idx[:P].long()
     stop = r.n_last.view(H, W).long()
+    curve = u8[:, 24:28].contiguous().view(torch.int32).view(G).long()
+    is_fill = ((r.meta.flags.long() & 2) != 0)[curve][gidx]
     ev = 0
     hit = 0
+    hit_fill = 0
     ks = r.params.k_sigma
     for ly in range(tile):
         for lx in range(tile):
@@ -124,13 +128,80 @@ def blend_work(step, tile):
             h = e & (dx * dx + dy * dy <= (ks * sigma[gidx]) ** 2)
             ev += int(e.sum().item())
             hit += int(h.sum().item())
-    return ev, hit
+            hit_fill += int((h & is_fill).sum().item())
+    return ev, hit, hit_fill
 
 
-# FP32 operations per pair in the forward blend loop (a fused multiply-add counts 2):
-# distance test 2 sub + mul + fma(2) + cmp = 6; in support: mul, exp2, mul, min,
-# mul (alpha T), 3 fma (6), sub, mul, cmp = 15.
-FWD_TEST_FLOPS, FWD_HIT_FLOPS = 6, 15
+# Algorithmic FP32 operations per in-support (pixel, Gaussian) pair; an FMA
+# counts 2.  Forward: d^2 (2 sub, mul, fma) 5, exp2 argument and exp2 2,
+# o G and the alpha_max clamp 2, alpha T 1, three colour FMAs 6, 1 - alpha
+# and T (1 - alpha) 2, termination test 1 = 19.  Reverse pass of a fill
+# Gaussian: d^2 5, exp2 2, o G and clamp 2, 1 - alpha and its reciprocal 2,
+# T recovery 1, alpha T 1, dL/dalpha 3 (sub + fma) = 9, colour gradient 3 FMAs
+# 6, colour behind 3 (mul + fma) = 9, gate and scale 1, dL/do_j FMA 2 = 40;
+# a stroke Gaussian adds dL/dmu and dL/dsigma: 14 = 54.
+FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 19, 40, 54
+# The build disables packed FP32 instructions, so the FP32 vector peak is
+# 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s, not the
+# packed 157.3.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def source_digest():
+    """SHA-256 of the blend kernel sources (identifies the build that counters were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("blend.hip", "nsplat_internal.h"):
+        with open(os.path.join(ROOT, "paper_2606_31764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary under
+    profiles/, or None when that summary was taken on other kernel sources."""
+    import re
+    path = os.path.join(ROOT, "profiles", "blend_bwd_c3_512_fills.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"traffic_bytes_per_launch\[%s\]:\s*([0-9.eE+]+)" % re.escape(kernel), txt)
+    if not m_sha or not m_b or m_sha.group(1) != source_digest():
+        return None
+    return float(m_b.group(1))
+
+
+def phase_bytes(step, tile):
+    """Algorithmic HBM bytes of one step's sample / bin / sort / ranges phases:
+    emit writes the 32 B record of every Gaussian (+4 B argmin of a fill
+    Gaussian); bin reads the records twice (count, emit), writes and rescans
+    the 4 B counts and writes the 8 B (key, index) pairs; every radix pass
+    reads the keys for its histogram, then reads and writes keys and indices
+    (20 B per pair); ranges reads the keys and writes 8 B per tile."""
+    r = step.r
+    cnt = r.read_counters()
+    G, P = int(cnt[0]), int(cnt[1])
+    plan = r.plan_np()
+    fill = (r.meta.flags.cpu().numpy() & 2) != 0
+    n_fill = int(plan[fill, 0].astype(np.int64).sum())
+    n_tiles = int(r.ctx.lib.nsplat_num_tiles(ctypes.byref(r.meta.scenes_c), int(tile)))
+    bits = 0
+    while bits < 31 and (1 << bits) < n_tiles:
+        bits += 1
+    passes = (bits + 7) // 8
+    return dict(emit=32 * G + 4 * n_fill, bin=64 * G + 12 * G + 8 * P, sort=passes * 20 * P,
+                ranges=4 * P + 8 * n_tiles), passes
+
+
+def hbm_table(nbytes, phases):
+    out = {}
+    for k, b in nbytes.items():
+        ms = phases.get(k)
+        if ms:
+            gbs = b / (ms * 1e-3) / 1e9
+            out[k] = dict(bytes=b, ms=ms, gbs=gbs, frac=gbs / PEAK["hbm_gbs"])
+    return out
 
 
 def bench_main(args):
@@ -182,6 +253,9 @@ def bench_main(args):
                            gaussians=st.G, pairs=st.pairs, tile=p.tile, batch=p.batch),
                phases_ms={k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
                roofline=roof)
+    nbytes, passes = phase_bytes(st, p.tile)
+    out["hbm_phases"] = hbm_table(nbytes, out["phases_ms"])
+    out["hbm_phases"]["radix_passes"] = passes
     if args.copy_probe:
         src = torch.ones(64 * 1024 * 1024, device="cuda")
         dst = torch.empty_like(src)
@@ -197,33 +271,21 @@ def bench_main(args):
 
 
 def roofline(st, dom, dom_ms, p):
-    """Roofline entry of the dominant kernel (algorithmic work / measured time)."""
-    if dom in ("blend_fwd",):
-        ev, hit = blend_work(st, p.tile)
-        flops = FWD_TEST_FLOPS * ev + FWD_HIT_FLOPS * hit
+    """Roofline entry of the dominant kernel: algorithmic FP32 operations of
+    its in-support pairs over its measured average launch time, against the
+    non-packed FP32 vector peak; HBM traffic from the profiled counters."""
+    if dom in ("blend_fwd", "blend_bwd"):
+        ev, hit, hit_fill = blend_work(st, p.tile)
+        if dom == "blend_fwd":
+            flops, kernel = FWD_HIT_FLOPS * hit, "k_blend_fwd"
+        else:
+            flops = BWD_FILL_HIT_FLOPS * hit_fill + BWD_STROKE_HIT_FLOPS * (hit - hit_fill)
+            kernel = "k_blend_bwd"
         ach = flops / (dom_ms * 1e-3) / 1e12
-        return dict(kernel="k_blend_fwd", bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
-                    frac=ach / PEAK["fp32_tflops"], traffic=None, evaluated_pairs=ev, in_support_pairs=hit,
+        return dict(kernel=kernel, bound="alu", achieved=ach, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / ALU_PEAK_TFLOPS, traffic=profiled_traffic(kernel), in_support_pairs=hit,
+                    in_support_fill_pairs=hit_fill, evaluated_pairs=ev, flops_per_launch=flops,
                     ms_per_launch=dom_ms)
-    if dom == "blend_bwd":
-        ev, hit = blend_work(st, p.tile)
-        # reverse pass: same distance test; per in-support pair ~40 FP32 ops plus 7 x 6 wavefront
-        # reduction adds per Gaussian and wavefront
-        flops = FWD_TEST_FLOPS * ev + 40 * hit
-        ach = flops / (dom_ms * 1e-3) / 1e12
-        return dict(kernel="k_blend_bwd", bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
-                    frac=ach / PEAK["fp32_tflops"], traffic=None, evaluated_pairs=ev, in_support_pairs=hit,
-                    ms_per_launch=dom_ms)
-    if dom == "emit":
-        # fill Gaussians: one FP64 segment test (~24 flops) per boundary segment per lattice point
-        plan = st.r.plan_np()
-        flags = st.r.meta.flags.cpu().numpy()
-        fill = (flags & 2) != 0
-        seg_tests = int((plan[fill, 0].astype(np.int64) * plan[fill, 1]).sum())
-        flops = 24.0 * seg_tests
-        ach = flops / (dom_ms * 1e-3) / 1e12
-        return dict(kernel="k_emit", bound="alu", achieved=ach, peak=PEAK["fp64_tflops"], unit="TFLOP/s",
-                    frac=ach / PEAK["fp64_tflops"], traffic=None, segment_tests=seg_tests, ms_per_launch=dom_ms)
     return dict(kernel=dom, bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=None,
                 ms_per_launch=dom_ms)
 
@@ -333,6 +395,10 @@ def bench_batched(args):
                tile=tile, batch_depth=depth, autotune_ms=tune_ms,
                batched_ms_at_plain_config=same_cfg_ms, speedup_at_plain_config=plain_ms / same_cfg_ms,
                phases_ms_plain=ph_plain, phases_ms_batched=ph_bat)
+    nbytes, passes = phase_bytes(bat, tile)
+    res["hbm_phases_batched"] = hbm_table(nbytes, ph_bat)
+    res["hbm_phases_batched"]["radix_passes"] = passes
+    res["pairs"] = int(bat.r.read_counters()[1])
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
     return res
 
