@@ -15,8 +15,8 @@
 //   k_adj_boundary  one lane per boundary point: the same point adjoint.
 //   Both reduce within the wavefront by (curve, span) segment before the FP64
 //   global atomics.
-//   k_fold          one thread per curve: control points -> key points (the
-//                   closed wrap), knots -> intervals (suffix sums of the
+//   k_fold          one wavefront per curve: control points -> key points
+//                   (the closed wrap), knots -> intervals (suffix sums of the
 //                   cumulative sum) -> tau, FP32 outputs.
 #include "nsplat_internal.h"
 
@@ -287,6 +287,8 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
     const int64_t g = base + lane;
     int64_t kcur = -1 - lane;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t skey = -1 - lane, sj = 0;  // boundary segment (start, end point) this lane's SDF gradient goes to
+    double sv[4] = {0.0, 0.0, 0.0, 0.0};
     int c = 0;
     CurveView v;
     v.p = 0;
@@ -326,12 +328,24 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
         if (d > 0.0 && dO != 0.0 && ds > 1e-18) {
           const double dd = dO * (double)cv.opacity[c] * ds * gh * sgn;  // dL/dd
           const double nxv = -px / d, nyv = -py / d;
-          double2* gb = w.gb + row[P_BOFF];
-          unsafeAtomicAdd(&gb[ib].x, -dd * (1.0 - t) * nxv);
-          unsafeAtomicAdd(&gb[ib].y, -dd * (1.0 - t) * nyv);
-          unsafeAtomicAdd(&gb[jb].x, -dd * t * nxv);
-          unsafeAtomicAdd(&gb[jb].y, -dd * t * nyv);
+          skey = (int64_t)row[P_BOFF] + ib;
+          sj = (int64_t)row[P_BOFF] + jb;
+          sv[0] = -dd * (1.0 - t) * nxv;
+          sv[1] = -dd * (1.0 - t) * nyv;
+          sv[2] = -dd * t * nxv;
+          sv[3] = -dd * t * nyv;
         }
+      }
+    }
+    // lanes on the same boundary segment (neighbouring lattice points) are
+    // summed in the wavefront before the FP64 atomics
+    if (__ballot(skey >= 0) != 0ull) {
+      seg_reduce(skey, sv);
+      if (seg_head(skey)) {
+        unsafeAtomicAdd(&w.gb[skey].x, sv[0]);
+        unsafeAtomicAdd(&w.gb[skey].y, sv[1]);
+        unsafeAtomicAdd(&w.gb[sj].x, sv[2]);
+        unsafeAtomicAdd(&w.gb[sj].y, sv[3]);
       }
     }
     if (__ballot(fill) != 0ull) accumulate_curve(w, kcur, c, v, cur);
@@ -396,17 +410,22 @@ __global__ __launch_bounds__(256) void k_adj_boundary(nsplat_curves cv, Work w, 
 
 // One thread per curve: fold the FP64 control-point and knot adjoints into
 // the key-point and interval parametrisation and write FP32 gradients.
-__global__ void k_fold(nsplat_curves cv, Work w, nsplat_grads gr) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cv.n_curves) return;
+// One wavefront per curve: colour / opacity sums to FP32, control-point
+// adjoints folded back onto key points (the closed wrap sends several control
+// points to one key point), and the knot adjoints turned into interval
+// adjoints: U_k = sum_{l<k} delta_l gives dL/d delta_l = sum_{k>l} dL/dU_k, a
+// suffix sum taken 64 knots at a time from the top with a carried total.
+__global__ __launch_bounds__(64) void k_fold(nsplat_curves cv, Work w, nsplat_grads gr) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
   const CurveView v = curve_view(cv, w.knots, c);
   const int C = cv.channels;
   const double* gc = w.gcurve + 4 * (int64_t)c;
-  gr.opacity[c] = (float)gc[0];
-  for (int ch = 0; ch < C; ++ch) gr.color[(int64_t)c * C + ch] = (float)gc[1 + ch];
+  if (lane == 0) gr.opacity[c] = (float)gc[0];
+  if (lane < C) gr.color[(int64_t)c * C + lane] = (float)gc[1 + lane];
   const bool ok = curve_valid(v);
   const double* gcp = w.gcp + 4 * ((int64_t)v.k0 + (int64_t)c * CP_PAD);
-  for (int k = 0; k < v.nk; ++k) {
+  for (int k = lane; k < v.nk; k += 64) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (ok) {
       if (!v.closed()) {
@@ -425,20 +444,32 @@ __global__ void k_fold(nsplat_curves cv, Work w, nsplat_grads gr) {
     gr.key_s[kk] = (float)acc[3];
   }
   float* gt = gr.tau + v.t0;
-  for (int t = 0; t < v.nt; ++t) gt[t] = 0.0f;
-  if (!ok) return;
-  // knots U_k = sum_{l<k} delta_l  =>  dL/d delta_l = sum_{k>l} dL/dU_k
-  double* gk = w.gknot + (int64_t)v.t0 + (int64_t)c * KNOT_PAD;
-  double suf = 0.0, next = gk[v.m];
-  for (int l = v.m - 1; l >= 0; --l) {
-    suf += next;
-    next = gk[l];
-    gk[l] = suf;
+  if (!ok) {
+    for (int t = lane; t < v.nt; t += 64) gt[t] = 0.0f;
+    return;
   }
+  double* gk = w.gknot + (int64_t)v.t0 + (int64_t)c * KNOT_PAD;
+  double carry = 0.0;  // sum of dL/dU_k above the current chunk
+  for (int b = (v.m / 64) * 64; b >= 0; b -= 64) {
+    const int l = b + lane;
+    const double x = l <= v.m ? gk[l] : 0.0;
+    double incl = x;  // sum over k >= l inside the chunk
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double o = __shfl_down(incl, off);
+      if (lane + off < 64) incl += o;
+    }
+    double excl = __shfl_down(incl, 1);  // sum over k > l inside the chunk
+    if (lane == 63) excl = 0.0;
+    const double total = __shfl(incl, 0);
+    if (l < v.m) gk[l] = excl + carry;
+    carry += total;
+  }
+  __syncthreads();
   if (!v.closed()) {
-    for (int t = 0; t < v.nt; ++t) gt[t] = (float)gk[v.p + t];
+    for (int t = lane; t < v.nt; t += 64) gt[t] = (float)gk[v.p + t];
   } else {
-    for (int t = 0; t < v.nt; ++t) {
+    for (int t = lane; t < v.nt; t += 64) {
       double acc = 0.0;
       for (int l = t + v.p - v.nt; l < v.m; l += v.nt)
         if (l >= 0) acc += gk[l];
@@ -492,7 +523,8 @@ hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g) {
                        *L.cv, L.w, L.bf->plan, L.bf->counters);
   }
   Phase ph(L, NSPLAT_T_FOLD);
-  hipLaunchKernelGGL(k_fold, dim3(grid_for(L.cv->n_curves, 64, 1 << 20)), dim3(64), 0, L.stream, *L.cv, L.w, *g);
+  if (L.cv->n_curves > 0)
+    hipLaunchKernelGGL(k_fold, dim3(L.cv->n_curves), dim3(64), 0, L.stream, *L.cv, L.w, *g);
   return hipGetLastError();
 }
 
