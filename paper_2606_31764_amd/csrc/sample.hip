@@ -408,8 +408,18 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       r.sigma = (float)(pt[2] / (double)pr.rho);  // Eq. 5
       r.opacity = (float)o;
     } else {
-      const int nx = row[P_NX];
-      const int iy = local / nx, ix = local - iy * nx;
+      // Lanes take the window in bands of 8 rows, column by column inside a
+      // band, so that a wavefront covers an 8 x 8 block of lattice points
+      // (nearby points visit the same boundary chunks); each point still
+      // lands at its row-major place g = goff + iy nx + ix.
+      const int nx = row[P_NX], ny = row[P_NY];
+      const int band = local / (8 * nx);
+      const int rows = min(8, ny - 8 * band);
+      const int i = local - band * 8 * nx;
+      const int ix = i / rows, iy = 8 * band + (i - (i / rows) * rows);
+      const int lin = iy * nx + ix;
+      const int64_t gp = (int64_t)w.goff[c] + lin;
+      r.local = lin;
       const double h = (double)read_h(pr);
       const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
       const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
@@ -422,7 +432,11 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       r.my = qy;
       r.sigma = (float)((double)pr.eta * h / (double)pr.rho);  // Eq. 6
       r.opacity = (float)(o * (1.0 / (1.0 + exp(-z))));        // Eq. 7
-      w.aux[g] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
+      if (gp < G) {  // a capped (overflowing) emission may map past the capacity
+        w.aux[gp] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
+        out[gp] = r;
+      }
+      continue;
     }
     out[g] = r;
   }
