@@ -71,7 +71,9 @@ __device__ inline void load_entry(const int32_t* __restrict__ idx, const Gauss* 
 
 // Tile-local centre (relative to the tile's first pixel centre), squared
 // support radius, exp2 coefficient -log2(e) / (2 sigma^2), and whether the
-// support square meets the quadrant (a conservative test).
+// support disc reaches the rectangle of the quadrant's pixel centres, with
+// the radius enlarged by a relative 1e-4 so that the test is conservative
+// under FP32 rounding.
 template <int TILE>
 __device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, float ks, int quad, float4* geo) {
   using Cfg = TileCfg<TILE>;
@@ -82,7 +84,9 @@ __device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, floa
   const float rc = rr * 1.0001f + 1e-4f;
   const float qx0 = (float)((quad & 1) * Cfg::SUB), qy0 = (float)((quad >> 1) * Cfg::SUB);
   const float qx1 = qx0 + (float)(Cfg::SUB - 1), qy1 = qy0 + (float)(Cfg::SUB - 1);
-  return !((cx + rc < qx0) || (cx - rc > qx1) || (cy + rc < qy0) || (cy - rc > qy1));
+  const float dx = fmaxf(fmaxf(qx0 - cx, cx - qx1), 0.0f);
+  const float dy = fmaxf(fmaxf(qy0 - cy, cy - qy1), 0.0f);
+  return dx * dx + dy * dy <= rc * rc;
 }
 
 __device__ inline uint64_t lanes_below() {
