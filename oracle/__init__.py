@@ -1,8 +1,10 @@
 """TEST INFRASTRUCTURE ONLY: the FP64 CPU oracle of the NURBS Splatting render path.
 
 A plain, slow, brute-force reference (``nsplat_oracle.cpp``) that follows the
-paper step by step (Sec. 3.1-3.4, Eq. 1-9, Suppl. S2 Eq. S1-S3, Eq. 14) and
-composites every Gaussian at every pixel.  Only ``tests/``, the smoke check and
+paper step by step (Sec. 3.1-3.4, Eq. 1-9, Suppl. S2 Eq. S1-S3, Eq. 14, and the
+regularisers of Sec. 3.5, Eq. 11-12) and composites every Gaussian at every
+pixel; the optimiser step (Adam with the cosine learning-rate decay and the
+clamps of the supplementary settings) is written out in numpy below.  Only ``tests/``, the smoke check and
 the CPU-baseline leg of the benchmark may import it.  It shares no code with
 the GPU library and the GPU library never calls it.
 
@@ -60,6 +62,11 @@ class _Params(ctypes.Structure):
         ("kappa", ctypes.c_int32)]
 
 
+class _Reg(ctypes.Structure):
+    _fields_ = [("bbox_weight", ctypes.c_double), ("bbox_kind", ctypes.c_int32), ("bbox", ctypes.c_void_p),
+                ("deriv_weight", ctypes.c_double), ("deriv_order", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -82,6 +89,9 @@ def lib():
             "or_sdf": (i32, [i32, vp, dbl, dbl, vp]),
             "or_anneal": (dbl, [dbl, dbl, dbl, dbl, dbl, dbl]),
             "or_num_threads": (i32, []),
+            "or_reg_loss": (dbl, [vp, vp, vp, vp, vp, i64, vp, vp]),
+            "or_reg_grad_full": (dbl, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "or_curve_derivs": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, i32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -295,6 +305,82 @@ def anneal(t, T, hmax, hmin, tb, te):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+# --- geometric regularisers (Sec. 3.5) and the optimiser step ------------------------
+
+def _reg(bbox_weight=0.0, bbox_kind=0, bbox=None, deriv_weight=0.0, deriv_order=3):
+    bb = None if bbox is None else np.ascontiguousarray(bbox, np.float64).reshape(-1, 4)
+    return _Reg(float(bbox_weight), int(bbox_kind), _p(bb), float(deriv_weight), int(deriv_order)), bb
+
+
+def reg_loss_grad(batch, plan_rows, params=None, **reg):
+    """Value of lambda_bbox L_bbox (Eq. 12) + lambda_deriv L_deriv^r (Eq. 11, averaged over
+    each scene's curves) at the samples of the given plan, and its gradient w.r.t. every
+    key point, weight, width and interval (dict in the input layout)."""
+    B = _Batch(batch, params)
+    k = B.keep
+    rg, keep_bb = _reg(**reg)
+    out = dict(key_xy=np.zeros_like(k["key_xy"]), key_w=np.zeros_like(k["key_w"]),
+               key_s=np.zeros_like(k["key_s"]), tau=np.zeros_like(k["tau"]),
+               color=np.zeros_like(k["color"]), opacity=np.zeros_like(k["opacity"]))
+    total = lib().or_reg_grad_full(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), ctypes.byref(rg),
+                                   *[_p(out[n]) for n in ("key_xy", "key_w", "key_s", "tau")])
+    del keep_bb
+    return float(total), out
+
+
+def reg_loss(batch, plan_rows, params=None, **reg):
+    """Value only (no gradient seeds)."""
+    B = _Batch(batch, params)
+    rg, keep_bb = _reg(**reg)
+    v = lib().or_reg_loss(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), ctypes.byref(rg), 0,
+                          None, None)
+    del keep_bb
+    return float(v)
+
+
+def curve_derivs(p, closed, key_xy, key_w, key_s, tau, t, r):
+    """u-derivatives of order 0..r of (x, y) at u = a + t (b - a): array [len(t), r + 1, 2]."""
+    kx = np.ascontiguousarray(key_xy, np.float64).reshape(-1, 2)
+    kw = np.ascontiguousarray(key_w, np.float64)
+    ks = np.ascontiguousarray(key_s, np.float64)
+    tu = np.ascontiguousarray(tau, np.float64)
+    t = np.ascontiguousarray(np.atleast_1d(t), np.float64)
+    out = np.zeros((len(t), r + 1, 2))
+    lib().or_curve_derivs(p, int(closed), len(kx), len(tu), _p(kx), _p(kw), _p(ks), _p(tu), len(t), _p(t),
+                          int(r), _p(out))
+    return out
+
+
+GROUPS = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+
+
+def cosine_lr(lr0, t, total, final_ratio):
+    """Cosine decay from lr0 at t = 0 to final_ratio * lr0 at t = total (held after)."""
+    x = min(max(t / total, 0.0), 1.0)
+    lo = final_ratio * lr0
+    return lo + (lr0 - lo) * 0.5 * (1.0 + np.cos(np.pi * x))
+
+
+def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, total=1000, final_ratio=0.1,
+              w_range=(0.01, 10.0), tau_range=(0.0, 2.0)):
+    """One Adam step (Kingma & Ba, Alg. 1; eps added to the bias-corrected root)
+    on every parameter group, at step t >= 1 with the learning rate of group
+    g = cosine_lr(lr[g], t - 1, total, final_ratio), then the clamps of the
+    supplementary settings (rational weights to w_range, knot intervals to
+    tau_range).  Updates params, m, v in place (FP64)."""
+    for i, g in enumerate(GROUPS):
+        x, d = params[g], grads[g]
+        m[g][...] = beta1 * m[g] + (1.0 - beta1) * d
+        v[g][...] = beta2 * v[g] + (1.0 - beta2) * d * d
+        mh = m[g] / (1.0 - beta1 ** t)
+        vh = v[g] / (1.0 - beta2 ** t)
+        x -= cosine_lr(lr[i], t - 1, total, final_ratio) * mh / (np.sqrt(vh) + eps)
+        if g == "key_w":
+            np.clip(x, w_range[0], w_range[1], out=x)
+        if g == "tau":
+            np.clip(x, tau_range[0], tau_range[1], out=x)
 
 
 def timed(fn, *a, **kw):

@@ -22,6 +22,9 @@
 //   Eq. 8, 9     front-to-back alpha compositing of EVERY Gaussian at EVERY
 //                pixel, residual transmittance onto the background
 //   Eq. 14       grid-step annealing schedule
+//   Sec. 3.5     the geometric regularisers: derivative (fairing) loss,
+//                Eq. 11, from k-th basis derivatives (NURBS Book Eq. 2.9) and
+//                the rational Leibniz rule, and the bounding-box loss, Eq. 12
 // and the exact derivative of the image loss with respect to every curve
 // parameter: the compositing adjoint is written out per pixel; the map from
 // curve parameters to Gaussians is differentiated in forward mode with dual
@@ -99,6 +102,16 @@ typedef struct {
   double cutoff;     // support radius in sigmas (<= 0: none)
   int32_t kappa;     // extra copies of each open-curve endpoint
 } or_params;
+
+// Geometric regularisers of Sec. 3.5, evaluated at the parameters u_j of the
+// curve's own samples (contour samples of a stroke, boundary points of a fill).
+typedef struct {
+  double bbox_weight;    // lambda of Eq. 12 (0: off)
+  int32_t bbox_kind;     // penalty phi: 0 ReLU, 1 softplus
+  const double* bbox;    // [S][4] = {x_min, y_min, x_max, y_max}, or NULL for [0, W] x [0, H]
+  double deriv_weight;   // lambda of Eq. 11 (0: off)
+  int32_t deriv_order;   // r
+} or_reg;
 
 }  // extern "C"
 
@@ -486,6 +499,116 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Sec. 3.5: geometric regularisers.
+// ---------------------------------------------------------------------------
+
+// k-th u-derivative of N_{i,d} (The NURBS Book, Eq. 2.9):
+//   N^(k)_{i,d} = d (N^(k-1)_{i,d-1} / (u_{i+d} - u_i) - N^(k-1)_{i+1,d-1} / (u_{i+d+1} - u_{i+1})),
+// with 0/0 := 0 and N^(0)_{i,d} = N_{i,d} (so the derivatives are those of the
+// span chosen by find_span: one-sided at knots).
+template <class T>
+T basis_deriv(const std::vector<T>& U, int i, int d, int k, const T& u, int span) {
+  if (k == 0) return basis(U, i, d, u, span);
+  if (d == 0) return T(0.0);
+  T a(0.0), b(0.0);
+  const T den1 = U[i + d] - U[i];
+  if (val(den1) != 0.0) a = basis_deriv(U, i, d - 1, k - 1, u, span) / den1;
+  const T den2 = U[i + d + 1] - U[i + 1];
+  if (val(den2) != 0.0) b = basis_deriv(U, i + 1, d - 1, k - 1, u, span) / den2;
+  return T((double)d) * (a - b);
+}
+
+// u-derivatives C^(k)(u), k = 0..r, of the planar rational curve (x, y):
+// A^(k) = sum_i N^(k)_{i,p} w_i P_i and W^(k) = sum_i N^(k)_{i,p} w_i, then the
+// rational Leibniz rule (The NURBS Book, Eq. 4.8)
+//   C^(k) = (A^(k) - sum_{i=1..k} binom(k, i) W^(i) C^(k-i)) / W.
+template <class T>
+void curve_derivs(const Curve<T>& cv, const T& u, int span, int r, std::vector<T>& Dx, std::vector<T>& Dy) {
+  std::vector<T> Ax(r + 1, T(0.0)), Ay(r + 1, T(0.0)), Wk(r + 1, T(0.0));
+  for (int k = 0; k <= r; ++k)
+    for (int i = span - cv.p; i <= span; ++i) {
+      const T nw = basis_deriv(cv.U, i, cv.p, k, u, span) * cv.W[i];
+      Ax[k] += nw * cv.X[i];
+      Ay[k] += nw * cv.Y[i];
+      Wk[k] += nw;
+    }
+  Dx.assign(r + 1, T(0.0));
+  Dy.assign(r + 1, T(0.0));
+  for (int k = 0; k <= r; ++k) {
+    T vx = Ax[k], vy = Ay[k];
+    double bin = 1.0;  // binom(k, i), built up over i
+    for (int i = 1; i <= k; ++i) {
+      bin = bin * (double)(k - i + 1) / (double)i;
+      vx = vx - T(bin) * Wk[i] * Dx[k - i];
+      vy = vy - T(bin) * Wk[i] * Dy[k - i];
+    }
+    Dx[k] = vx / Wk[0];
+    Dy[k] = vy / Wk[0];
+  }
+}
+
+// Penalty of Eq. 12: ReLU (kind 0) or softplus (kind 1).
+inline double penalty(double x, int kind) {
+  if (kind == 0) return x > 0.0 ? x : 0.0;
+  return x > 0.0 ? x + std::log1p(std::exp(-x)) : std::log1p(std::exp(x));
+}
+inline Dual penalty(const Dual& x, int kind) {
+  if (kind == 0) return x.v > 0.0 ? x : Dual(0.0, 0.0);
+  return Dual(penalty(x.v, 1), x.d / (1.0 + std::exp(-x.v)));
+}
+
+// Regularisers of curve c at the parameters of its own samples:
+//   lambda_bbox * sum_j [phi(b_min - C(u_j)) + phi(C(u_j) - b_max)] (both axes)
+// + lambda_deriv / n_scene * (1 / (u_max - u_min)) int ||C^(r)||^2 du,
+// the integral by the trapezoid rule on the open samples (both ends
+// included) or the periodic rectangle rule on closed ones, and n_scene the
+// number of curves in the curve's scene (the average over curves).
+template <class T>
+T curve_reg(const or_curves* in, const or_scenes* sc, const int32_t* row, int c, const or_reg* rg,
+            double n_scene, int seed_kind, int seed_index) {
+  const int ns = row[P_NSAMP];
+  if (ns <= 0) return T(0.0);
+  const Curve<T> cv = build_curve<T>(in, c, seed_kind, seed_index);
+  const int s = in->scene[c];
+  double b0x = 0.0, b0y = 0.0, b1x = sc->hw[2 * s + 1], b1y = sc->hw[2 * s];
+  if (rg->bbox) {
+    b0x = rg->bbox[4 * s]; b0y = rg->bbox[4 * s + 1]; b1x = rg->bbox[4 * s + 2]; b1y = rg->bbox[4 * s + 3];
+  }
+  T loss(0.0);
+  std::vector<T> Dx, Dy;
+  for (int j = 0; j < ns; ++j) {
+    const T u = sample_u(cv, j, ns, cv.closed);
+    const int span = find_span(cv, val(u));
+    if (rg->bbox_weight != 0.0) {
+      T pt[3];
+      curve_point(cv, u, span, pt);
+      const T pen = penalty(T(b0x) - pt[0], rg->bbox_kind) + penalty(pt[0] - T(b1x), rg->bbox_kind) +
+                    penalty(T(b0y) - pt[1], rg->bbox_kind) + penalty(pt[1] - T(b1y), rg->bbox_kind);
+      loss += T(rg->bbox_weight) * pen;
+    }
+    if (rg->deriv_weight != 0.0) {
+      double wq;
+      if (cv.closed) wq = 1.0 / ns;
+      else wq = (j == 0 || j == ns - 1) ? 0.5 / (ns - 1) : 1.0 / (ns - 1);
+      curve_derivs(cv, u, span, rg->deriv_order, Dx, Dy);
+      const int r = rg->deriv_order;
+      loss += T(rg->deriv_weight / n_scene * wq) * (Dx[r] * Dx[r] + Dy[r] * Dy[r]);
+    }
+  }
+  return loss;
+}
+
+std::vector<double> curves_per_scene(const or_curves* in, const or_scenes* sc) {
+  std::vector<double> n(sc->n_scenes, 0.0);
+  for (int c = 0; c < in->n_curves; ++c) n[in->scene[c]] += 1.0;
+  return n;
+}
+
+}  // namespace
+
 extern "C" {
 
 // Plan: per curve {count, n_samples, ix0, iy0, nx, ny, g_offset, near-int flag}
@@ -741,6 +864,52 @@ int or_param_grad_full(const or_curves* in, const or_scenes* sc, const or_params
   return 0;
 }
 
+// Regularisers (Sec. 3.5, Eq. 11 and Eq. 12) summed over all curves for the
+// given plan, and their derivative for each seed [n][3] = (curve, kind,
+// index); colour and opacity do not enter them.
+double or_reg_loss(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
+                   const or_reg* rg, int64_t n, const int32_t* seeds, double* grad) {
+  (void)pr;
+  const std::vector<double> nsc = curves_per_scene(in, sc);
+  double total = 0.0;
+  for (int c = 0; c < in->n_curves; ++c)
+    total += curve_reg<double>(in, sc, plan + P_STRIDE * c, c, rg, nsc[in->scene[c]], S_NONE, 0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    const int c = seeds[3 * i], kind = seeds[3 * i + 1], idx = seeds[3 * i + 2];
+    if (kind < S_KEY_X || kind > S_TAU) {
+      grad[i] = 0.0;
+      continue;
+    }
+    grad[i] = curve_reg<Dual>(in, sc, plan + P_STRIDE * c, c, rg, nsc[in->scene[c]], kind, idx).d;
+  }
+  return total;
+}
+
+// The regularisers' value and every gradient component in the layout of the
+// inputs (zero for colour and opacity).
+double or_reg_grad_full(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
+                        const or_reg* rg, double* g_key_xy, double* g_key_w, double* g_key_s, double* g_tau) {
+  std::vector<int32_t> seeds;
+  std::vector<double*> dst;
+  for (int c = 0; c < in->n_curves; ++c) {
+    const int k0 = in->key_off[c], nk = in->key_off[c + 1] - k0;
+    const int t0 = in->tau_off[c], nt = in->tau_off[c + 1] - t0;
+    for (int k = 0; k < nk; ++k) {
+      seeds.insert(seeds.end(), {c, S_KEY_X, k}); dst.push_back(g_key_xy + 2 * (k0 + k));
+      seeds.insert(seeds.end(), {c, S_KEY_Y, k}); dst.push_back(g_key_xy + 2 * (k0 + k) + 1);
+      seeds.insert(seeds.end(), {c, S_KEY_W, k}); dst.push_back(g_key_w + k0 + k);
+      seeds.insert(seeds.end(), {c, S_KEY_S, k}); dst.push_back(g_key_s + k0 + k);
+    }
+    for (int t = 0; t < nt; ++t) { seeds.insert(seeds.end(), {c, S_TAU, t}); dst.push_back(g_tau + t0 + t); }
+  }
+  const int64_t n = (int64_t)dst.size();
+  std::vector<double> out(n);
+  const double total = or_reg_loss(in, sc, pr, plan, rg, n, seeds.data(), out.data());
+  for (int64_t i = 0; i < n; ++i) *dst[i] = out[i];
+  return total;
+}
+
 // ---------------------------------------------------------------------------
 // Single-curve geometry, for the closed-form tests.
 // ---------------------------------------------------------------------------
@@ -811,6 +980,27 @@ double or_arc_length(int p, int closed, int nk, int nt, const double* key_xy, co
   double dummy[4] = {0, 0, 0, 0};
   const or_curves c = one_curve(p, closed, nk, nt, key_xy, key_w, key_s, tau, meta, dummy);
   return arc_length(build_curve<double>(&c, 0, S_NONE, 0), n_L);
+}
+
+// u-derivatives of order 0..r of the planar curve at u = a + t (b - a):
+// out [n][r + 1][2].
+int or_curve_derivs(int p, int closed, int nk, int nt, const double* key_xy, const double* key_w,
+                    const double* key_s, const double* tau, int n, const double* t, int r, double* out) {
+  int32_t meta[6];
+  double dummy[4] = {0, 0, 0, 0};
+  const or_curves c = one_curve(p, closed, nk, nt, key_xy, key_w, key_s, tau, meta, dummy);
+  const Curve<double> cv = build_curve<double>(&c, 0, S_NONE, 0);
+  const double a = dom_lo(cv), b = dom_hi(cv);
+  std::vector<double> Dx, Dy;
+  for (int i = 0; i < n; ++i) {
+    const double u = t[i] >= 1.0 ? b : a + t[i] * (b - a);
+    curve_derivs(cv, u, find_span(cv, u), r, Dx, Dy);
+    for (int k = 0; k <= r; ++k) {
+      out[2 * ((r + 1) * i + k)] = Dx[k];
+      out[2 * ((r + 1) * i + k) + 1] = Dy[k];
+    }
+  }
+  return 0;
 }
 
 // Signed distance at q to the closed polyline b[n][2]: out = (d, wn, sdf).
