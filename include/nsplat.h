@@ -237,6 +237,75 @@ int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_s
                     const float* T_final, const int32_t* n_last, const nsplat_grads* grads,
                     int persistent, void* stream);
 
+/* Geometric regularisers of Sec. 3.5 added to the loss by nsplat_backward_reg.
+ * Both are evaluated at the parameters u_j of each curve's own samples: the M
+ * contour samples of a stroke (its endpoint copies counted once) and the N_b
+ * boundary points of a fill.
+ *   Bounding box (Eq. 12): bbox_weight * sum_j sum_{x,y} [phi(b_min - C(u_j))
+ *     + phi(C(u_j) - b_max)], phi = ReLU (bbox_kind 0) or softplus (1), the box
+ *     of each scene from `bbox` (dev FP32 [S][4] = {x_min, y_min, x_max, y_max})
+ *     or, when bbox is NULL, the canvas [0, W] x [0, H].
+ *   Derivative (Eq. 11): deriv_weight / n_scene * the domain average of
+ *     ||C^(r)(u)||^2 for the planar curve (x, y), r = deriv_order in 1..3,
+ *     taken with the trapezoid rule on an open curve's samples (both ends
+ *     included) or the rectangle rule on a closed curve's, n_scene being the
+ *     number of curves of the curve's scene (the loss averages over curves).
+ *     C^(r) comes from the span's derivative control points (differences of
+ *     the homogeneous control points over knot spans) evaluated with the
+ *     degree p - k basis, and the rational Leibniz rule.
+ * A weight of 0 switches a term off.  `loss` (dev FP32 [2], may be NULL)
+ * receives the two terms' values (added to what it holds). */
+typedef struct {
+  float bbox_weight;
+  int32_t bbox_kind;
+  const float* bbox;
+  float deriv_weight;
+  int32_t deriv_order;
+  float* loss;
+} nsplat_reg;
+
+/* nsplat_backward plus the gradients of the regularisers in `reg` (NULL: none;
+ * then identical to nsplat_backward).  Needs the same state (nsplat_sample,
+ * nsplat_bin and nsplat_forward of this step).  Errors as nsplat_backward, and
+ * NSPLAT_EINVAL for a deriv_order outside 1..3 or a bbox_kind other than 0, 1. */
+int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                        const nsplat_params* params, const nsplat_buffers* bufs, const float* dL_dimage,
+                        const float* T_final, const int32_t* n_last, const nsplat_reg* reg,
+                        const nsplat_grads* grads, int persistent, void* stream);
+
+/* Learnable parameters, writable (dev FP32; the arrays the curves point to). */
+typedef struct {
+  int32_t n_curves, channels, n_keys, n_taus;
+  float* key_xy;   /* [K][2] */
+  float* key_w;    /* [K]    */
+  float* key_s;    /* [K]    */
+  float* tau;      /* [T]    */
+  float* color;    /* [N][C] */
+  float* opacity;  /* [N]    */
+} nsplat_values;
+
+/* Optimiser settings of the supplementary material: Adam with per-group
+ * learning rates (order key_xy, key_w, key_s, tau, color, opacity), each
+ * decayed by a cosine from lr to final_ratio * lr over total_steps steps, and
+ * the clamps of the rational weights to [w_min, w_max] and of the knot
+ * intervals to [tau_min, tau_max] after every step. */
+typedef struct {
+  float lr[6];
+  float beta1, beta2, eps;
+  float final_ratio;
+  int32_t total_steps;
+  float w_min, w_max, tau_min, tau_max;
+} nsplat_adam;
+
+/* One Adam step (Kingma & Ba, Alg. 1, eps added to the bias-corrected root)
+ * on every parameter, in place, at step t = *step_dev + 1 (dev int32: steps
+ * taken so far; incremented), with learning rate
+ * lr_t = lr (final_ratio + (1 - final_ratio) (1 + cos(pi min(1, (t - 1) / total_steps))) / 2).
+ * m and v (dev FP32, each 4 K + T + N (C + 1) values, zero before the first
+ * step) hold the moments, group after group in the order above. */
+int nsplat_adam_step(nsplat_ctx* ctx, const nsplat_adam* cfg, const nsplat_values* params,
+                     const nsplat_grads* grads, float* m, float* v, int32_t* step_dev, void* stream);
+
 /* Eq. 14: writes h(t) = h_max + (h_min - h_max) (1 + cos(pi (1 - phi))) / 2,
  * phi = clamp((t / T - t_b) / (t_e - t_b), 0, 1), to h_dev (dev float), with t
  * read from step_dev (dev int32) when it is non-NULL (and then incremented),

@@ -50,6 +50,24 @@ class Grads(ctypes.Structure):
     _fields_ = [(n, vp) for n in ("key_xy", "key_w", "key_s", "tau", "color", "opacity")]
 
 
+class Reg(ctypes.Structure):
+    _fields_ = [("bbox_weight", ctypes.c_float), ("bbox_kind", ctypes.c_int32), ("bbox", vp),
+                ("deriv_weight", ctypes.c_float), ("deriv_order", ctypes.c_int32), ("loss", vp)]
+
+
+class Values(ctypes.Structure):
+    _fields_ = [("n_curves", ctypes.c_int32), ("channels", ctypes.c_int32), ("n_keys", ctypes.c_int32),
+                ("n_taus", ctypes.c_int32)] + [(n, vp) for n in ("key_xy", "key_w", "key_s", "tau", "color",
+                                                                   "opacity")]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("final_ratio", ctypes.c_float), ("total_steps", ctypes.c_int32),
+                ("w_min", ctypes.c_float), ("w_max", ctypes.c_float), ("tau_min", ctypes.c_float),
+                ("tau_max", ctypes.c_float)]
+
+
 _SIGS = {
     "nsplat_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
     "nsplat_destroy": (ctypes.c_int, [vp]),
@@ -60,6 +78,8 @@ _SIGS = {
     "nsplat_bin": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
     "nsplat_forward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
     "nsplat_backward": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
+    "nsplat_backward_reg": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
+    "nsplat_adam_step": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "nsplat_anneal_h": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, vp]),
     "nsplat_l2_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, vp]),

@@ -15,6 +15,10 @@
 //   k_adj_boundary  one lane per boundary point: the same point adjoint.
 //   Both reduce within the wavefront by (curve, span) segment before the FP64
 //   global atomics.
+//   k_reg_stroke,   the geometric regularisers of Sec. 3.5 at stroke samples
+//   k_reg_boundary  and fill boundary points: bounding-box penalty (Eq. 12)
+//                   into the centre / boundary-point adjoints, derivative
+//                   loss (Eq. 11) by reverse mode straight to the curve.
 //   k_fold          one wavefront per curve: control points -> key points
 //                   (the closed wrap), knots -> intervals (suffix sums of the
 //                   cumulative sum) -> tau, FP32 outputs.
@@ -490,6 +494,461 @@ __global__ void k_zero_dev(float* p, const int32_t* count, int64_t mult, int64_t
     p[i] = 0.0f;
 }
 
+// ---------------------------------------------------------------------------
+// Geometric regularisers (Sec. 3.5): derivative loss (Eq. 11) and
+// bounding-box loss (Eq. 12), at the parameters of each curve's own samples.
+// ---------------------------------------------------------------------------
+
+constexpr int MAXR = 3;  // highest derivative order of the derivative loss
+
+// Value scale * ||C^(r)(u)||^2 of the planar curve at u on `span` and its
+// reverse-mode adjoint.  Forward: the span's homogeneous control points
+// H_j = (w x, w y, w); derivative control points
+//   PK_k[j] = (p - k + 1) (PK_{k-1}[j+1] - PK_{k-1}[j]) / (U[span+j+1] - U[span-p+j+k])
+// (every denominator spans the non-empty span, so none vanishes);
+// S^(k)(u) = sum_j N_{span-p+k+j, p-k}(u) PK_k[j], the homogeneous k-th
+// derivative; and the rational Leibniz rule
+//   C^(k) = (A^(k) - sum_{i=1..k} binom(k, i) W^(i) C^(k-i)) / W, (A, W) = S.
+// Reverse: the same steps backwards, with the adjoint of the degree p - k
+// basis functions entering the Cox-de Boor triangle at its level p - k.
+__device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView& v, double u, int span, int r,
+                                       double scale, PtAdj& out) {
+  const double* U = v.U;
+  const int p = v.p;
+  const int R = r < p ? r : p;
+  double tri[TRI];
+  double N[MAXP + 1], left[MAXP + 1], right[MAXP + 1];
+  N[0] = 1.0;
+  tri[0] = 1.0;
+#pragma unroll
+  for (int d = 1; d <= MAXP; ++d) {
+    if (d > p) break;
+    left[d] = u - U[span + 1 - d];
+    right[d] = U[span + d] - u;
+    double saved = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      const double temp = N[q] / (right[q + 1] + left[d - q]);
+      N[q] = saved + right[q + 1] * temp;
+      saved = left[d - q] * temp;
+    }
+    N[d] = saved;
+#pragma unroll
+    for (int q = 0; q <= d; ++q) tri[d * (d + 1) / 2 + q] = N[q];
+  }
+  double X[MAXP + 1], Y[MAXP + 1], Wt[MAXP + 1];
+  double PK[MAXR + 1][MAXP + 1][3];
+#pragma unroll
+  for (int j = 0; j <= MAXP; ++j) {
+    X[j] = Y[j] = Wt[j] = 0.0;
+    if (j > p) continue;
+    const int k = v.k0 + v.key_of_cp(span - p + j);
+    Wt[j] = (double)cv.key_w[k];
+    X[j] = (double)cv.key_xy[2 * k];
+    Y[j] = (double)cv.key_xy[2 * k + 1];
+    PK[0][j][0] = Wt[j] * X[j];
+    PK[0][j][1] = Wt[j] * Y[j];
+    PK[0][j][2] = Wt[j];
+  }
+#pragma unroll
+  for (int k = 1; k <= MAXR; ++k) {
+    if (k > R) break;
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      if (j > p - k) break;
+      const double c = (double)(p - k + 1) / (U[span + j + 1] - U[span - p + j + k]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) PK[k][j][q] = c * (PK[k - 1][j + 1][q] - PK[k - 1][j][q]);
+    }
+  }
+  // (register arrays are indexed with compile-time indices only: the degree
+  // d = p - k is matched by an unrolled loop instead of computed)
+  double S[MAXR + 1][3];
+#pragma unroll
+  for (int k = 0; k <= MAXR; ++k) {
+    S[k][0] = S[k][1] = S[k][2] = 0.0;
+    if (k > R) continue;
+#pragma unroll
+    for (int d = 0; d <= MAXP; ++d) {
+      if (d != p - k) continue;
+#pragma unroll
+      for (int j = 0; j <= d; ++j) {
+        const double n = tri[d * (d + 1) / 2 + j];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S[k][q] += n * PK[k][j][q];
+      }
+    }
+  }
+  const double binom[MAXR + 1][MAXR + 1] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+  const double W0 = S[0][2];
+  double Cx[MAXR + 1], Cy[MAXR + 1];
+#pragma unroll
+  for (int k = 0; k <= MAXR; ++k) {
+    Cx[k] = Cy[k] = 0.0;
+    if (k > r) continue;
+    double ax = S[k][0], ay = S[k][1];  // zero for k > R
+#pragma unroll
+    for (int i = 1; i <= MAXR; ++i) {
+      if (i > k) break;
+      ax -= binom[k][i] * S[i][2] * Cx[k - i];
+      ay -= binom[k][i] * S[i][2] * Cy[k - i];
+    }
+    Cx[k] = ax / W0;
+    Cy[k] = ay / W0;
+  }
+  const double value = scale * (Cx[r] * Cx[r] + Cy[r] * Cy[r]);
+  // reverse: Leibniz rule
+  double dCx[MAXR + 1], dCy[MAXR + 1], dS[MAXR + 1][3];
+#pragma unroll
+  for (int k = 0; k <= MAXR; ++k) {
+    dCx[k] = dCy[k] = 0.0;
+    dS[k][0] = dS[k][1] = dS[k][2] = 0.0;
+  }
+  dCx[r] = 2.0 * scale * Cx[r];
+  dCy[r] = 2.0 * scale * Cy[r];
+#pragma unroll
+  for (int k = MAXR; k >= 0; --k) {
+    if (k > r) continue;
+    const double gx = dCx[k] / W0, gy = dCy[k] / W0;
+    dS[k][0] += gx;
+    dS[k][1] += gy;
+#pragma unroll
+    for (int i = 1; i <= MAXR; ++i) {
+      if (i > k) break;
+      dS[i][2] -= binom[k][i] * (gx * Cx[k - i] + gy * Cy[k - i]);
+      dCx[k - i] -= binom[k][i] * S[i][2] * gx;
+      dCy[k - i] -= binom[k][i] * S[i][2] * gy;
+    }
+    dS[0][2] -= gx * Cx[k] + gy * Cy[k];
+  }
+  // reverse: S^(k) = sum_j N_{p-k}[j] PK_k[j]
+  double dPK[MAXR + 1][MAXP + 1][3], dN[MAXR + 1][MAXP + 1];
+#pragma unroll
+  for (int k = 0; k <= MAXR; ++k)
+#pragma unroll
+    for (int j = 0; j <= MAXP; ++j) {
+      dN[k][j] = 0.0;
+      dPK[k][j][0] = dPK[k][j][1] = dPK[k][j][2] = 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k <= MAXR; ++k) {
+    if (k > R) continue;
+#pragma unroll
+    for (int d = 0; d <= MAXP; ++d) {
+      if (d != p - k) continue;
+#pragma unroll
+      for (int j = 0; j <= d; ++j) {
+        const double n = tri[d * (d + 1) / 2 + j];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dPK[k][j][q] = n * dS[k][q];
+        dN[k][j] = dS[k][0] * PK[k][j][0] + dS[k][1] * PK[k][j][1] + dS[k][2] * PK[k][j][2];
+      }
+    }
+  }
+  // reverse: derivative control points; knot slot s <-> knot index span - MAXP + 1 + s
+#pragma unroll
+  for (int k = 0; k < 2 * MAXP; ++k) out.knot[k] = 0.0;
+#pragma unroll
+  for (int k = MAXR; k >= 1; --k) {
+    if (k > R) continue;
+#pragma unroll
+    for (int j = 0; j < MAXP; ++j) {
+      if (j > p - k) break;
+      const int hi = span + j + 1, lo = span - p + j + k;
+      const double D = U[hi] - U[lo];
+      const double c = (double)(p - k + 1) / D;
+      double dD = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        dPK[k - 1][j + 1][q] += c * dPK[k][j][q];
+        dPK[k - 1][j][q] -= c * dPK[k][j][q];
+        dD -= dPK[k][j][q] * PK[k][j][q];
+      }
+      dD /= D;
+      out.knot[j + MAXP] += dD;  // slot of knot hi = span + j + 1
+#pragma unroll
+      for (int sl = 0; sl < 2 * MAXP; ++sl)
+        if (sl == lo - span + MAXP - 1) out.knot[sl] -= dD;
+    }
+  }
+  // homogeneous control points -> (x, y, w); the width does not enter
+#pragma unroll
+  for (int j = 0; j <= MAXP; ++j) {
+    out.cp[j][0] = out.cp[j][1] = out.cp[j][2] = out.cp[j][3] = 0.0;
+    if (j > p) continue;
+    out.cp[j][0] = Wt[j] * dPK[0][j][0];
+    out.cp[j][1] = Wt[j] * dPK[0][j][1];
+    out.cp[j][2] = X[j] * dPK[0][j][0] + Y[j] * dPK[0][j][1] + dPK[0][j][2];
+  }
+  // reverse through the Cox-de Boor triangle (as point_adjoint), the degree
+  // p - k adjoint dN[k] joining at level p - k
+  double Nb[MAXP + 1];
+#pragma unroll
+  for (int q = 0; q <= MAXP; ++q) Nb[q] = dN[0][q];
+  double ub = 0.0;
+#pragma unroll
+  for (int d = MAXP; d >= 1; --d) {
+    if (d > p) continue;
+#pragma unroll
+    for (int k = 1; k <= MAXR; ++k)
+      if (k <= R && d == p - k) {
+#pragma unroll
+        for (int q = 0; q <= MAXP; ++q) Nb[q] += dN[k][q];
+      }
+    double Np[MAXP + 1];
+#pragma unroll
+    for (int q = 0; q <= MAXP; ++q) Np[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q <= d; ++q) {
+      const double nb = Nb[q];
+      const int i = span - d + q;
+      if (q >= 1) {
+        const double Ui = U[i], Uid = U[i + d];
+        const double D = Uid - Ui;
+        Np[q - 1] += nb * (u - Ui) / D;
+        const double g = nb * tri[(d - 1) * d / 2 + q - 1];
+        ub += g / D;
+        out.knot[MAXP - 1 - d + q] -= g * (Uid - u) / (D * D);
+        out.knot[MAXP - 1 + q] -= g * (u - Ui) / (D * D);
+      }
+      if (q <= d - 1) {
+        const double Ui1 = U[i + 1], Uid1 = U[i + d + 1];
+        const double D = Uid1 - Ui1;
+        Np[q] += nb * (Uid1 - u) / D;
+        const double g = nb * tri[(d - 1) * d / 2 + q];
+        ub -= g / D;
+        out.knot[MAXP + q] += g * (u - Ui1) / (D * D);
+        out.knot[MAXP - d + q] += g * (Uid1 - u) / (D * D);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q <= MAXP; ++q) Nb[q] = Np[q];
+  }
+  out.ubar = ub;
+  return value;
+}
+
+// Penalty of Eq. 12 and its derivative: ReLU (kind 0) or softplus (kind 1).
+__device__ inline double penalty(double x, int kind, double* d) {
+  if (kind == 0) {
+    *d = x > 0.0 ? 1.0 : 0.0;
+    return x > 0.0 ? x : 0.0;
+  }
+  *d = 1.0 / (1.0 + exp(-x));
+  return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x));
+}
+
+struct RegArgs {
+  double bbox_weight, deriv_weight;
+  int bbox_kind, deriv_order;
+  const float* bbox;
+  float* loss;
+};
+
+// The scene's box: the given one, or the canvas [0, W] x [0, H].
+__device__ inline void scene_box(const RegArgs& ra, const SceneTab* scenes, int s, double (&b)[4]) {
+  if (ra.bbox) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = (double)ra.bbox[4 * s + i];
+  } else {
+    b[0] = 0.0;
+    b[1] = 0.0;
+    b[2] = (double)scenes[s].W;
+    b[3] = (double)scenes[s].H;
+  }
+}
+
+// Bounding-box penalty of one point and its gradient.
+__device__ inline double box_penalty(const RegArgs& ra, const double (&b)[4], double x, double y, double* gx,
+                                     double* gy) {
+  double d0, d1, d2, d3;
+  const double v = penalty(b[0] - x, ra.bbox_kind, &d0) + penalty(x - b[2], ra.bbox_kind, &d1) +
+                   penalty(b[1] - y, ra.bbox_kind, &d2) + penalty(y - b[3], ra.bbox_kind, &d3);
+  *gx = ra.bbox_weight * (d1 - d0);
+  *gy = ra.bbox_weight * (d3 - d2);
+  return ra.bbox_weight * v;
+}
+
+// Number of curves of scene s (curves are grouped by scene in ascending order).
+__device__ inline int curves_in_scene(const nsplat_curves& cv, int s) {
+  int lo = 0, hi = cv.n_curves;  // first curve with scene >= s
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cv.scene[mid] < s) lo = mid + 1;
+    else hi = mid;
+  }
+  int a = lo;
+  hi = cv.n_curves;  // first curve with scene > s
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cv.scene[mid] <= s) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - a;
+}
+
+// Trapezoid (open) or rectangle (closed) weight of sample j of `count`.
+__device__ inline double quad_weight(int j, int count, bool closed) {
+  if (closed) return 1.0 / (double)count;
+  return (j == 0 || j == count - 1) ? 0.5 / (double)(count - 1) : 1.0 / (double)(count - 1);
+}
+
+// Block sum of two values into loss[0], loss[1] (one atomic each per block).
+__device__ inline void block_loss(double a, double b, float* loss) {
+  __shared__ double red[2][4];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  if (__lane_id() == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) {
+    const double ta = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double tb = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (ta != 0.0) unsafeAtomicAdd(loss, (float)ta);
+    if (tb != 0.0) unsafeAtomicAdd(loss + 1, (float)tb);
+  }
+}
+
+// Stroke samples (one lane per stroke Gaussian; endpoint copies skipped): the
+// box gradient joins the Gaussian's centre adjoint, the derivative loss goes
+// straight to the control points, knots and domain ends.
+__global__ __launch_bounds__(256) void k_reg_stroke(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
+                                                    const int32_t* counters, const Gauss* __restrict__ gs,
+                                                    int kappa) {
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const int lane = __lane_id();
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double lb = 0.0, ld = 0.0;
+  for (int64_t base = wave0; base < G; base += stride) {
+    const int64_t g = base + lane;
+    int64_t kspan = -1 - lane, kcur = -1 - lane;
+    double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    PtAdj pa;
+    int c = 0, span = 0;
+    CurveView v;
+    v.p = 0;
+    bool act = false;
+    if (g < G) {
+      const Gauss rec = gs[g];
+      c = rec.curve;
+      v = curve_view(cv, w.knots, c);
+      const int32_t* row = plan + (int64_t)P_STRIDE * c;
+      const int M = row[P_NSAMP];
+      const int j = v.closed() ? rec.local : rec.local - kappa;
+      if (!v.filled() && curve_valid(v) && j >= 0 && j < M) {
+        if (ra.bbox_weight != 0.0) {
+          double b[4], gx, gy;
+          scene_box(ra, w.scenes, cv.scene[c], b);
+          lb += box_penalty(ra, b, rec.mx, rec.my, &gx, &gy);
+          float* gg = w.ggrad + g * GG;
+          gg[0] += (float)gx;
+          gg[1] += (float)gy;
+        }
+        if (ra.deriv_weight != 0.0) {
+          act = true;
+          double dt;
+          const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), &dt);
+          span = find_span(v.U, v.p, v.m, u);
+          const double sc = ra.deriv_weight / (double)curves_in_scene(cv, cv.scene[c]) *
+                            quad_weight(j, M, v.closed());
+          ld += deriv_adjoint(cv, v, u, span, ra.deriv_order, sc, pa);
+          cur[4] = pa.ubar * (1.0 - dt);
+          cur[5] = pa.ubar * dt;
+          kspan = (int64_t)v.t0 + (int64_t)c * KNOT_PAD + span;
+          kcur = c;
+        }
+      }
+    }
+    if (!act) {
+#pragma unroll
+      for (int q = 0; q <= MAXP; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pa.cp[q][k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+    }
+    const bool any = __ballot(act) != 0ull;
+    accumulate_points(w, kspan, c, v, span, pa, any);
+    if (any) accumulate_curve(w, kcur, c, v, cur);
+  }
+  block_loss(lb, ld, ra.loss);
+}
+
+// Fill boundary samples (one lane per boundary point): the box gradient joins
+// the boundary-point adjoint, the derivative loss goes straight to the curve.
+__global__ __launch_bounds__(256) void k_reg_boundary(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
+                                                      const int32_t* counters) {
+  const int64_t NB = counters[NSPLAT_CNT_BOUND];
+  const int lane = __lane_id();
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int n = cv.n_curves;
+  double lb = 0.0, ld = 0.0;
+  for (int64_t base = wave0; base < NB; base += stride) {
+    const int64_t bi = base + lane;
+    int64_t kspan = -1 - lane, kcur = -1 - lane;
+    double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    PtAdj pa;
+    int c = 0, span = 0;
+    CurveView v;
+    v.p = 0;
+    bool act = false;
+    if (bi < NB) {
+      int lo = 0, hi = n - 1;  // the last c with boff <= bi
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (plan[(int64_t)P_STRIDE * mid + P_BOFF] <= bi) lo = mid;
+        else hi = mid - 1;
+      }
+      c = lo;
+      v = curve_view(cv, w.knots, c);
+      const int32_t* row = plan + (int64_t)P_STRIDE * c;
+      const int nb = row[P_NSAMP];
+      const int j = (int)(bi - row[P_BOFF]);
+      if (v.filled() && curve_valid(v) && j >= 0 && j < nb) {
+        if (ra.bbox_weight != 0.0) {
+          double b[4], gx, gy;
+          scene_box(ra, w.scenes, cv.scene[c], b);
+          const double2 q = w.bpts[bi];
+          lb += box_penalty(ra, b, q.x, q.y, &gx, &gy);
+          w.gb[bi].x += gx;
+          w.gb[bi].y += gy;
+        }
+        if (ra.deriv_weight != 0.0) {
+          act = true;
+          double dt;
+          const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, nb, true, &dt);
+          span = find_span(v.U, v.p, v.m, u);
+          const double sc = ra.deriv_weight / (double)curves_in_scene(cv, cv.scene[c]) * quad_weight(j, nb, true);
+          ld += deriv_adjoint(cv, v, u, span, ra.deriv_order, sc, pa);
+          cur[4] = pa.ubar * (1.0 - dt);
+          cur[5] = pa.ubar * dt;
+          kspan = (int64_t)v.t0 + (int64_t)c * KNOT_PAD + span;
+          kcur = c;
+        }
+      }
+    }
+    if (!act) {
+#pragma unroll
+      for (int q = 0; q <= MAXP; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pa.cp[q][k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+    }
+    const bool any = __ballot(act) != 0ull;
+    accumulate_points(w, kspan, c, v, span, pa, any);
+    if (any) accumulate_curve(w, kcur, c, v, cur);
+  }
+  block_loss(lb, ld, ra.loss);
+}
+
 }  // namespace
 
 hipError_t launch_zero_grads(const Launch& L) {
@@ -506,6 +965,23 @@ hipError_t launch_zero_grads(const Launch& L) {
   if (L.bf->caps.boundary > 0)
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(2 * L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
                        (double*)L.w.gb, 2 * L.bf->caps.boundary);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
+  Phase ph(L, NSPLAT_T_ADJ_GAUSS);
+  RegArgs ra;
+  ra.bbox_weight = (double)reg->bbox_weight;
+  ra.deriv_weight = (double)reg->deriv_weight;
+  ra.bbox_kind = reg->bbox_kind;
+  ra.deriv_order = reg->deriv_order;
+  ra.bbox = reg->bbox;
+  ra.loss = reg->loss;
+  hipLaunchKernelGGL(k_reg_stroke, dim3(grid_for(L.bf->caps.gauss, 256, 4096)), dim3(256), 0, L.stream, *L.cv, L.w,
+                     ra, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss, L.pr->kappa);
+  if (L.bf->caps.boundary > 0)
+    hipLaunchKernelGGL(k_reg_boundary, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
+                       *L.cv, L.w, ra, L.bf->plan, L.bf->counters);
   return hipGetLastError();
 }
 

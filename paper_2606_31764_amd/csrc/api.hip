@@ -312,9 +312,9 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes
   return NSPLAT_OK;
 }
 
-int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
-                    const nsplat_buffers* bf, const float* dL, const float* T_final, const int32_t* n_last,
-                    const nsplat_grads* gr, int persistent, void* stream) {
+int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                        const nsplat_buffers* bf, const float* dL, const float* T_final, const int32_t* n_last,
+                        const nsplat_reg* reg, const nsplat_grads* gr, int persistent, void* stream) {
   Launch L;
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
@@ -322,10 +322,45 @@ int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
   if (cv->n_curves > 0 && (!gr->key_xy || !gr->key_w || !gr->key_s || !gr->color || !gr->opacity ||
                            (cv->n_taus > 0 && !gr->tau)))
     return fail(ctx, NSPLAT_EINVAL, "a gradient pointer is NULL");
+  const bool use_reg = reg && (reg->bbox_weight != 0.0f || reg->deriv_weight != 0.0f);
+  if (use_reg) {
+    if (reg->deriv_weight != 0.0f && (reg->deriv_order < 1 || reg->deriv_order > 3))
+      return fail(ctx, NSPLAT_EINVAL, "deriv_order must be in 1..3 (got %d)", reg->deriv_order);
+    if (reg->bbox_kind != 0 && reg->bbox_kind != 1)
+      return fail(ctx, NSPLAT_EINVAL, "bbox_kind must be 0 (ReLU) or 1 (softplus) (got %d)", reg->bbox_kind);
+  }
   hipError_t h = launch_zero_grads(L);
   if (h == hipSuccess) h = launch_blend_bwd(L, dL, T_final, n_last, persistent);
+  if (h == hipSuccess && use_reg && cv->n_curves > 0) h = launch_reg(L, reg);
   if (h == hipSuccess && cv->n_curves > 0) h = launch_adjoint(L, gr);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_backward");
+  return NSPLAT_OK;
+}
+
+int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                    const nsplat_buffers* bf, const float* dL, const float* T_final, const int32_t* n_last,
+                    const nsplat_grads* gr, int persistent, void* stream) {
+  return nsplat_backward_reg(ctx, cv, sc, pr, bf, dL, T_final, n_last, nullptr, gr, persistent, stream);
+}
+
+int nsplat_adam_step(nsplat_ctx* ctx, const nsplat_adam* cfg, const nsplat_values* prm, const nsplat_grads* gr,
+                     float* m, float* v, int32_t* step_dev, void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  if (!cfg || !prm || !gr || !step_dev) return fail(ctx, NSPLAT_EINVAL, "cfg / params / grads / step is NULL");
+  if (prm->n_curves < 0 || prm->n_keys < 0 || prm->n_taus < 0 || (prm->channels != 1 && prm->channels != 3))
+    return fail(ctx, NSPLAT_EINVAL, "bad parameter sizes");
+  const int64_t n = 4 * (int64_t)prm->n_keys + prm->n_taus + (int64_t)prm->n_curves * (prm->channels + 1);
+  if (n > 0 && (!m || !v)) return fail(ctx, NSPLAT_EINVAL, "moment buffers are NULL");
+  if ((prm->n_keys > 0 && (!prm->key_xy || !prm->key_w || !prm->key_s || !gr->key_xy || !gr->key_w ||
+                           !gr->key_s)) ||
+      (prm->n_taus > 0 && (!prm->tau || !gr->tau)) ||
+      (prm->n_curves > 0 && (!prm->color || !prm->opacity || !gr->color || !gr->opacity)))
+    return fail(ctx, NSPLAT_EINVAL, "a parameter or gradient pointer is NULL");
+  if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f) || !(cfg->w_min <= cfg->w_max) || !(cfg->tau_min <= cfg->tau_max))
+    return fail(ctx, NSPLAT_EINVAL, "bad Adam settings");
+  hipError_t h = launch_adam(cfg, prm, gr, m, v, step_dev, (hipStream_t)stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_adam_step");
   return NSPLAT_OK;
 }
 

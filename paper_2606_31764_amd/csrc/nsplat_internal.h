@@ -281,6 +281,9 @@ hipError_t launch_blend_fwd(const Launch& L, float* image, float* T_final, int32
 hipError_t launch_blend_bwd(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last,
                             int persistent);
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g);
+hipError_t launch_reg(const Launch& L, const nsplat_reg* reg);
+hipError_t launch_adam(const nsplat_adam* cfg, const nsplat_values* prm, const nsplat_grads* g, float* m, float* v,
+                       int32_t* step_dev, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_scan(uint32_t* data, const int32_t* n_dev, int64_t n_cap, uint32_t* total_out, uint32_t* tmp,
                        hipStream_t s);

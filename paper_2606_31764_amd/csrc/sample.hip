@@ -379,6 +379,7 @@ __device__ inline double polyline_sdf(double qx, double qy, const double2* __res
 __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
                                               const int32_t* counters, Gauss* __restrict__ out) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const bool capped = (int64_t)counters[NSPLAT_CNT_GAUSS_REQ] > G;
   const int n = cv.n_curves;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
     // curve: the last c with goff[c] <= g
@@ -411,12 +412,22 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       // Lanes take the window in bands of 8 rows, column by column inside a
       // band, so that a wavefront covers an 8 x 8 block of lattice points
       // (nearby points visit the same boundary chunks); each point still
-      // lands at its row-major place g = goff + iy nx + ix.
+      // lands at its row-major place g = goff + iy nx + ix.  When the
+      // Gaussian count was capped (capacity overflow), lanes keep their own
+      // row-major point instead, so that every record below the cap is
+      // written.
       const int nx = row[P_NX], ny = row[P_NY];
-      const int band = local / (8 * nx);
-      const int rows = min(8, ny - 8 * band);
-      const int i = local - band * 8 * nx;
-      const int ix = i / rows, iy = 8 * band + (i - (i / rows) * rows);
+      int ix, iy;
+      if (!capped) {
+        const int band = local / (8 * nx);
+        const int rows = min(8, ny - 8 * band);
+        const int i = local - band * 8 * nx;
+        ix = i / rows;
+        iy = 8 * band + (i - ix * rows);
+      } else {
+        iy = local / nx;
+        ix = local - iy * nx;
+      }
       const int lin = iy * nx + ix;
       const int64_t gp = (int64_t)w.goff[c] + lin;
       r.local = lin;

@@ -209,15 +209,26 @@ class Renderer:
                                      int(self.persistent), _stream()))
         return self.image
 
-    def backward(self, tensors, dL: torch.Tensor, params=None):
+    def backward(self, tensors, dL: torch.Tensor, params=None, reg: "Reg" = None, grads=None):
+        """Parameter gradients of the image loss (upstream dL) plus, with `reg`,
+        the geometric regularisers (Eq. 11-12).  `grads` may pass preallocated
+        output tensors (e.g. for graph capture)."""
         cv, pr = self._structs(tensors, params)
-        grads = [torch.empty_like(t) for t in tensors]
+        if grads is None:
+            grads = [torch.empty_like(t) for t in tensors]
         gc = L.Grads(*[_ptr(g) for g in grads])
         c = self.ctx
         dL = dL.contiguous()
-        c.check(c.lib.nsplat_backward(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c), ctypes.byref(pr),
-                                      ctypes.byref(self.bufs), _ptr(dL), _ptr(self.T), _ptr(self.n_last),
-                                      ctypes.byref(gc), int(self.persistent), _stream()))
+        if reg is None:
+            c.check(c.lib.nsplat_backward(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c),
+                                          ctypes.byref(pr), ctypes.byref(self.bufs), _ptr(dL), _ptr(self.T),
+                                          _ptr(self.n_last), ctypes.byref(gc), int(self.persistent), _stream()))
+        else:
+            rc = reg.struct()
+            c.check(c.lib.nsplat_backward_reg(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c),
+                                              ctypes.byref(pr), ctypes.byref(self.bufs), _ptr(dL), _ptr(self.T),
+                                              _ptr(self.n_last), ctypes.byref(rc), ctypes.byref(gc),
+                                              int(self.persistent), _stream()))
         return grads
 
     def run_forward(self, tensors, frozen=False, sync=True, params=None):
@@ -286,6 +297,53 @@ class NSplatFunction(torch.autograd.Function):
     def backward(ctx, grad_img):
         grads = ctx.renderer.backward(ctx.tensors, grad_img)
         return (*grads, None, None, None)
+
+
+@dataclasses.dataclass
+class Reg:
+    """Geometric regularisers of Sec. 3.5 for Renderer.backward: bounding-box
+    penalty (Eq. 12; kind 0 ReLU, 1 softplus; bbox [S][4] device tensor or None
+    for the canvas) and derivative loss of order r (Eq. 11).  `loss` (device
+    [2]) accumulates the two values."""
+    bbox_weight: float = 0.0
+    bbox_kind: int = 0
+    bbox: Optional[torch.Tensor] = None
+    deriv_weight: float = 0.0
+    deriv_order: int = 3
+    loss: Optional[torch.Tensor] = None
+
+    def struct(self):
+        return L.Reg(float(self.bbox_weight), int(self.bbox_kind),
+                     _ptr(self.bbox) if self.bbox is not None else None, float(self.deriv_weight),
+                     int(self.deriv_order), _ptr(self.loss) if self.loss is not None else None)
+
+
+class Adam:
+    """Device Adam over the six parameter groups with the supplementary
+    settings: per-group learning rates (key_xy, key_w, key_s, tau, color,
+    opacity), cosine decay to final_ratio over total_steps, clamps w in
+    [0.01, 10] and tau in [0, 2].  The step counter lives on the device, so a
+    captured graph advances it."""
+
+    def __init__(self, tensors, lr=(1.5, 0.1, 0.2, 0.1, 0.01, 0.01), betas=(0.9, 0.999), eps=1e-8,
+                 total_steps=1000, final_ratio=0.1, w_range=(0.01, 10.0), tau_range=(0.0, 2.0), ctx=None):
+        self.ctx = ctx or Context(tensors[0].device.index or 0)
+        self.tensors = tensors
+        n = sum(t.numel() for t in tensors)
+        self.m = torch.zeros(n, device=tensors[0].device)
+        self.v = torch.zeros(n, device=tensors[0].device)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=tensors[0].device)
+        self.cfg = L.Adam((ctypes.c_float * 6)(*lr), betas[0], betas[1], eps, final_ratio, int(total_steps),
+                          w_range[0], w_range[1], tau_range[0], tau_range[1])
+        key_xy, key_w, key_s, tau, color, opacity = tensors
+        self.vals = L.Values(int(opacity.numel()), int(color.numel() // max(opacity.numel(), 1)),
+                             int(key_w.numel()), int(tau.numel()), *[_ptr(t) for t in tensors])
+
+    def step(self, grads):
+        gc = L.Grads(*[_ptr(g) for g in grads])
+        c = self.ctx
+        c.check(c.lib.nsplat_adam_step(c.h, ctypes.byref(self.cfg), ctypes.byref(self.vals), ctypes.byref(gc),
+                                       _ptr(self.m), _ptr(self.v), _ptr(self.step_dev), _stream()))
 
 
 def render(renderer: Renderer, key_xy, key_w, key_s, tau, color, opacity, frozen=False, sync=True):

@@ -203,3 +203,41 @@ def test_batch_depths_agree(tile):
         np.testing.assert_array_equal(outs[d]["image"], outs[64]["image"])
         np.testing.assert_array_equal(outs[d]["n_last"], outs[64]["n_last"])
         assert grad_close(outs[d]["grads"], outs[64]["grads"], rtol=1e-5, atol=1e-7) <= 1.0
+
+
+def test_capacity_overflow_without_growth_is_flagged_and_consistent():
+    """A step that overflows the Gaussian capacity with no host check in between
+    (as inside a captured graph) sets the status bit and still leaves every record
+    below the cap written (the fill lattice then goes row-major), so the later
+    kernels of the step read only valid records."""
+    import torch
+    from paper_2606_31764_amd import _lib as Lb
+    from paper_2606_31764_amd.render import Reg, Renderer, param_tensors
+    b = synth.concat([synth.config2(seed=2900, n_curves=3, size=64), synth.config3(seed=2901, n_paths=4, size=64)])
+    p = Params().replace(delta_c=2.0, h=2.0)
+    sizer = Renderer(b, p)
+    t = param_tensors(b)
+    sizer.run_forward(t)
+    cnt = sizer.read_counters()
+    G_full = cnt[Lb.CNT_GAUSS]
+    caps = dict(gauss=G_full // 2, pairs=4 * cnt[Lb.CNT_PAIRS] + 1024, boundary=2 * cnt[Lb.CNT_BOUND_REQ] + 64)
+    r = Renderer(b, p, caps=caps)
+    r.sample(t, sync=False)
+    r.bin(t, sync=False)
+    img = r.forward(t)
+    grads = r.backward(t, 2.0 * (img - 0.5), reg=Reg(bbox_weight=1.0, deriv_weight=0.1))
+    torch.cuda.synchronize()
+    cnt2 = r.read_counters()
+    assert cnt2[Lb.CNT_STATUS] & Lb.STATUS_GAUSS_CAP
+    assert cnt2[Lb.CNT_GAUSS] == caps["gauss"] and cnt2[Lb.CNT_GAUSS_REQ] == G_full
+    rec = r.gaussians()
+    plan = r.plan_np()
+    assert np.all((rec["curve"] >= 0) & (rec["curve"] < b.n_curves))
+    assert np.all(rec["local"] >= 0) and np.all(rec["local"] < plan[rec["curve"], 0])
+    # the records below the cap are exactly the full run's first records
+    ref = sizer.gaussians()
+    n = caps["gauss"]
+    np.testing.assert_array_equal(rec["curve"], ref["curve"][:n])
+    np.testing.assert_array_equal(rec["local"], ref["local"][:n])
+    assert np.array_equal(rec["mu"], ref["mu"][:n])
+    assert all(torch.isfinite(g).all().item() for g in grads)
