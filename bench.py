@@ -25,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = dict(hbm_gbs=8000.0, fp32_tflops=157.3, fp64_tflops=78.6)
-PHASES = ["plan", "emit", "bin", "sort", "ranges", "blend_fwd", "blend_bwd", "adj_gauss", "adj_bound", "fold"]
+PHASES = ["plan", "emit", "bin", "sort", "ranges", "blend_fwd", "blend_bwd", "adj_gauss", "adj_bound", "fold",
+          "reg"]
 
 
 def log(*a):
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-optim", action="store_true", help="skip the full optimisation-step measurement")
+    ap.add_argument("--optim-steps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
@@ -80,10 +83,10 @@ def timing_on(ctx, on):
 
 
 def timing_read(ctx):
-    ms = (ctypes.c_double * 10)()
-    n = (ctypes.c_int64 * 10)()
+    ms = (ctypes.c_double * len(PHASES))()
+    n = (ctypes.c_int64 * len(PHASES))()
     ctx.check(ctx.lib.nsplat_timing_read(ctx.h, ms, n))
-    return {PHASES[i]: (ms[i], n[i]) for i in range(10)}
+    return {PHASES[i]: (ms[i], n[i]) for i in range(len(PHASES))}
 
 
 def blend_work(step, tile):
@@ -265,6 +268,8 @@ def bench_main(args):
         out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_batched:
         out["batched"] = bench_batched(args)
+    if not args.no_optim:
+        out["optim_step"] = bench_optim(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, p, target)
     return out
@@ -400,6 +405,82 @@ def bench_batched(args):
     res["hbm_phases_batched"]["radix_passes"] = passes
     res["pairs"] = int(bat.r.read_counters()[1])
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
+    return res
+
+
+def bench_optim(args):
+    """One full optimisation step on the long-spline workload (16 open cubics x
+    2000 key points, 1024^2 grayscale): sample, bin, forward, L2 gradient,
+    backward with the derivative loss (r = 3) and the bounding-box loss at the
+    calligraphy weights (lambda_deriv 1, lambda_bbox 5), and the Adam step with
+    its cosine decay and clamps, captured once in a HIP graph and replayed."""
+    import torch
+    from paper_2606_31764_amd import synth
+    from paper_2606_31764_amd.render import Adam, Context, Params, Reg, Renderer, param_tensors
+    b = synth.config4()
+    p = Params().replace(**synth.CONFIG_PARAMS[4])
+    ctx = Context(0)
+    pert = synth.perturbed(b, seed=4999)
+    tr = Renderer(pert, p, ctx=ctx)
+    target = tr.run_forward(param_tensors(pert)).clone()
+    del tr
+    t0 = param_tensors(b)
+    sizer = Renderer(b, p, ctx=ctx)
+    sizer.run_forward(t0)
+    cnt = sizer.read_counters()
+    del sizer
+    # the parameters move during the run: capacities with 2x slack
+    caps = dict(gauss=2 * cnt[3] + 1024, pairs=2 * cnt[4] + 4096, boundary=2 * cnt[5] + 64)
+    t = [x.clone() for x in t0]
+    r = Renderer(b, p, caps=caps, ctx=ctx)
+    opt = Adam(t, lr=(1.5, 0.1, 0.2, 0.1, 0.01, 0.01), total_steps=150, ctx=ctx)
+    dL = torch.empty_like(target)
+    grads = [torch.empty_like(x) for x in t]
+    losses = torch.zeros(3, device="cuda")
+    reg = Reg(bbox_weight=5.0, bbox_kind=0, deriv_weight=1.0, deriv_order=3, loss=losses[1:])
+
+    def step():
+        img = r.run_forward(t, sync=False)
+        ctx.check(ctx.lib.nsplat_l2_grad(ctx.h, ctypes.c_void_p(img.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                         ctypes.c_void_p(dL.data_ptr()), ctypes.c_void_p(losses.data_ptr()),
+                                         img.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        r.backward(t, dL, reg=reg, grads=grads)
+        opt.step(grads)
+
+    s_cap = torch.cuda.Stream()
+    s_cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_cap):
+        for _ in range(2):
+            step()
+    torch.cuda.current_stream().wait_stream(s_cap)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    K = args.optim_steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    losses.zero_()
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    cnt = r.read_counters()
+    lv = (losses / K).cpu().numpy().tolist()
+    # per-phase times of one eager step (outside the timed region)
+    timing_on(ctx, True)
+    step()
+    torch.cuda.synchronize()
+    ph = timing_read(ctx)
+    timing_on(ctx, False)
+    del g
+    res = dict(workload="16 open cubics x 2000 key points, 1024x1024 grayscale, delta_c 10; L2 + derivative "
+                        "loss (r = 3) + bounding-box loss, Adam", gaussians=int(cnt[0]), pairs=int(cnt[1]),
+               status=int(cnt[2]), ms_per_step=ms, gaussians_per_s=cnt[0] / (ms * 1e-3),
+               loss_l2_bbox_deriv=lv, phases_ms={k: v[0] for k, v in ph.items()})
+    log("optim step: %d Gaussians, %.3f ms/step (reg %.3f ms), status %d" % (cnt[0], ms, ph["reg"][0], cnt[2]))
     return res
 
 

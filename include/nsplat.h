@@ -79,7 +79,8 @@ extern "C" {
 #define NSPLAT_T_ADJ_GAUSS 7   /* per-Gaussian sample adjoint                   */
 #define NSPLAT_T_ADJ_BOUND 8   /* boundary-point adjoint                        */
 #define NSPLAT_T_FOLD 9        /* zeroing and the fold to key points / tau      */
-#define NSPLAT_NUM_TIMERS 10
+#define NSPLAT_T_REG 10        /* geometric regularisers (nsplat_backward_reg)  */
+#define NSPLAT_NUM_TIMERS 11
 
 /* plan[] row layout (dev int32[n_curves][8]) */
 #define NSPLAT_PLAN_COUNT 0   /* Gaussians of the curve                        */

@@ -969,7 +969,7 @@ hipError_t launch_zero_grads(const Launch& L) {
 }
 
 hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
-  Phase ph(L, NSPLAT_T_ADJ_GAUSS);
+  Phase ph(L, NSPLAT_T_REG);
   RegArgs ra;
   ra.bbox_weight = (double)reg->bbox_weight;
   ra.deriv_weight = (double)reg->deriv_weight;
