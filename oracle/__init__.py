@@ -92,6 +92,7 @@ def lib():
             "or_reg_loss": (dbl, [vp, vp, vp, vp, vp, i64, vp, vp]),
             "or_reg_grad_full": (dbl, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "or_curve_derivs": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, i32, vp]),
+            "or_udf_loss": (dbl, [vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -351,6 +352,21 @@ def curve_derivs(p, closed, key_xy, key_w, key_s, tau, t, r):
     lib().or_curve_derivs(p, int(closed), len(kx), len(tu), _p(kx), _p(kw), _p(ks), _p(tu), len(t), _p(t),
                           int(r), _p(out))
     return out
+
+
+def udf_loss(batch, plan_rows, image, target, tau, sel=None, params=None):
+    """Distance-weighted image loss (LIVE's unsigned-distance weights): value,
+    dL/dImage (image layout) and the per-pixel distance d."""
+    B = _Batch(batch, params)
+    img = np.ascontiguousarray(image, np.float64).ravel()
+    tgt = np.ascontiguousarray(target, np.float64).ravel()
+    dL = np.zeros_like(img)
+    npix = int(sum(int(h) * int(w) for h, w in batch.hw))
+    dist = np.zeros(npix)
+    sl = None if sel is None else np.ascontiguousarray(sel, np.int32)
+    v = lib().or_udf_loss(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), _p(sl), float(tau), _p(img),
+                          _p(tgt), _p(dL), _p(dist))
+    return float(v), dL, dist
 
 
 GROUPS = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")

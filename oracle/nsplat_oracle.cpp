@@ -25,6 +25,8 @@
 //   Sec. 3.5     the geometric regularisers: derivative (fairing) loss,
 //                Eq. 11, from k-th basis derivatives (NURBS Book Eq. 2.9) and
 //                the rational Leibniz rule, and the bounding-box loss, Eq. 12
+//   Sec. 4.2     the distance-weighted image loss of layer-wise vectorisation
+//                (LIVE's unsigned-distance weights, udf_weight)
 // and the exact derivative of the image loss with respect to every curve
 // parameter: the compositing adjoint is written out per pixel; the map from
 // curve parameters to Gaussians is differentiated in forward mode with dual
@@ -907,6 +909,66 @@ double or_reg_grad_full(const or_curves* in, const or_scenes* sc, const or_param
   std::vector<double> out(n);
   const double total = or_reg_loss(in, sc, pr, plan, rg, n, seeds.data(), out.data());
   for (int64_t i = 0; i < n; ++i) *dst[i] = out[i];
+  return total;
+}
+
+// Distance-weighted image loss (Sec. 4.2; the weights of LIVE, Ma et al.
+// 2022): for every pixel centre q of a scene, d(q) = distance to the nearest
+// boundary segment of the scene's selected filled curves (their N_b-point
+// closed polylines of Sec. 3.3; sel == NULL selects every filled curve),
+// w(q) = max(0, tau - d(q)), normalised to sum 1 over the scene (all zero if
+// no pixel is within tau); L = sum_q w(q) (1/C) sum_c (I_c(q) - I*_c(q))^2,
+// the weights held constant.  Writes dL/dI (image layout) and d (per pixel,
+// +inf where no curve is selected) and returns L summed over the scenes.
+double or_udf_loss(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
+                   const int32_t* sel, double tau, const double* img, const double* tgt, double* dL, double* dist) {
+  const int C = in->channels;
+  std::vector<std::vector<double>> bxs(in->n_curves), bys(in->n_curves);
+  std::vector<char> use(in->n_curves, 0);
+  for (int c = 0; c < in->n_curves; ++c) {
+    const int32_t* row = plan + P_STRIDE * c;
+    if (!(in->flags[c] & F_FILLED) || row[P_NSAMP] <= 0 || (sel && !sel[c])) continue;
+    use[c] = 1;
+    boundary_points(build_curve<double>(in, c, S_NONE, 0), row[P_NSAMP], bxs[c], bys[c]);
+  }
+  double total = 0.0;
+  int64_t pix_off = 0;
+  for (int s = 0; s < sc->n_scenes; ++s) {
+    const int H = sc->hw[2 * s], W = sc->hw[2 * s + 1];
+    const int64_t plane = (int64_t)H * W;
+    std::vector<double> wq(plane, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        const double qx = x + 0.5, qy = y + 0.5;
+        double d = INFINITY;
+        for (int c = 0; c < in->n_curves; ++c) {
+          if (!use[c] || in->scene[c] != s) continue;
+          const std::vector<double>& bx = bxs[c];
+          const std::vector<double>& by = bys[c];
+          const size_t n = bx.size();
+          for (size_t i = 0; i < n; ++i) {
+            const size_t k = (i + 1) % n;
+            d = std::min(d, seg_dist(qx, qy, bx[i], by[i], bx[k], by[k]));
+          }
+        }
+        dist[pix_off + (int64_t)y * W + x] = d;
+        wq[(int64_t)y * W + x] = std::max(0.0, tau - d);
+      }
+    double sum = 0.0;
+    for (int64_t i = 0; i < plane; ++i) sum += wq[i];
+    for (int64_t i = 0; i < plane; ++i) {
+      const double wn = sum > 0.0 ? wq[i] / sum : 0.0;
+      for (int ch = 0; ch < C; ++ch) {
+        const int64_t k = pix_off * C + ch * plane + i;
+        const double e = img[k] - tgt[k];
+        total += wn * e * e / C;
+        dL[k] = 2.0 * wn * e / C;
+      }
+    }
+    pix_off += plane;
+  }
+  (void)pr;
   return total;
 }
 

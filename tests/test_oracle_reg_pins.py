@@ -276,3 +276,60 @@ def test_derivative_loss_approximates_the_integral_within_the_trapezoid_bound():
     bound = f2 / (12.0 * (M - 1) ** 2)
     assert abs(v - exact) <= bound + 1e-9 * exact
     assert abs(v - exact) > 0.0 or f2 == 0.0
+
+
+def _seg_dist_np(q, A, B):
+    """Distance from points q [n, 2] to segments A->B [m, 2] (numpy, vectorised)."""
+    e = B - A
+    ee = np.sum(e * e, axis=1)
+    r = q[:, None, :] - A[None, :, :]
+    t = np.where(ee > 0, np.sum(r * e[None], axis=2) / np.where(ee > 0, ee, 1.0), 0.0)
+    t = np.clip(t, 0.0, 1.0)
+    pnt = A[None] + t[..., None] * e[None] - q[:, None, :]
+    return np.sqrt(np.sum(pnt * pnt, axis=2)).min(axis=1)
+
+
+def test_udf_weights_against_a_numpy_brute_force():
+    """Distances to the boundary polyline (boundary points taken from the
+    separate curve_eval path, distances by a vectorised numpy projection),
+    weights max(0, tau - d) normalised per scene, loss and dL/dI."""
+    b = synth.config3(seed=5800, n_paths=3, size=40)
+    prm = dict(h=2.0)
+    plan, _, _ = oracle.plan(b, prm)
+    rng = np.random.default_rng(3)
+    n_img = 3 * 40 * 40
+    img, tgt = rng.uniform(0, 1, n_img), rng.uniform(0, 1, n_img)
+    sel = np.array([1, 0, 1], np.int32)
+    tau = 6.0
+    v, dL, dist = oracle.udf_loss(b, plan, img, tgt, tau, sel=sel, params=prm)
+    ys, xs = np.mgrid[0:40, 0:40]
+    q = np.stack([xs.ravel() + 0.5, ys.ravel() + 0.5], 1).astype(np.float64)
+    d = np.full(len(q), np.inf)
+    for c in np.nonzero(sel)[0]:
+        k0, k1 = b.key_off[c], b.key_off[c + 1]
+        t0, t1 = b.tau_off[c], b.tau_off[c + 1]
+        nb = int(plan[c, oracle.P_NSAMP])
+        pts = oracle.curve_eval(int(b.degree[c]), True, b.key_xy[k0:k1], b.key_w[k0:k1], b.key_s[k0:k1],
+                                b.tau[t0:t1], np.arange(nb) / nb)[:, :2]
+        d = np.minimum(d, _seg_dist_np(q, pts, np.roll(pts, -1, axis=0)))
+    assert np.allclose(dist, d, rtol=0, atol=1e-9)
+    wq = np.maximum(0.0, tau - d)
+    wn = wq / wq.sum()
+    e = (img - tgt).reshape(3, -1)
+    assert abs(v - np.sum(wn * np.sum(e * e, axis=0) / 3)) <= 1e-12
+    assert np.allclose(dL.reshape(3, -1), 2 * wn * e / 3, rtol=0, atol=1e-15)
+
+
+def test_udf_weights_sum_to_one_and_vanish_beyond_tau():
+    b = synth.concat([synth.config3(seed=5900, n_paths=2, size=32), synth.config3(seed=5901, n_paths=2, size=24)])
+    prm = dict(h=2.0)
+    plan, _, _ = oracle.plan(b, prm)
+    n_img = 3 * (32 * 32 + 24 * 24)
+    img = np.full(n_img, 0.75)
+    tgt = np.full(n_img, 0.25)
+    v, dL, dist = oracle.udf_loss(b, plan, img, tgt, 4.0, params=prm)
+    # a constant error e per channel: L = sum_s sum_q w (e^2) = (number of scenes) e^2
+    assert abs(v - 2 * 0.25) <= 1e-12
+    # zero gradient wherever d >= tau
+    far = np.concatenate([np.tile(dist[:32 * 32] >= 4.0, 3), np.tile(dist[32 * 32:] >= 4.0, 3)])
+    assert np.all(dL[far] == 0.0) and np.any(dL != 0.0)
