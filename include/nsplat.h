@@ -274,6 +274,21 @@ int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* curves, const nspl
                         const float* T_final, const int32_t* n_last, const nsplat_reg* reg,
                         const nsplat_grads* grads, int persistent, void* stream);
 
+/* Distance-weighted image loss of the layer-wise vectorisation application
+ * (Sec. 4.2: "udf_weight", with the weights of LIVE, Ma et al. 2022): for
+ * every pixel centre q of a scene, d(q) = distance to the nearest boundary
+ * segment of the scene's selected filled curves (the closed N_b-point
+ * boundary polylines of Sec. 3.3 from this step's nsplat_sample; sel: dev
+ * int32 [n_curves], nonzero = selected, or NULL for every filled curve),
+ * w(q) = max(0, tau - d(q)) normalised to sum 1 over the scene (all 0 if no
+ * pixel is within tau), and L = sum_q w(q) (1/C) sum_c (I_c(q) - I*_c(q))^2
+ * with the weights held constant.  Writes dL/dImage to dL_dimage (dev FP32,
+ * image layout) and adds L over all scenes to *loss (dev FP32, may be NULL).
+ * NSPLAT_EINVAL for a NULL array or tau <= 0. */
+int nsplat_udf_loss(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                    const nsplat_params* params, const nsplat_buffers* bufs, const int32_t* sel, float tau,
+                    const float* image, const float* target, float* dL_dimage, float* loss, void* stream);
+
 /* Learnable parameters, writable (dev FP32; the arrays the curves point to). */
 typedef struct {
   int32_t n_curves, channels, n_keys, n_taus;

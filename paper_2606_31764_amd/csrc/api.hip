@@ -52,6 +52,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(double4) * (size_t)(bcap / SDF_CHUNK + 2 * N + 2),  // cbox
       sizeof(int32_t) * (size_t)std::max<int64_t>(nsplat_num_tiles(sc, 8), 1),  // order
       sizeof(int32_t) * 64,                                // obin
+      sizeof(double) * (size_t)(S + 1),                    // sacc
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -86,6 +87,7 @@ Work carve(void* ws, const Layout& lay) {
   w.cbox = (double4*)(b + lay.off[18]);
   w.order = (int32_t*)(b + lay.off[19]);
   w.obin = (int32_t*)(b + lay.off[20]);
+  w.sacc = (double*)(b + lay.off[21]);
   return w;
 }
 
@@ -341,6 +343,19 @@ int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
                     const nsplat_buffers* bf, const float* dL, const float* T_final, const int32_t* n_last,
                     const nsplat_grads* gr, int persistent, void* stream) {
   return nsplat_backward_reg(ctx, cv, sc, pr, bf, dL, T_final, n_last, nullptr, gr, persistent, stream);
+}
+
+int nsplat_udf_loss(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
+                    const nsplat_buffers* bf, const int32_t* sel, float tau, const float* image, const float* target,
+                    float* dL, float* loss, void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  if (!image || !target || !dL) return fail(ctx, NSPLAT_EINVAL, "image / target / dL_dimage is NULL");
+  if (!(tau > 0.0f)) return fail(ctx, NSPLAT_EINVAL, "tau must be positive (got %g)", (double)tau);
+  hipError_t h = launch_udf(L, sel, tau, image, target, dL, loss);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_udf_loss");
+  return NSPLAT_OK;
 }
 
 int nsplat_adam_step(nsplat_ctx* ctx, const nsplat_adam* cfg, const nsplat_values* prm, const nsplat_grads* gr,

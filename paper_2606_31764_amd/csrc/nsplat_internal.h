@@ -18,7 +18,7 @@ constexpr double LN2 = 0.69314718055994530942;
 constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 21;                // workspace entries
+constexpr int N_WS = 22;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -59,12 +59,13 @@ struct Work {
   double4* cbox;       // [caps.boundary / SDF_CHUNK + 2 * n_curves + 2] fill SDF chunk boxes
   int32_t* order;      // [tiles at the smallest tile size] tiles by decreasing list length
   int32_t* obin;       // [64] list-length class counts, then their offsets
+  double* sacc;        // [n_scenes + 1] per-scene sums (distance-weighted loss)
 };
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
-// boundary point boff) has a header at cbox_base(boff, c) whose x is the
-// largest coordinate magnitude of its boundary, then one box (x0, x1, y0, y1)
-// per chunk of SDF_CHUNK segments.
+// boundary point boff) has a header at cbox_base(boff, c) holding the box
+// (x0, x1, y0, y1) of its whole boundary, then one box per chunk of
+// SDF_CHUNK segments.
 constexpr int SDF_CHUNK = 8;
 __host__ __device__ inline int64_t cbox_base(int64_t boff, int c) { return boff / SDF_CHUNK + 2 * (int64_t)c; }
 
@@ -282,6 +283,8 @@ hipError_t launch_blend_bwd(const Launch& L, const float* dL, const float* T_fin
                             int persistent);
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g);
 hipError_t launch_reg(const Launch& L, const nsplat_reg* reg);
+hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const float* image, const float* target,
+                      float* dL, float* loss);
 hipError_t launch_adam(const nsplat_adam* cfg, const nsplat_values* prm, const nsplat_grads* g, float* m, float* v,
                        int32_t* step_dev, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

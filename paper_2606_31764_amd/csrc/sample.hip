@@ -268,7 +268,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
   x1 = fmax(x1, red[1][0]);
   y0 = fmin(y0, red[2][0]);
   y1 = fmax(y1, red[3][0]);
-  w.cbox[cbox_base(boff, c)] = make_double4(fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))), 0.0, 0.0, 0.0);
+  w.cbox[cbox_base(boff, c)] = make_double4(x0, x1, y0, y1);
   if (!frozen) {
     const SceneTab* st = w.scenes + cv.scene[c];
     const double h = (double)read_h(pr), pad = (double)pr.fill_pad;
@@ -310,7 +310,8 @@ __device__ inline double polyline_sdf(double qx, double qy, const double2* __res
                                       const double4* __restrict__ box, int nb, int* arg, double* targ,
                                       double* sgn_out) {
   const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
-  const double scale = 1.0 + fabs(qx) + fabs(qy) + 2.0 * box[0].x;
+  const double4 hb = box[0];  // the whole boundary's box
+  const double scale = 1.0 + fabs(qx) + fabs(qy) + 2.0 * fmax(fmax(fabs(hb.x), fabs(hb.y)), fmax(fabs(hb.z), fabs(hb.w)));
   box += 1;
   double ub = INFINITY;
   for (int k = 0; k < K; ++k) {
@@ -453,7 +454,161 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
   }
 }
 
+// Squared distance from q to the closed polyline b[0..nb) (with its chunk
+// boxes), or `best` if that is smaller: chunks whose box lies farther than
+// the running minimum (with a relative margin of 1e-12) are not visited.
+__device__ inline double polyline_dist2(double qx, double qy, const double2* __restrict__ bp,
+                                        const double4* __restrict__ box, int nb, double best) {
+  const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
+  for (int k = 0; k < K; ++k) {
+    const double4 b = box[k];
+    const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
+    const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
+    if (ex0 * ex0 + ey0 * ey0 > best * (1.0 + 1e-12)) continue;
+    const int i0 = k * SDF_CHUNK;
+    const int i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
+    double2 A = bp[i0];
+    for (int i = i0; i < i1; ++i) {
+      const double2 B = bp[i + 1 < nb ? i + 1 : 0];
+      const double ex = B.x - A.x, ey = B.y - A.y;
+      const double ee = ex * ex + ey * ey;
+      const double rx = qx - A.x, ry = qy - A.y;
+      double t = 0.0;
+      if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+      t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+      const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+      best = fmin(best, px * px + py * py);
+      A = B;
+    }
+  }
+  return best;
+}
+
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// The scene of global pixel index i: the last s with pix_off <= i.
+__device__ inline int scene_of_pixel(const SceneTab* st, int n_scenes, int64_t i) {
+  int lo = 0, hi = n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (st[mid].pix_off <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Distance-weighted loss, pass 1: per pixel q, d(q) = distance to the nearest
+// boundary segment of the scene's selected filled curves, w(q) =
+// max(0, tau - d(q)) stored in the first channel plane of dL, and the per-scene
+// sums of w.
+__global__ __launch_bounds__(256) void k_udf_weight(nsplat_curves cv, Work w, const int32_t* plan, int64_t bcap,
+                                                    int n_scenes, int C, const int32_t* sel, float tau,
+                                                    float* __restrict__ dL) {
+  const int64_t npix = w.scenes[n_scenes].pix_off;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - __lane_id(); base < npix;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + __lane_id();
+    int s = -1;
+    double wq = 0.0;
+    if (i < npix) {
+      s = scene_of_pixel(w.scenes, n_scenes, i);
+      const SceneTab st = w.scenes[s];
+      const int64_t li = i - st.pix_off;
+      const int y = (int)(li / st.W), x = (int)(li - (int64_t)y * st.W);
+      const double qx = x + 0.5, qy = y + 0.5;
+      // curves of scene s: [c0, c1)
+      int lo = 0, hi = cv.n_curves;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cv.scene[mid] < s) lo = mid + 1;
+        else hi = mid;
+      }
+      const int c0 = lo;
+      hi = cv.n_curves;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cv.scene[mid] <= s) lo = mid + 1;
+        else hi = mid;
+      }
+      double best = INFINITY;
+      for (int c = c0; c < lo; ++c) {
+        if (!(cv.flags[c] & NSPLAT_FILLED) || (sel && !sel[c])) continue;
+        const int32_t* row = plan + (int64_t)P_STRIDE * c;
+        const int nb = row[P_NSAMP];
+        const int64_t boff = row[P_BOFF];
+        if (nb <= 0 || boff + nb > bcap || !curve_valid(curve_view(cv, w.knots, c))) continue;
+        const double4* box = w.cbox + cbox_base(boff, c);
+        const double4 hb = box[0];
+        const double ex0 = fmax(fmax(hb.x - qx, qx - hb.y), 0.0);
+        const double ey0 = fmax(fmax(hb.z - qy, qy - hb.w), 0.0);
+        if (ex0 * ex0 + ey0 * ey0 > best * (1.0 + 1e-12)) continue;
+        best = polyline_dist2(qx, qy, w.bpts + boff, box + 1, nb, best);
+      }
+      wq = fmax(0.0, (double)tau - sqrt(best));
+      dL[st.pix_off * C + li] = (float)wq;
+    }
+    // per-scene sums: one atomic per wavefront when its pixels share a scene
+    const int s0 = __builtin_amdgcn_readfirstlane(s);
+    const bool same = __ballot(i < npix && s != s0) == 0ull;
+    if (same) {
+      double t = wq;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+      if (__lane_id() == 0 && s0 >= 0 && t != 0.0) unsafeAtomicAdd(&w.sacc[s0], t);
+    } else if (s >= 0 && wq != 0.0) {
+      unsafeAtomicAdd(&w.sacc[s], wq);
+    }
+  }
+}
+
+// Pass 2: dL/dI_c(q) = 2 w(q) / W_s (I_c - I*_c) / C with W_s the scene's sum
+// of w (0 when it is 0), and the loss sum_q w / W_s (1/C) sum_c (I_c - I*_c)^2.
+__global__ __launch_bounds__(256) void k_udf_grad(Work w, int n_scenes, int C, const float* __restrict__ image,
+                                                  const float* __restrict__ target, float* __restrict__ dL,
+                                                  float* loss) {
+  __shared__ double red[4];
+  const int64_t npix = w.scenes[n_scenes].pix_off;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = scene_of_pixel(w.scenes, n_scenes, i);
+    const SceneTab st = w.scenes[s];
+    const int64_t li = i - st.pix_off, plane = (int64_t)st.H * st.W;
+    const double sum = w.sacc[s];
+    const double wn = sum > 0.0 ? (double)dL[st.pix_off * C + li] / sum : 0.0;
+    for (int c = 0; c < C; ++c) {
+      const int64_t k = st.pix_off * C + c * plane + li;
+      const double e = (double)image[k] - (double)target[k];
+      acc += wn * e * e / C;
+      dL[k] = (float)(2.0 * wn * e / C);
+    }
+  }
+  if (loss) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, (float)((red[0] + red[1]) + (red[2] + red[3])));
+  }
+}
+
 }  // namespace
+
+hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const float* image, const float* target,
+                      float* dL, float* loss) {
+  const int S = L.sc->n_scenes, C = L.cv->channels;
+  int64_t npix = 0;
+  for (int s = 0; s < S; ++s) npix += (int64_t)L.sc->hw_host[2 * s] * L.sc->hw_host[2 * s + 1];
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, L.stream, L.w.sacc, 0.0, (int64_t)(S + 1));
+  if (npix <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_udf_weight, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, L.stream, *L.cv, L.w,
+                     L.bf->plan, (int64_t)L.bf->caps.boundary, S, C, sel, tau, dL);
+  hipLaunchKernelGGL(k_udf_grad, dim3(grid_for(npix, 256, 2048)), dim3(256), 0, L.stream, L.w, S, C, image, target,
+                     dL, loss);
+  return hipGetLastError();
+}
 
 hipError_t launch_scene_setup(const Launch& L) {
   hipLaunchKernelGGL(k_scene_setup, dim3(1), dim3(64), 0, L.stream, *L.sc, *L.pr, L.w.scenes);

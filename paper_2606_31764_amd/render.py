@@ -231,6 +231,20 @@ class Renderer:
                                               int(self.persistent), _stream()))
         return grads
 
+    def udf_loss(self, tensors, image: torch.Tensor, target: torch.Tensor, tau: float, sel=None, loss=None,
+                 params=None, out=None):
+        """dL/dImage of the distance-weighted image loss (LIVE's unsigned-distance
+        weights around the selected filled curves; sel: device int32 [n_curves] or
+        None for every filled curve) for this step's boundaries; the loss value
+        is added to `loss` (device [1]) when given."""
+        cv, pr = self._structs(tensors, params)
+        dL = torch.empty_like(image) if out is None else out
+        c = self.ctx
+        c.check(c.lib.nsplat_udf_loss(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c), ctypes.byref(pr),
+                                      ctypes.byref(self.bufs), _ptr(sel), float(tau), _ptr(image.contiguous()),
+                                      _ptr(target.contiguous()), _ptr(dL), _ptr(loss), _stream()))
+        return dL
+
     def run_forward(self, tensors, frozen=False, sync=True, params=None):
         """sample -> bin -> forward.  With sync, any capacity overflow grows the
         buffers and re-runs from sampling (growing reallocates the workspace)."""

@@ -211,3 +211,28 @@ def test_full_step_in_a_graph():
             d = (a - e).abs().max().item()
             assert d <= 1e-4 * (1.0 + e.abs().max().item()), (k, d)
         _ = (torch.randn(100, device="cuda") * 3).sum().item()
+
+
+@pytest.mark.parametrize("selected", [False, True])
+def test_udf_loss_matches_oracle(selected):
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.concat([synth.config3(seed=6000, n_paths=5, size=72),
+                      synth.config2(seed=6001, n_curves=2, size=40), synth.config3(seed=6002, n_paths=3, size=48)])
+    p = Params().replace(delta_c=2.0, h=2.0)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    img = r.run_forward(t).clone()
+    rng = np.random.default_rng(6003)
+    tgt = torch.as_tensor(rng.uniform(0, 1, img.numel()).astype(np.float32), device="cuda")
+    sel_np = (rng.uniform(size=b.n_curves) < 0.5).astype(np.int32) if selected else None
+    sel = None if sel_np is None else torch.as_tensor(sel_np, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    dL = r.udf_loss(t, img, tgt, tau=8.0, sel=sel, loss=loss)
+    torch.cuda.synchronize()
+    op = oracle_params(p)
+    plan, _, _ = oracle.plan(b, op)
+    v, dref, _ = oracle.udf_loss(b, plan, img.cpu().numpy(), tgt.cpu().numpy(), 8.0, sel=sel_np, params=op)
+    got = dL.cpu().numpy().astype(np.float64)
+    assert np.abs(got - dref).max() <= 1e-5 * np.abs(dref).max() + 1e-12
+    assert abs(float(loss.item()) - v) <= 1e-5 * abs(v) + 1e-9
