@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--optim-steps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--only", choices=["batched", "optim"], default=None,
+                    help="run one secondary leg alone (for profiling); prints its result as JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -538,7 +540,12 @@ def main():
         print("bench.py measures one GPU only: the render path of this repository runs on a single MI355X "
               "(multi-GPU sharding is a design note, not a measured path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    out = bench_main(args)
+    if args.only == "batched":
+        out = bench_batched(args)
+    elif args.only == "optim":
+        out = bench_optim(args)
+    else:
+        out = bench_main(args)
     print(json.dumps(out), flush=True)
 
 
