@@ -43,7 +43,8 @@ __device__ inline void pixel_of(int quad, int lane, int q, int* lx, int* ly) {
 // Next work item of this wavefront: the static assignment, or the next entry
 // of the device work queue (persistent form).
 __device__ inline int next_item(int it, int persistent, int32_t* queue) {
-  if (!persistent) return it == 0 ? (int)(blockIdx.x * WPB + (threadIdx.x >> 6)) : 0x7fffffff;
+  if (!persistent)
+    return __builtin_amdgcn_readfirstlane(it == 0 ? (int)(blockIdx.x * WPB + (threadIdx.x >> 6)) : 0x7fffffff);
   int v = 0;
   if (__lane_id() == 0) v = atomicAdd(queue, 1);
   return __builtin_amdgcn_readfirstlane(v);
@@ -97,6 +98,17 @@ __device__ inline uint64_t lanes_below() {
 // LDS bytes per wavefront for a step of `depth` entries.
 constexpr int FWD_ENTRY_BYTES = 36;   // geometry, opacity + colour, list position
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
+// The adjoint parks the per-lane gradient values it still has to sum over
+// the wavefront in LDS rows of 64 floats, one row per value (three for a
+// stroke Gaussian, one for a fill Gaussian), and sums RB rows at a time (see
+// flush_rows).  Rows are padded to 72 floats so that the flush's eight rows
+// fall into different banks.
+constexpr int RB = 8;
+constexpr int RB_ROW = 72;            // floats per parked row
+constexpr size_t BWD_PARK_BYTES = (size_t)RB * RB_ROW * 4;
+__host__ __device__ constexpr size_t bwd_wave_bytes(int E) {
+  return ((size_t)64 * E * BWD_ENTRY_BYTES + BWD_PARK_BYTES + 15) / 16 * 16;
+}
 
 template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
@@ -264,7 +276,7 @@ __device__ inline float wave_totals_to_lanes(const float (&v)[N]) {
 __device__ inline int wave_min(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Flushes one wavefront's running per-curve sums (colour, and opacity for a
@@ -282,6 +294,33 @@ __device__ inline void flush_curve(double* gcurve, int c, bool fill, float (&acc
   const float t = wave_totals_to_lanes<C + 1>(v);
   const int lane = __lane_id();
   if (lane <= C && t != 0.0f) unsafeAtomicAdd(gcurve + 4 * (int64_t)c + lane, (double)t);
+}
+
+// Sums the first n (<= RB) parked rows over the 64 lanes and adds each total
+// to its adjoint value ggrad[row_g * GG + row_c] (row_g, row_c: lane r of
+// those registers describes row r).  Lane (r, part) = (lane / 8, lane % 8)
+// adds up floats part, part + 8, ... of row r; DPP row shifts finish the sum
+// in the group's last lane, which issues the atomic.  Every lane of the
+// wavefront must call it.
+__device__ inline void flush_rows(const float* park, int n, int row_g, int row_c, float* __restrict__ ggrad) {
+  static_assert(RB * 8 == 64, "eight lanes per parked row");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int lane = __lane_id(), r = lane >> 3, part = lane & 7;
+  const float* row = park + r * RB_ROW + part;
+  float t = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t += row[8 * j];
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x111, 0xf, 0xf, true));  // row_shr:1
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x112, 0xf, 0xf, true));  // row_shr:2
+  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xf, true));  // row_shr:4
+  const int g = __builtin_amdgcn_ds_bpermute(r << 2, row_g);
+  const int c = __builtin_amdgcn_ds_bpermute(r << 2, row_c);
+  if (part == 7 && r < n && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)g * GG + c, t);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Adjoint of the forward blend, back to front from each pixel's stopping
@@ -304,10 +343,13 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  char* mine_lds = smem + (size_t)wv * (64 * E) * BWD_ENTRY_BYTES;
+  char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(E);
   float4* wgeo = (float4*)mine_lds;
   float4* wpc = wgeo + 64 * E;
   int4* wmeta = (int4*)(wpc + 64 * E);  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
+  float* park = (float*)(wmeta + 64 * E);  // [RB][RB_ROW] parked gradient values
+  int n_rows = 0;                          // parked rows (wavefront-uniform)
+  int row_g = 0, row_c = 0;                // lane r: Gaussian and value index of row r
   const uint64_t below = lanes_below();
   float* __restrict__ ggrad = w.ggrad;
   for (int it = 0;; ++it) {
@@ -352,8 +394,6 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     int cur = -1, since = 0;
     bool cur_fill = false;
     float accC[3] = {0.0f, 0.0f, 0.0f}, accO = 0.0f;
-    int pend_g = -1;  // fill Gaussian whose dL/do_j awaits its reduction
-    float pend_v = 0.0f;
     Entry e[E];
     int base = lo;
 #pragma unroll
@@ -441,31 +481,33 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
           }
         }
         if (__ballot(act) == 0ull) continue;
+        // park the values still to be summed over the wavefront
+        const int need = fill ? 1 : 3;
+        if (n_rows + need > RB) {
+          flush_rows(park, n_rows, row_g, row_c, ggrad);
+          n_rows = 0;
+        }
+        // lanes n_rows .. n_rows + need - 1 describe the new rows
+        const unsigned rel = (unsigned)(lane - n_rows);
+        const bool mine = rel < (unsigned)need;
         if (fill) {
-          // fill Gaussians carry one value; two of them are reduced together
-          if (pend_g < 0) {
-            pend_g = ~gsig;
-            pend_v = v[3];
-          } else {
-            const float vv[2] = {pend_v, v[3]};
-            const float t = wave_totals_to_lanes<2>(vv);
-            const int gd = lane == 0 ? pend_g : ~gsig;
-            if (lane < 2 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)gd * GG + 3, t);
-            pend_g = -1;
-          }
+          park[n_rows * RB_ROW + lane] = v[3];
+          row_g = mine ? ~gsig : row_g;
+          row_c = mine ? 3 : row_c;
         } else {
           accO += v[3];
-          const float vv[3] = {v[0], v[1], v[2]};
-          const float t = wave_totals_to_lanes<3>(vv);
-          if (lane < 3 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)gsig * GG + lane, t);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) park[(n_rows + i) * RB_ROW + lane] = v[i];
+          row_g = mine ? gsig : row_g;
+          row_c = mine ? (int)rel : row_c;
         }
+        n_rows = __builtin_amdgcn_readfirstlane(n_rows + need);
       }
       __builtin_amdgcn_wave_barrier();
     }
-    if (pend_g >= 0) {
-      const float vv[1] = {pend_v};
-      const float t = wave_totals_to_lanes<1>(vv);
-      if (lane < 1 && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)pend_g * GG + 3 + lane, t);
+    if (n_rows > 0) {
+      flush_rows(park, n_rows, row_g, row_c, ggrad);
+      n_rows = 0;
     }
     if (cur >= 0) flush_curve<C>(w.gcurve, cur, cur_fill, accC, accO);
   }
@@ -507,7 +549,7 @@ template <int C, int TILE, int E>
 hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
   const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
   if (n_items <= 0) return hipSuccess;
-  const size_t lds = (size_t)WPB * 64 * E * BWD_ENTRY_BYTES;
+  const size_t lds = (size_t)WPB * bwd_wave_bytes(E);
   int grid = (n_items + WPB - 1) / WPB;
   if (persistent) {
     grid = resident_grid(k_blend_bwd<C, TILE, E>, grid, L.n_cu, lds);
