@@ -336,11 +336,15 @@ int nsplat_l2_grad(nsplat_ctx* ctx, const float* a, const float* b, float* out, 
 
 /* Per-phase timing.  nsplat_timing(ctx, 1) starts recording a HIP event pair
  * around every NSPLAT_T_* phase the library launches (on that call's stream)
- * and clears the sums; nsplat_timing(ctx, 0) stops.  nsplat_timing_read waits
+ * and clears the sums; nsplat_timing(ctx, NSPLAT_TIMING_ONLY | mask) records
+ * only the phases whose bits (1 << NSPLAT_T_*) are set in mask, so that one
+ * kernel can be timed inside an otherwise unobserved run;
+ * nsplat_timing(ctx, 0) stops.  nsplat_timing_read waits
  * for the recorded events, adds their elapsed times to ms[NSPLAT_NUM_TIMERS]
  * and launch counts to count[NSPLAT_NUM_TIMERS] (host arrays, overwritten
  * with the sums since the last enable) and recycles the events.  Not for use
  * under graph capture. */
+#define NSPLAT_TIMING_ONLY 0x40000000
 int nsplat_timing(nsplat_ctx* ctx, int enable);
 int nsplat_timing_read(nsplat_ctx* ctx, double* ms, int64_t* count);
 

@@ -402,6 +402,8 @@ int nsplat_timing(nsplat_ctx* ctx, int enable) {
   if (!ctx) return NSPLAT_EINVAL;
   Timer& t = ctx->timer;
   t.on = enable != 0;
+  t.mask = (enable & NSPLAT_TIMING_ONLY) ? (uint32_t)enable & ((1u << NSPLAT_NUM_TIMERS) - 1u)
+                                         : (1u << NSPLAT_NUM_TIMERS) - 1u;
   t.used = 0;
   t.n_spans = 0;
   for (int i = 0; i < NSPLAT_NUM_TIMERS; ++i) {

@@ -250,6 +250,7 @@ __device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) 
 // bracketed by two events on the launch stream; sums are read back on demand.
 struct Timer {
   bool on = false;
+  uint32_t mask = 0;  // phases recorded while on (bit NSPLAT_T_*)
   hipEvent_t* pool = nullptr;
   int cap = 0, used = 0;
   int span_id[4096];
@@ -298,8 +299,10 @@ struct Phase {
   Timer* t;
   int id;
   hipStream_t s;
-  Phase(const Launch& L, int i) : t(L.tm), id(i), s(L.stream) { if (t && t->on) timer_begin(t, id, s); }
-  ~Phase() { if (t && t->on) timer_end(t, id, s); }
+  Phase(const Launch& L, int i) : t(L.tm && L.tm->on && ((L.tm->mask >> i) & 1u) ? L.tm : nullptr), id(i), s(L.stream) {
+    if (t) timer_begin(t, id, s);
+  }
+  ~Phase() { if (t) timer_end(t, id, s); }
 };
 
 inline int grid_for(int64_t n, int threads, int max_blocks) {
