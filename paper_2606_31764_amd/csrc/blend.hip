@@ -363,7 +363,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const int x0 = (lt % st.tiles_x) * TILE, y0 = (lt / st.tiles_x) * TILE;
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const int64_t plane = (int64_t)st.H * st.W;
-    float px[PPT], py[PPT], T[PPT], A[PPT][3], gI[PPT][3];
+    // S: the loss gradient dotted with the colour composited behind the
+    // current entry, sum_c dL/dI_c A_c (the A_c themselves are not needed)
+    float px[PPT], py[PPT], T[PPT], S[PPT], gI[PPT][3];
     int stop[PPT];
     int my_lo = end;
 #pragma unroll
@@ -374,18 +376,18 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
       py[q] = (float)ly;
       T[q] = 1.0f;
       stop[q] = end;  // invalid pixels never take part
+      S[q] = 0.0f;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        A[q][c] = c < C ? bg[s * C + c] : 0.0f;
-        gI[q][c] = 0.0f;
-      }
+      for (int c = 0; c < 3; ++c) gI[q][c] = 0.0f;
       if (x0 + lx < st.W && y0 + ly < st.H) {
         const int64_t pix = (int64_t)st.pix_off + (int64_t)(y0 + ly) * st.W + (x0 + lx);
         T[q] = Tfin[pix];
         stop[q] = nlast[pix];
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+        for (int c = 0; c < C; ++c) {
           gI[q][c] = dL[(int64_t)st.pix_off * C + c * plane + (int64_t)(y0 + ly) * st.W + (x0 + lx)];
+          S[q] = __builtin_fmaf(gI[q][c], bg[s * C + c], S[q]);
+        }
         my_lo = min(my_lo, stop[q]);
       }
     }
@@ -463,13 +465,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
           // only, so the loop-carried chain is one multiply (unchanged when alpha = 0)
           T[q] = T[q] * (in ? __builtin_amdgcn_rcpf(onem) : 1.0f);
           const float aT = alpha * T[q];
-          float dLda = 0.0f;
+          // dL/dalpha / T = sum_c dL/dI_c (col_c - A_c) = K - S, and the colour
+          // behind the next entry A_c' = alpha col_c + (1 - alpha) A_c gives
+          // S' = alpha K + (1 - alpha) S
+          float K = 0.0f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            dLda = __builtin_fmaf(gI[q][c], col[c] - A[q][c], dLda);
+            K = __builtin_fmaf(gI[q][c], col[c], K);
             accC[c] = __builtin_fmaf(gI[q][c], aT, accC[c]);
-            A[q][c] = __builtin_fmaf(alpha, col[c], onem * A[q][c]);
           }
+          float dLda = K - S[q];
+          S[q] = __builtin_fmaf(alpha, K, onem * S[q]);
           dLda = (in && oG < amax) ? dLda * T[q] : 0.0f;
           v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
           if (!fill) {

@@ -241,3 +241,38 @@ def test_capacity_overflow_without_growth_is_flagged_and_consistent():
     np.testing.assert_array_equal(rec["local"], ref["local"][:n])
     assert np.array_equal(rec["mu"], ref["mu"][:n])
     assert all(torch.isfinite(g).all().item() for g in grads)
+
+
+def test_timing_mask_records_only_selected_phases():
+    """nsplat_timing with NSPLAT_TIMING_ONLY | mask records event pairs around the
+    masked phases alone; plain enable records every phase of the step."""
+    import ctypes
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=2950, n_paths=6, size=64)
+    p = Params().replace(h=2.0)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    img = r.run_forward(t)
+    c = r.ctx
+    only, bwd_id, n_timers = 0x40000000, 6, 11
+
+    def step_counts(enable):
+        c.check(c.lib.nsplat_timing(c.h, enable))
+        r.sample(t, sync=False)
+        r.bin(t, sync=False)
+        im = r.forward(t)
+        r.backward(t, 2.0 * (im - 0.5))
+        torch.cuda.synchronize()
+        ms = (ctypes.c_double * n_timers)()
+        n = (ctypes.c_int64 * n_timers)()
+        c.check(c.lib.nsplat_timing_read(c.h, ms, n))
+        c.check(c.lib.nsplat_timing(c.h, 0))
+        return list(n), list(ms)
+
+    n_all, _ = step_counts(1)
+    assert all(n_all[i] >= 1 for i in range(10))  # every phase but the regulariser
+    n_one, ms_one = step_counts(only | (1 << bwd_id))
+    assert n_one[bwd_id] == 1 and ms_one[bwd_id] > 0.0
+    assert sum(n_one) == 1
+    assert bool(torch.isfinite(img).all())
