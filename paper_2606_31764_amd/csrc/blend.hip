@@ -100,12 +100,13 @@ constexpr int FWD_ENTRY_BYTES = 36;   // geometry, opacity + colour, list positi
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
 // The adjoint parks the per-lane gradient values it still has to sum over
 // the wavefront in LDS rows of 64 floats, one row per value (three for a
-// stroke Gaussian, one for a fill Gaussian), and sums RB rows at a time (see
-// flush_rows).  Rows are padded to 72 floats so that the flush's eight rows
-// fall into different banks.
-constexpr int RB = 8;
-constexpr int RB_ROW = 72;            // floats per parked row
-constexpr size_t BWD_PARK_BYTES = (size_t)RB * RB_ROW * 4;
+// stroke Gaussian, one for a fill Gaussian), each with its (Gaussian, value
+// index) target, and sums RB rows at a time (see flush_rows).  Rows are
+// padded to 68 floats so that the flush's reads of the RB rows fall into
+// different banks.
+constexpr int RB = 16;
+constexpr int RB_ROW = 68;            // floats per parked row
+constexpr size_t BWD_PARK_BYTES = (size_t)RB * RB_ROW * 4 + (size_t)RB * 8;
 __host__ __device__ constexpr size_t bwd_wave_bytes(int E) {
   return ((size_t)64 * E * BWD_ENTRY_BYTES + BWD_PARK_BYTES + 15) / 16 * 16;
 }
@@ -297,27 +298,26 @@ __device__ inline void flush_curve(double* gcurve, int c, bool fill, float (&acc
 }
 
 // Sums the first n (<= RB) parked rows over the 64 lanes and adds each total
-// to its adjoint value ggrad[row_g * GG + row_c] (row_g, row_c: lane r of
-// those registers describes row r).  Lane (r, part) = (lane / 8, lane % 8)
-// adds up floats part, part + 8, ... of row r; DPP row shifts finish the sum
-// in the group's last lane, which issues the atomic.  Every lane of the
-// wavefront must call it.
-__device__ inline void flush_rows(const float* park, int n, int row_g, int row_c, float* __restrict__ ggrad) {
-  static_assert(RB * 8 == 64, "eight lanes per parked row");
+// to its target ggrad[g * GG + value] (tgt[row] = (g, value)).  Lane (r, part)
+// = (lane / 4, lane % 4) adds up floats part, part + 4, ..., part + 60 of row
+// r; two DPP row shifts finish the sum in the quad's last lane, which issues
+// the atomic.  Every lane of the wavefront must call it.
+__device__ inline void flush_rows(const float* park, const int2* tgt, int n, float* __restrict__ ggrad) {
+  static_assert(RB * 4 == 64, "four lanes per parked row");
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int lane = __lane_id(), r = lane >> 3, part = lane & 7;
+  const int lane = __lane_id(), r = lane >> 2, part = lane & 3;
   const float* row = park + r * RB_ROW + part;
   float t = 0.0f;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) t += row[8 * j];
+  for (int j = 0; j < 16; ++j) t += row[4 * j];
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x111, 0xf, 0xf, true));  // row_shr:1
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x112, 0xf, 0xf, true));  // row_shr:2
-  t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xf, true));  // row_shr:4
-  const int g = __builtin_amdgcn_ds_bpermute(r << 2, row_g);
-  const int c = __builtin_amdgcn_ds_bpermute(r << 2, row_c);
-  if (part == 7 && r < n && t != 0.0f) unsafeAtomicAdd(ggrad + (int64_t)g * GG + c, t);
+  if (part == 3 && r < n && t != 0.0f) {
+    const int2 tg = tgt[r];
+    unsafeAtomicAdd(ggrad + (int64_t)tg.x * GG + tg.y, t);
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -348,8 +348,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   float4* wpc = wgeo + 64 * E;
   int4* wmeta = (int4*)(wpc + 64 * E);  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
   float* park = (float*)(wmeta + 64 * E);  // [RB][RB_ROW] parked gradient values
+  int2* ptgt = (int2*)(park + RB * RB_ROW);  // [RB] their (Gaussian, value index) targets
   int n_rows = 0;                          // parked rows (wavefront-uniform)
-  int row_g = 0, row_c = 0;                // lane r: Gaussian and value index of row r
   const uint64_t below = lanes_below();
   float* __restrict__ ggrad = w.ggrad;
   for (int it = 0;; ++it) {
@@ -490,29 +490,24 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         // park the values still to be summed over the wavefront
         const int need = fill ? 1 : 3;
         if (n_rows + need > RB) {
-          flush_rows(park, n_rows, row_g, row_c, ggrad);
+          flush_rows(park, ptgt, n_rows, ggrad);
           n_rows = 0;
         }
-        // lanes n_rows .. n_rows + need - 1 describe the new rows
-        const unsigned rel = (unsigned)(lane - n_rows);
-        const bool mine = rel < (unsigned)need;
         if (fill) {
           park[n_rows * RB_ROW + lane] = v[3];
-          row_g = mine ? ~gsig : row_g;
-          row_c = mine ? 3 : row_c;
+          if (lane == 0) ptgt[n_rows] = make_int2(~gsig, 3);
         } else {
           accO += v[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) park[(n_rows + i) * RB_ROW + lane] = v[i];
-          row_g = mine ? gsig : row_g;
-          row_c = mine ? (int)rel : row_c;
+          if (lane < 3) ptgt[n_rows + lane] = make_int2(gsig, lane);
         }
         n_rows = __builtin_amdgcn_readfirstlane(n_rows + need);
       }
       __builtin_amdgcn_wave_barrier();
     }
     if (n_rows > 0) {
-      flush_rows(park, n_rows, row_g, row_c, ggrad);
+      flush_rows(park, ptgt, n_rows, ggrad);
       n_rows = 0;
     }
     if (cur >= 0) flush_curve<C>(w.gcurve, cur, cur_fill, accC, accO);
