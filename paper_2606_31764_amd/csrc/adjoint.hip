@@ -212,16 +212,6 @@ __device__ inline void accumulate_curve(const Work& w, int64_t key, int c, const
   }
 }
 
-__device__ inline int curve_of(const int32_t* goff, int n, int64_t g) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (goff[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Stroke Gaussians: dL/d(mu, sigma) -> the curve point adjoint at u_j.
 __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_params pr, Work w,
                                                     const int32_t* plan, const int32_t* counters,

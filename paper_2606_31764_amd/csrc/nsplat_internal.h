@@ -233,6 +233,45 @@ __device__ inline double sample_u(double a, double b, int j, int count, bool clo
 __device__ inline float read_h(const nsplat_params& pr) { return pr.h_dev ? *pr.h_dev : pr.h; }
 
 // Scene of a global tile index (binary search over the scene table).
+// The curve of Gaussian g: the last c with goff[c] <= g (goff ascending,
+// goff[0] = 0).
+__device__ inline int curve_search(const int32_t* goff, int n, int64_t g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (goff[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The same for a wavefront whose active lanes hold ascending g: one search
+// for the first active lane's g (wavefront-uniform; goff is read through the
+// constant address space, so the loads are scalar), then each lane steps
+// forward over at most 8 curve starts; a lane that would need more, or holds
+// a smaller g, searches alone.  goff must not change during the kernel.
+__device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) {
+  typedef const __attribute__((address_space(4))) int32_t* const_i32;
+  const const_i32 cg = (const_i32)goff;
+  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g);
+  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)g >> 32));
+  const int64_t g0 = (int64_t)(((uint64_t)hi32 << 32) | lo32);
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cg[mid] <= g0) lo = mid;
+    else hi = mid - 1;
+  }
+  const int c0 = lo;
+  if (g < g0) return curve_search(goff, n, g);
+  int c = c0;
+  for (int k = 0; k < 8; ++k) {
+    if (c + 1 >= n || goff[c + 1] > g) return c;
+    ++c;
+  }
+  return curve_search(goff, n, g);
+}
+
 __device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) {
   int lo = 0, hi = n_scenes - 1;
   while (lo < hi) {

@@ -383,14 +383,7 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
   const bool capped = (int64_t)counters[NSPLAT_CNT_GAUSS_REQ] > G;
   const int n = cv.n_curves;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
-    // curve: the last c with goff[c] <= g
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (w.goff[mid] <= g) lo = mid;
-      else hi = mid - 1;
-    }
-    const int c = lo;
+    const int c = curve_of_wave(w.goff, n, g);  // the last c with goff[c] <= g
     const CurveView v = curve_view(cv, w.knots, c);
     const int32_t* row = plan + (int64_t)P_STRIDE * c;
     const int local = (int)(g - w.goff[c]);
