@@ -28,7 +28,10 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   const int64_t N = cv->n_curves, K = cv->n_keys, T = cv->n_taus, S = sc->n_scenes;
   const int64_t gcap = caps->gauss, pcap = caps->pairs, bcap = caps->boundary;
   lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
-  const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, 1});
+  const int64_t tiles8 = nsplat_num_tiles(sc, 8);
+  int64_t n_pix = 0;
+  for (int s = 0; s < sc->n_scenes; ++s) n_pix += (int64_t)sc->hw_host[2 * s] * sc->hw_host[2 * s + 1];
+  const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, tiles8 + 1, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
   const size_t sizes[N_WS] = {
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
@@ -50,9 +53,13 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(int32_t) * 64,                                // queue
       sizeof(int32_t) * (size_t)std::max<int64_t>(gcap, 1),  // aux
       sizeof(double4) * (size_t)(bcap / SDF_CHUNK + 2 * N + 2),  // cbox
-      sizeof(int32_t) * (size_t)std::max<int64_t>(nsplat_num_tiles(sc, 8), 1),  // order
+      sizeof(int32_t) * (size_t)std::max<int64_t>(tiles8, 1),  // order
       sizeof(int32_t) * 64,                                // obin
       sizeof(double) * (size_t)(S + 1),                    // sacc
+      sizeof(int32_t) * (size_t)(tiles8 + 1),              // ck_off
+      sizeof(int32_t) * (size_t)(tiles8 + 1),              // item_off
+      sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
+      sizeof(float) * 3 * (size_t)std::max<int64_t>(n_pix, 1),  // afin
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -88,6 +95,10 @@ Work carve(void* ws, const Layout& lay) {
   w.order = (int32_t*)(b + lay.off[19]);
   w.obin = (int32_t*)(b + lay.off[20]);
   w.sacc = (double*)(b + lay.off[21]);
+  w.ck_off = (int32_t*)(b + lay.off[22]);
+  w.item_off = (int32_t*)(b + lay.off[23]);
+  w.ckbuf = (float*)(b + lay.off[24]);
+  w.afin = (float*)(b + lay.off[25]);
   return w;
 }
 

@@ -8,6 +8,8 @@
 //                 Gaussian order
 //   k_tile_ranges [begin, end) of every tile's slice
 //   k_order_*     the blend kernels' tile order, longest lists first
+//   k_chunk_counts, k_item_counts + scans: checkpoint slots per tile and the
+//                 adjoint's (tile, quadrant, chunk) items in blend order
 #include "nsplat_internal.h"
 
 namespace nsp {
@@ -231,6 +233,23 @@ __global__ __launch_bounds__(256) void k_order_scatter(const int32_t* __restrict
   if (t < n_tiles) order[base[k] + r] = t;
 }
 
+// Forward-state checkpoints of tile t: one per chunk boundary inside its list.
+__global__ void k_chunk_counts(const int32_t* __restrict__ ranges, int n_tiles, uint32_t* __restrict__ ck) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
+    const int n = n_chunks(ranges[2 * t + 1] - ranges[2 * t]);
+    ck[t] = n > 0 ? (uint32_t)(n - 1) : 0u;
+  }
+}
+
+// Adjoint work items of the tile at blend-order position i: quadrants x chunks.
+__global__ void k_item_counts(const int32_t* __restrict__ ranges, const int32_t* __restrict__ order, int n_tiles,
+                              int quads, uint32_t* __restrict__ items) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += gridDim.x * blockDim.x) {
+    const int t = order[i];
+    items[i] = (uint32_t)(quads * n_chunks(ranges[2 * t + 1] - ranges[2 * t]));
+  }
+}
+
 }  // namespace
 
 hipError_t launch_bin(const Launch& L) {
@@ -290,6 +309,16 @@ hipError_t launch_bin(const Launch& L) {
       hipLaunchKernelGGL(k_order_count, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin);
       hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, L.stream, L.w.obin);
       hipLaunchKernelGGL(k_order_scatter, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin, L.w.order);
+      const int cb = grid_for(nt, 256, 4096);
+      hipLaunchKernelGGL(k_chunk_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, nt, (uint32_t*)L.w.ck_off);
+      e = launch_scan((uint32_t*)L.w.ck_off, nullptr, nt, (uint32_t*)L.w.ck_off + nt, L.w.scan_tmp, L.stream);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_item_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, L.w.order, nt,
+                         L.pr->tile == 8 ? 1 : 4, (uint32_t*)L.w.item_off);
+      e = launch_scan((uint32_t*)L.w.item_off, nullptr, nt, (uint32_t*)L.w.item_off + nt, L.w.scan_tmp, L.stream);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.item_off, 0, (int64_t)1);
     }
   }
   return hipGetLastError();

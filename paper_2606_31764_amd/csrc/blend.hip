@@ -111,6 +111,14 @@ __host__ __device__ constexpr size_t bwd_wave_bytes(int E) {
   return ((size_t)64 * E * BWD_ENTRY_BYTES + BWD_PARK_BYTES + 15) / 16 * 16;
 }
 
+// Lower end of the step that starts at list position h (walking down from
+// the list end): at most `depth` entries, not below `start`, and not across
+// the boundary of h's chunk.
+__device__ inline int step_floor(int h, int start, int depth, int end) {
+  const int k = (end - h) / CK;
+  return max(max(start, h - depth), end - (k + 1) * CK);
+}
+
 template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
@@ -153,13 +161,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       done[q] = !(x0 + lx < st.W && y0 + ly < st.H);
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
-    // front to back: list positions end-1 down to start, `depth` per step
+    // front to back: list positions end-1 down to start, at most `depth` per
+    // step and never across a chunk boundary, where the state is stored
+    const int ck0 = w.ck_off[tile];
     Entry e[E];
-    int hi = end;
+    int hi = end, lo_s = step_floor(hi, start, depth, end);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
-      load_entry<C>(idx, gs, cv, hi - 1 - k, k < depth && hi - 1 - k >= start, &e[u]);
+      load_entry<C>(idx, gs, cv, hi - 1 - k, k < hi - lo_s, &e[u]);
     }
     while (hi > start) {
       int cnt = 0;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
         const int mypos = hi - 1 - k;
-        const bool ok = k < depth && mypos >= start;
+        const bool ok = k < hi - lo_s;
         float4 geo;
         const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
         const uint64_t m = __ballot(keep);
@@ -179,11 +189,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         }
         cnt += __popcll(m);
       }
-      hi -= depth;
+      const int nhi = lo_s, nlo = step_floor(nhi, start, depth, end);
 #pragma unroll
       for (int u = 0; u < E; ++u) {  // next step, in flight while this one is composited
         const int k = u * 64 + lane;
-        load_entry<C>(idx, gs, cv, hi - 1 - k, k < depth && hi - 1 - k >= start, &e[u]);
+        load_entry<C>(idx, gs, cv, nhi - 1 - k, k < nhi - nlo, &e[u]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -220,6 +230,19 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         if (jstop[q] >= 0) stop[q] = wpos[jstop[q]];
         mine = mine && done[q];
       }
+      hi = nhi;
+      lo_s = nlo;
+      if (hi > start && (end - hi) % CK == 0) {
+        // state in front of chunk (end - hi) / CK: T and the accumulated colour
+        float* ckp = w.ckbuf + (int64_t)(ck0 + (end - hi) / CK - 1) * (4 * TILE * TILE);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const int slot = (quad * PPT + q) * 64 + lane;
+          ckp[slot] = T[q];
+#pragma unroll
+          for (int c = 0; c < C; ++c) ckp[(1 + c) * TILE * TILE + slot] = acc[q][c];
+        }
+      }
       __builtin_amdgcn_wave_barrier();
       if (__ballot(!mine) == 0ull) break;  // every pixel of the quadrant has stopped
     }
@@ -232,9 +255,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         const int64_t pix = (int64_t)st.pix_off + (int64_t)y * st.W + x;
         const int64_t plane = (int64_t)st.H * st.W;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-          image[(int64_t)st.pix_off * C + c * plane + (int64_t)y * st.W + x] =
-              __builtin_fmaf(T[q], bg[s * C + c], acc[q][c]);
+        for (int c = 0; c < C; ++c) {
+          const int64_t o = (int64_t)st.pix_off * C + c * plane + (int64_t)y * st.W + x;
+          image[o] = __builtin_fmaf(T[q], bg[s * C + c], acc[q][c]);
+          w.afin[o] = acc[q][c];
+        }
         Tfin[pix] = T[q];
         nlast[pix] = stop[q];
       }
@@ -323,15 +348,22 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Adjoint of the forward blend, back to front from each pixel's stopping
-// position.  Per Gaussian it accumulates dL/dmu and dL/dsigma for stroke
-// Gaussians and dL/do_j for fill Gaussians (whose own opacity carries the
-// SDF); colour gradients (and a stroke curve's opacity gradient, its o_j all
-// being o) belong to the curve, so each lane keeps running per-curve sums that
-// are flushed when the curve changes along the list or every FLUSH entries.
+// Adjoint of the forward blend, one work item per (tile, quadrant, chunk).
+// Inside a chunk it walks front to back like the forward and starts from the
+// forward's state at the chunk boundary, so T follows the forward's own
+// products.  With K = sum_c dL/dI_c col_c and U the loss-weighted colour
+// accumulated in front (U += K alpha T), Eq. 8 gives
+//   dL/dalpha = T K - (R - U) / (1 - alpha),   R = sum_c dL/dI_c I_c,
+// R - U being the loss-weighted colour still to come behind the entry (the
+// back layers and the background).  Per Gaussian it accumulates dL/dmu and
+// dL/dsigma for stroke Gaussians and dL/do_j for fill Gaussians (whose own
+// opacity carries the SDF); colour gradients (and a stroke curve's opacity
+// gradient, its o_j all being o) belong to the curve, so each lane keeps
+// running per-curve sums that are flushed when the curve changes along the
+// list or every FLUSH entries.
 template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
-    nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
+    nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
     int persistent) {
@@ -352,20 +384,34 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   int n_rows = 0;                          // parked rows (wavefront-uniform)
   const uint64_t below = lanes_below();
   float* __restrict__ ggrad = w.ggrad;
+  typedef const __attribute__((address_space(4))) int32_t* const_i32;
+  const const_i32 item_off = (const_i32)w.item_off;  // not written during the kernel: scalar loads
+  const int n_items = item_off[n_tiles];
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
     if (item >= n_items) break;
-    const int tq = item / Cfg::QUADS, quad = item - tq * Cfg::QUADS;
+    // blend-order position of the item's tile: the last i with item_off[i] <= item
+    int tq = 0;
+    {
+      int lo_t = 0, hi_t = n_tiles - 1;
+      while (lo_t < hi_t) {
+        const int mid = (lo_t + hi_t + 1) >> 1;
+        if (item_off[mid] <= item) lo_t = mid;
+        else hi_t = mid - 1;
+      }
+      tq = lo_t;
+    }
+    const int r_it = item - item_off[tq];
+    const int quad = r_it % Cfg::QUADS, kc = r_it / Cfg::QUADS;
     const int tile = w.order[tq];
     const int s = scene_of_tile(w.scenes, n_scenes, tile);
     const SceneTab st = w.scenes[s];
     const int lt = tile - st.tile_off;
     const int x0 = (lt % st.tiles_x) * TILE, y0 = (lt / st.tiles_x) * TILE;
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const int c_hi = end - kc * CK, c_lo = max(start, end - (kc + 1) * CK);  // the chunk's positions
     const int64_t plane = (int64_t)st.H * st.W;
-    // S: the loss gradient dotted with the colour composited behind the
-    // current entry, sum_c dL/dI_c A_c (the A_c themselves are not needed)
-    float px[PPT], py[PPT], T[PPT], S[PPT], gI[PPT][3];
+    float px[PPT], py[PPT], T[PPT], U[PPT], R[PPT], gI[PPT][3];
     int stop[PPT];
     int my_lo = end;
 #pragma unroll
@@ -375,41 +421,56 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
       px[q] = (float)lx;
       py[q] = (float)ly;
       T[q] = 1.0f;
+      U[q] = 0.0f;
+      R[q] = 0.0f;
       stop[q] = end;  // invalid pixels never take part
-      S[q] = 0.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) gI[q][c] = 0.0f;
       if (x0 + lx < st.W && y0 + ly < st.H) {
         const int64_t pix = (int64_t)st.pix_off + (int64_t)(y0 + ly) * st.W + (x0 + lx);
-        T[q] = Tfin[pix];
+        const float tf = Tfin[pix];
         stop[q] = nlast[pix];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          gI[q][c] = dL[(int64_t)st.pix_off * C + c * plane + (int64_t)(y0 + ly) * st.W + (x0 + lx)];
-          S[q] = __builtin_fmaf(gI[q][c], bg[s * C + c], S[q]);
+          const int64_t o = (int64_t)st.pix_off * C + c * plane + (int64_t)(y0 + ly) * st.W + (x0 + lx);
+          gI[q][c] = dL[o];
+          R[q] = __builtin_fmaf(gI[q][c], __builtin_fmaf(tf, bg[s * C + c], w.afin[o]), R[q]);
         }
         my_lo = min(my_lo, stop[q]);
       }
     }
-    const int lo = max(wave_min(my_lo), start);
-    const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
+    // positions below every pixel's stopping position take no part
+    const int lo = max(wave_min(my_lo), c_lo);
+    if (c_hi <= lo) continue;
+    if (kc > 0) {  // the forward's state in front of this chunk
+      const float* ckp = w.ckbuf + (int64_t)(w.ck_off[tile] + kc - 1) * (4 * TILE * TILE);
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int slot = (quad * PPT + q) * 64 + lane;
+        T[q] = ckp[slot];
+#pragma unroll
+        for (int c = 0; c < C; ++c) U[q] = __builtin_fmaf(gI[q][c], ckp[(1 + c) * TILE * TILE + slot], U[q]);
+      }
+    }
     int cur = -1, since = 0;
     bool cur_fill = false;
     float accC[3] = {0.0f, 0.0f, 0.0f}, accO = 0.0f;
+    const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
+    // front to back over the chunk's positions c_hi - 1 down to lo
     Entry e[E];
-    int base = lo;
+    int hi = c_hi, lo_s = max(lo, hi - depth);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
-      load_entry<C>(idx, gs, cv, base + k, k < depth && base + k < end, &e[u]);
+      load_entry<C>(idx, gs, cv, hi - 1 - k, k < hi - lo_s, &e[u]);
     }
-    while (base < end) {
+    while (hi > lo) {
       int cnt = 0;
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
-        const int mypos = base + k;
-        const bool ok = k < depth && mypos < end;
+        const int mypos = hi - 1 - k;
+        const bool ok = k < hi - lo_s;
         float4 geo;
         const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
         const uint64_t m = __ballot(keep);
@@ -423,11 +484,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         }
         cnt += __popcll(m);
       }
-      base += depth;
+      const int nhi = lo_s, nlo = max(lo, nhi - depth);
 #pragma unroll
       for (int u = 0; u < E; ++u) {  // next step, in flight while this one is processed
         const int k = u * 64 + lane;
-        load_entry<C>(idx, gs, cv, base + k, k < depth && base + k < end, &e[u]);
+        load_entry<C>(idx, gs, cv, nhi - 1 - k, k < nhi - nlo, &e[u]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -461,22 +522,16 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
           const float oG = pc.x * G;
           const float alpha = in ? fminf(amax, oG) : 0.0f;
           const float onem = 1.0f - alpha;
-          // transmittance in front of this Gaussian; the reciprocal depends on alpha
-          // only, so the loop-carried chain is one multiply (unchanged when alpha = 0)
-          T[q] = T[q] * (in ? __builtin_amdgcn_rcpf(onem) : 1.0f);
           const float aT = alpha * T[q];
-          // dL/dalpha / T = sum_c dL/dI_c (col_c - A_c) = K - S, and the colour
-          // behind the next entry A_c' = alpha col_c + (1 - alpha) A_c gives
-          // S' = alpha K + (1 - alpha) S
           float K = 0.0f;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             K = __builtin_fmaf(gI[q][c], col[c], K);
             accC[c] = __builtin_fmaf(gI[q][c], aT, accC[c]);
           }
-          float dLda = K - S[q];
-          S[q] = __builtin_fmaf(alpha, K, onem * S[q]);
-          dLda = (in && oG < amax) ? dLda * T[q] : 0.0f;
+          U[q] = __builtin_fmaf(K, aT, U[q]);
+          const float dLda = (in && oG < amax) ? T[q] * K - (R[q] - U[q]) * __builtin_amdgcn_rcpf(onem) : 0.0f;
+          T[q] = T[q] * onem;
           v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
           if (!fill) {
             const float dG = dLda * pc.x;
@@ -505,6 +560,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         n_rows = __builtin_amdgcn_readfirstlane(n_rows + need);
       }
       __builtin_amdgcn_wave_barrier();
+      hi = nhi;
+      lo_s = nlo;
     }
     if (n_rows > 0) {
       flush_rows(park, ptgt, n_rows, ggrad);
@@ -548,18 +605,20 @@ hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last,
 
 template <int C, int TILE, int E>
 hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
-  const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
-  if (n_items <= 0) return hipSuccess;
+  if (L.n_tiles <= 0) return hipSuccess;
+  // the item count lives on the device; the grid covers its bound
+  // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
+  const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * (L.bf->caps.pairs / CK + L.n_tiles);
   const size_t lds = (size_t)WPB * bwd_wave_bytes(E);
-  int grid = (n_items + WPB - 1) / WPB;
+  int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {
     grid = resident_grid(k_blend_bwd<C, TILE, E>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_BWD);
   hipLaunchKernelGGL((k_blend_bwd<C, TILE, E>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
-                     L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, dL,
-                     T_final, n_last, persistent);
+                     L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
+                     dL, T_final, n_last, persistent);
   return hipGetLastError();
 }
 

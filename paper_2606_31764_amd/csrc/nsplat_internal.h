@@ -18,7 +18,7 @@ constexpr double LN2 = 0.69314718055994530942;
 constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 22;                // workspace entries
+constexpr int N_WS = 26;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -60,7 +60,20 @@ struct Work {
   int32_t* order;      // [tiles at the smallest tile size] tiles by decreasing list length
   int32_t* obin;       // [64] list-length class counts, then their offsets
   double* sacc;        // [n_scenes + 1] per-scene sums (distance-weighted loss)
+  int32_t* ck_off;     // [tiles at the smallest tile size + 1] first checkpoint of each tile (scan)
+  int32_t* item_off;   // [tiles at the smallest tile size + 1] first adjoint item of each tile in blend order (scan)
+  float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries
+  float* afin;         // [pixels][3] accumulated colour at each pixel's end of compositing
 };
+
+// The compositing lists are cut into chunks of CK list positions, counted
+// from each tile's front (list end): chunk k holds the positions
+// [end - (k + 1) CK, end - k CK).  The forward stores every pixel's state at
+// the chunk boundaries it passes, and the adjoint runs one work item per
+// (tile, quadrant, chunk), so that a long list no longer sets the length of
+// the adjoint pass.
+constexpr int CK = 512;
+__host__ __device__ inline int n_chunks(int len) { return (len + CK - 1) / CK; }
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
 // boundary point boff) has a header at cbox_base(boff, c) holding the box
