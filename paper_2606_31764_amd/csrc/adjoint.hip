@@ -472,9 +472,20 @@ __global__ __launch_bounds__(64) void k_fold(nsplat_curves cv, Work w, nsplat_gr
   }
 }
 
-__global__ void k_zero_f64(double* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
+// Zeroes up to four FP64 arrays in one launch (index space n0 + n1 + n2 + n3).
+struct ZeroSet {
+  double* p[4];
+  int64_t n[4];
+};
+
+__global__ void k_zero_f64(ZeroSet z) {
+  const int64_t total = z.n[0] + z.n[1] + z.n[2] + z.n[3];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = i;
+    int a = 0;
+    while (a < 3 && j >= z.n[a]) j -= z.n[a++];
+    z.p[a][j] = 0.0;
+  }
 }
 
 __global__ void k_zero_dev(float* p, const int32_t* count, int64_t mult, int64_t cap) {
@@ -948,13 +959,17 @@ hipError_t launch_zero_grads(const Launch& L) {
   const int64_t nkn = (int64_t)cv.n_taus + (int64_t)cv.n_curves * KNOT_PAD;
   hipLaunchKernelGGL(k_zero_dev, dim3(grid_for(L.bf->caps.gauss * GG, 256, 8192)), dim3(256), 0, L.stream,
                      L.w.ggrad, L.bf->counters + NSPLAT_CNT_GAUSS, (int64_t)GG, (int64_t)L.bf->caps.gauss);
-  hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(4 * ncp, 256, 4096)), dim3(256), 0, L.stream, L.w.gcp, 4 * ncp);
-  hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(nkn, 256, 4096)), dim3(256), 0, L.stream, L.w.gknot, nkn);
-  hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(4 * cv.n_curves, 256, 4096)), dim3(256), 0, L.stream, L.w.gcurve,
-                     (int64_t)4 * cv.n_curves);
-  if (L.bf->caps.boundary > 0)
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(2 * L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
-                       (double*)L.w.gb, 2 * L.bf->caps.boundary);
+  ZeroSet z;
+  z.p[0] = L.w.gcp;
+  z.n[0] = 4 * ncp;
+  z.p[1] = L.w.gknot;
+  z.n[1] = nkn;
+  z.p[2] = L.w.gcurve;
+  z.n[2] = (int64_t)4 * cv.n_curves;
+  z.p[3] = (double*)L.w.gb;
+  z.n[3] = L.bf->caps.boundary > 0 ? 2 * L.bf->caps.boundary : 0;
+  const int64_t total = z.n[0] + z.n[1] + z.n[2] + z.n[3];
+  if (total > 0) hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(total, 256, 4096)), dim3(256), 0, L.stream, z);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
-// Device-wide exclusive prefix sums (reduce / scan-top / scan-down with
-// wavefront scans inside each block), fills, and the small helper kernels
+// Device-wide exclusive prefix sums (one block for small arrays, else
+// reduce / scan-top / scan-down with wavefront scans inside each block), fills, and the small helper kernels
 // (grid-step annealing of Eq. 14, L2 loss gradient).
 #include "nsplat_internal.h"
 
@@ -102,6 +102,46 @@ __global__ void k_scan_down(uint32_t* __restrict__ data, const int32_t* n_dev, i
   }
 }
 
+// Small scans (n <= SMALL_SCAN) in one launch: one block of 1024 threads
+// walks the array in tiles of 4096 (four consecutive entries per thread),
+// carrying the running total from tile to tile.
+constexpr int SMALL_THREADS = 1024;
+constexpr int64_t SMALL_SCAN = 65536;
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_scan_small(uint32_t* __restrict__ data, const int32_t* n_dev,
+                                                              int64_t n_cap, uint32_t* total_out) {
+  __shared__ uint32_t wsum[SMALL_THREADS / 64];
+  const int64_t n = n_dev ? (int64_t)min((int64_t)*n_dev, n_cap) : n_cap;
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < n; base += 4 * SMALL_THREADS) {
+    const int64_t k0 = base + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = k0 + i < n ? data[k0 + i] : 0u;
+    const uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
+    const uint32_t incl = wave_incl_scan(s);
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < SMALL_THREADS / 64; ++i) {
+      if (i < wid) wbase += wsum[i];
+      tot += wsum[i];
+    }
+    __syncthreads();
+    uint32_t run = carry + wbase + incl - s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (k0 + i < n) {
+        data[k0 + i] = run;
+        run += v[i];
+      }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -152,6 +192,10 @@ hipError_t launch_scan(uint32_t* data, const int32_t* n_dev, int64_t n_cap, uint
                        hipStream_t s) {
   const int64_t nb = (n_cap + SCAN_ITEMS - 1) / SCAN_ITEMS;
   if (nb <= 0) return total_out ? launch_fill_u32(total_out, 0u, 1, s) : hipSuccess;
+  if (n_cap <= SMALL_SCAN) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SMALL_THREADS), 0, s, data, n_dev, n_cap, total_out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n_dev, n_cap, tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, tmp, nb, total_out);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n_dev, n_cap, tmp);
