@@ -250,6 +250,105 @@ __global__ void k_item_counts(const int32_t* __restrict__ ranges, const int32_t*
   }
 }
 
+// The three steps above for up to SMALL_TILES tiles in one block (larger
+// counts go through the multi-block kernels, which are faster there): the tile
+// order by length class, then the checkpoint offsets (tile order) and the
+// adjoint item offsets (blend order) as exclusive scans with their totals at
+// index n_tiles, four entries per thread per round.
+constexpr int PLAN_THREADS = 1024;
+constexpr int SMALL_TILES = 8192;
+
+__device__ inline uint32_t plan_wave_scan(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(const int32_t* __restrict__ ranges, int n_tiles,
+                                                            int quads, int32_t* __restrict__ order,
+                                                            int32_t* __restrict__ ck_off,
+                                                            int32_t* __restrict__ item_off) {
+  __shared__ int h[32], base[32];
+  __shared__ uint32_t wsum[2][PLAN_THREADS / 64];
+  const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  if (tid < 32) h[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += PLAN_THREADS) atomicAdd(&h[len_class(ranges, t)], 1);
+  __syncthreads();
+  if (tid < 64) {
+    const int v = tid < 32 ? h[tid] : 0;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (tid < 32) {
+      base[tid] = incl - v;
+      h[tid] = 0;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += PLAN_THREADS) {
+    const int k = len_class(ranges, t);
+    order[base[k] + atomicAdd(&h[k], 1)] = t;
+  }
+  __syncthreads();
+  uint32_t carry[2] = {0u, 0u};
+  for (int b0 = 0; b0 < n_tiles; b0 += 4 * PLAN_THREADS) {
+    const int i0 = b0 + 4 * tid;
+    uint32_t v[2][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = i0 + j;
+      uint32_t ck = 0u, it = 0u;
+      if (i < n_tiles) {
+        const int n = n_chunks(ranges[2 * i + 1] - ranges[2 * i]);
+        ck = n > 0 ? (uint32_t)(n - 1) : 0u;
+        const int t = order[i];
+        it = (uint32_t)(quads * n_chunks(ranges[2 * t + 1] - ranges[2 * t]));
+      }
+      v[0][j] = ck;
+      v[1][j] = it;
+    }
+    uint32_t incl[2], sum[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      sum[a] = (v[a][0] + v[a][1]) + (v[a][2] + v[a][3]);
+      incl[a] = plan_wave_scan(sum[a]);
+      if (lane == 63) wsum[a][wid] = incl[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      uint32_t wb = 0, tot = 0;
+#pragma unroll
+      for (int q = 0; q < PLAN_THREADS / 64; ++q) {
+        if (q < wid) wb += wsum[a][q];
+        tot += wsum[a][q];
+      }
+      uint32_t run = carry[a] + wb + incl[a] - sum[a];
+      int32_t* out = a == 0 ? ck_off : item_off;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i0 + j < n_tiles) {
+          out[i0 + j] = (int32_t)run;
+          run += v[a][j];
+        }
+      carry[a] += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ck_off[n_tiles] = (int32_t)carry[0];
+    item_off[n_tiles] = (int32_t)carry[1];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_bin(const Launch& L) {
@@ -304,7 +403,10 @@ hipError_t launch_bin(const Launch& L) {
     hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
                        L.bf->ranges);
     const int nt = (int)L.n_tiles, ob = (nt + 255) / 256;
-    if (nt > 0) {
+    if (nt > 0 && nt <= SMALL_TILES) {
+      hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, nt,
+                         L.pr->tile == 8 ? 1 : 4, L.w.order, L.w.ck_off, L.w.item_off);
+    } else if (nt > 0) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
       hipLaunchKernelGGL(k_order_count, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin);
       hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, L.stream, L.w.obin);
