@@ -276,3 +276,18 @@ def test_timing_mask_records_only_selected_phases():
     assert n_one[bwd_id] == 1 and ms_one[bwd_id] > 0.0
     assert sum(n_one) == 1
     assert bool(torch.isfinite(img).all())
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_many_tiles_agree(persistent):
+    """An 800x800 canvas has 10,000 tiles at tile 8 (the multi-block path of the
+    tile order and of the chunk and item offsets) and 2,500 at tile 16 (the
+    single-block path); both give the same image and gradients."""
+    b = synth.config2(seed=2750, n_curves=8, size=800)
+    p = Params().replace(delta_c=1.0)
+    tb = synth.perturbed(b, seed=3)
+    target = gpu_run(tb, p.replace(tile=16), backward=False)["image"]
+    outs = {t: gpu_run(b, p.replace(tile=t), target=target, persistent=persistent) for t in (8, 16)}
+    assert outs[8]["ranges"].shape[0] == 10000 and outs[16]["ranges"].shape[0] == 2500
+    assert np.abs(outs[8]["image"] - outs[16]["image"]).max() < 2e-6
+    assert grad_close(outs[8]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
