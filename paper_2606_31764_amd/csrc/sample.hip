@@ -306,16 +306,26 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
 // point does, and one left of q never crosses it.  The left/right decision
 // keeps a margin that makes every orientation test in the chunk exact in
 // sign, so the count equals the plain one.
-__device__ inline double polyline_sdf(double qx, double qy, const double2* __restrict__ bp,
-                                      const double4* __restrict__ box, int nb, int* arg, double* targ,
+// Element access for polyline_sdf: P is a pointer to double in the generic
+// or the constant address space (points as (x, y) pairs, boxes as 4-tuples).
+template <class P>
+__device__ inline double2 ld_pt(P p, int i) {
+  return make_double2(p[2 * i], p[2 * i + 1]);
+}
+template <class P>
+__device__ inline double4 ld_box(P p, int i) {
+  return make_double4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+}
+
+template <class P>
+__device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, int nb, int* arg, double* targ,
                                       double* sgn_out) {
   const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
-  const double4 hb = box[0];  // the whole boundary's box
+  const double4 hb = ld_box(boxd, 0);  // the whole boundary's box
   const double scale = 1.0 + fabs(qx) + fabs(qy) + 2.0 * fmax(fmax(fabs(hb.x), fabs(hb.y)), fmax(fabs(hb.z), fabs(hb.w)));
-  box += 1;
   double ub = INFINITY;
   for (int k = 0; k < K; ++k) {
-    const double2 V = bp[k * SDF_CHUNK];
+    const double2 V = ld_pt(bpd, k * SDF_CHUNK);
     const double dx = V.x - qx, dy = V.y - qy;
     ub = fmin(ub, dx * dx + dy * dy);
   }
@@ -323,7 +333,7 @@ __device__ inline double polyline_sdf(double qx, double qy, const double2* __res
   double best = INFINITY, tbest = 0.0;
   int ibest = 0, wn = 0;
   for (int k = 0; k < K; ++k) {
-    const double4 b = box[k];  // x0, x1, y0, y1
+    const double4 b = ld_box(boxd, 1 + k);  // x0, x1, y0, y1
     const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
     const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
     const double lb = ex0 * ex0 + ey0 * ey0;
@@ -334,16 +344,16 @@ __device__ inline double polyline_sdf(double qx, double qy, const double2* __res
     int wk = 0;
     if (!visit && b.z <= qy && qy < b.w) {
       if (b.x > qx + mx) {
-        const double2 E = bp[i1 < nb ? i1 : 0];
-        wk = (E.y > qy ? 1 : 0) - (bp[i0].y > qy ? 1 : 0);
+        const double2 E = ld_pt(bpd, i1 < nb ? i1 : 0);
+        wk = (E.y > qy ? 1 : 0) - (ld_pt(bpd, i0).y > qy ? 1 : 0);
       } else if (!(b.y < qx - mx)) {
         visit = true;
       }
     }
     if (visit) {
-      double2 A = bp[i0];
+      double2 A = ld_pt(bpd, i0);
       for (int i = i0; i < i1; ++i) {
-        const double2 B = bp[i + 1 < nb ? i + 1 : 0];
+        const double2 B = ld_pt(bpd, i + 1 < nb ? i + 1 : 0);
         const double ex = B.x - A.x, ey = B.y - A.y;
         const double ee = ex * ex + ey * ey;
         const double rx = qx - A.x, ry = qy - A.y;
@@ -430,8 +440,19 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
       int arg;
       double t, sgn;
-      const double d = polyline_sdf(qx, qy, w.bpts + row[P_BOFF], w.cbox + cbox_base(row[P_BOFF], c), row[P_NSAMP],
-                                    &arg, &t, &sgn);
+      double d;
+      const int cu = __builtin_amdgcn_readfirstlane(c);
+      if (__ballot(c != cu) == 0ull) {
+        // the whole wavefront is on one curve: its boundary is read through
+        // the constant address space with uniform indices (scalar loads)
+        typedef const __attribute__((address_space(4))) double* cdp;
+        const int32_t* ru = plan + (int64_t)P_STRIDE * cu;
+        d = polyline_sdf(qx, qy, (cdp)(w.bpts + ru[P_BOFF]), (cdp)(w.cbox + cbox_base(ru[P_BOFF], cu)), ru[P_NSAMP],
+                         &arg, &t, &sgn);
+      } else {
+        d = polyline_sdf(qx, qy, (const double*)(w.bpts + row[P_BOFF]),
+                         (const double*)(w.cbox + cbox_base(row[P_BOFF], c)), row[P_NSAMP], &arg, &t, &sgn);
+      }
       const double z = ((double)pr.gamma / h) * (sgn * d);
       r.mx = qx;
       r.my = qy;
