@@ -305,17 +305,23 @@ __device__ inline int wave_min(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Flushes one wavefront's running per-curve sums (colour, and opacity for a
-// stroke curve) into the FP64 per-curve accumulators.
-template <int C>
-__device__ inline void flush_curve(double* gcurve, int c, bool fill, float (&accC)[3], float& accO) {
+// Flushes one wavefront's running per-curve sums into the FP64 per-curve
+// accumulators: the colour gradient sum_q dL/dI_c(q) sum(alpha T) of each
+// channel, and the opacity gradient of a stroke curve.
+template <int C, int PPT>
+__device__ inline void flush_curve(double* gcurve, int c, bool fill, const float (&gI)[PPT][3],
+                                   float (&sumaT)[PPT], float& accO) {
   float v[C + 1];
   v[0] = fill ? 0.0f : accO;
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) {
-    v[1 + ch] = accC[ch];
-    accC[ch] = 0.0f;
+    float a = 0.0f;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) a = __builtin_fmaf(gI[q][ch], sumaT[q], a);
+    v[1 + ch] = a;
   }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) sumaT[q] = 0.0f;
   accO = 0.0f;
   const float t = wave_totals_to_lanes<C + 1>(v);
   const int lane = __lane_id();
@@ -454,7 +460,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     }
     int cur = -1, since = 0;
     bool cur_fill = false;
-    float accC[3] = {0.0f, 0.0f, 0.0f}, accO = 0.0f;
+    // per pixel: K = sum_c dL/dI_c col_c of the current curve, and the sum of
+    // alpha T over its entries (the curve's colour gradient is dL/dI_c times it)
+    float Kc[PPT], sumaT[PPT], accO = 0.0f;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) Kc[q] = sumaT[q] = 0.0f;
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
     // front to back over the chunk's positions c_hi - 1 down to lo
     Entry e[E];
@@ -501,7 +511,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         const int c_k = __builtin_amdgcn_readfirstlane(mt.y);
         const bool fill = gsig < 0;
         if (c_k != cur || since >= FLUSH) {
-          if (cur >= 0) flush_curve<C>(w.gcurve, cur, cur_fill, accC, accO);
+          if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, sumaT, accO);
+          if (c_k != cur) {
+            const float col[3] = {pc.y, pc.z, pc.w};
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+              float K = 0.0f;
+#pragma unroll
+              for (int c = 0; c < C; ++c) K = __builtin_fmaf(gI[q][c], col[c], K);
+              Kc[q] = K;
+            }
+          }
           cur = c_k;
           cur_fill = fill;
           since = 0;
@@ -509,7 +529,6 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         ++since;
         const int pos = mt.z;
         const float is3 = __int_as_float(mt.w);
-        const float col[3] = {pc.y, pc.z, pc.w};
         float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         bool act = false;
 #pragma unroll
@@ -523,12 +542,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
           const float alpha = in ? fminf(amax, oG) : 0.0f;
           const float onem = 1.0f - alpha;
           const float aT = alpha * T[q];
-          float K = 0.0f;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            K = __builtin_fmaf(gI[q][c], col[c], K);
-            accC[c] = __builtin_fmaf(gI[q][c], aT, accC[c]);
-          }
+          const float K = Kc[q];
+          sumaT[q] += aT;
           U[q] = __builtin_fmaf(K, aT, U[q]);
           const float dLda = (in && oG < amax) ? T[q] * K - (R[q] - U[q]) * __builtin_amdgcn_rcpf(onem) : 0.0f;
           T[q] = T[q] * onem;
@@ -567,7 +582,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
       flush_rows(park, ptgt, n_rows, ggrad);
       n_rows = 0;
     }
-    if (cur >= 0) flush_curve<C>(w.gcurve, cur, cur_fill, accC, accO);
+    if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, sumaT, accO);
   }
 }
 
