@@ -197,7 +197,7 @@ def phase_bytes(step, tile):
     bits = 0
     while bits < 31 and (1 << bits) < n_tiles:
         bits += 1
-    passes = (bits + 7) // 8
+    passes = (bits + 9) // 10
     return dict(emit=32 * G + 4 * n_fill, bin=64 * G + 12 * G + 8 * P, sort=passes * 20 * P,
                 ranges=4 * P + 8 * n_tiles), passes
 

@@ -31,7 +31,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   const int64_t tiles8 = nsplat_num_tiles(sc, 8);
   int64_t n_pix = 0;
   for (int s = 0; s < sc->n_scenes; ++s) n_pix += (int64_t)sc->hw_host[2 * s] * sc->hw_host[2 * s + 1];
-  const int64_t scan_n = std::max<int64_t>({gcap, 256 * lay.sort_blocks, tiles8 + 1, 1});
+  const int64_t scan_n = std::max<int64_t>({gcap, (int64_t)RADIX_MAX * lay.sort_blocks, tiles8 + 1, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
   const size_t sizes[N_WS] = {
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
@@ -43,7 +43,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys0
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys1
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // vals1
-      sizeof(uint32_t) * (size_t)(256 * std::max<int64_t>(lay.sort_blocks, 1)),  // hist
+      sizeof(uint32_t) * (size_t)(RADIX_MAX * std::max<int64_t>(lay.sort_blocks, 1)),  // hist
       sizeof(uint32_t) * (size_t)(lay.scan_blocks + 1),    // scan_tmp
       sizeof(float) * GG * (size_t)std::max<int64_t>(gcap, 1),  // ggrad
       sizeof(double) * 4 * (size_t)(K + N * CP_PAD),       // gcp

@@ -91,11 +91,11 @@ constexpr int SORT_WAVES = SORT_THREADS / 64;
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const int32_t* counters, int shift, int bits,
                                                              uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
+  __shared__ uint32_t h[RADIX_MAX];
   const int64_t n = counters[NSPLAT_CNT_PAIRS];
-  const int nb = gridDim.x;
+  const int nb = gridDim.x, nd = 1 << bits;
   const uint32_t mask = (1u << bits) - 1u;
-  h[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < nd; d += SORT_THREADS) h[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
   for (int i = 0; i < SORT_ROUNDS; ++i) {
@@ -103,7 +103,77 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
     if (k < n) atomicAdd(&h[(keys[k] >> shift) & mask], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < (1 << bits)) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < nd; d += SORT_THREADS) hist[(int64_t)d * nb + blockIdx.x] = h[d];
+}
+
+// Stable scatter for digits of 9 to RADIX_BITS_MAX bits.  Wavefront w of the
+// block owns the contiguous items base + 1024 w .. base + 1024 w + 1023: it
+// counts their digits into its own LDS row, the rows are turned into
+// per-wavefront starting offsets (block offset from the scanned histogram
+// plus the counts of the earlier wavefronts), and each wavefront then places
+// its items in order, 64 at a time, ranking equal digits with ballots and
+// advancing only its own offsets, so no block barrier is needed per round.
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter_wide(const uint32_t* __restrict__ kin,
+                                                                     const uint32_t* __restrict__ vin,
+                                                                     uint32_t* __restrict__ kout,
+                                                                     uint32_t* __restrict__ vout,
+                                                                     const int32_t* counters, int shift, int bits,
+                                                                     const uint32_t* __restrict__ hist) {
+  static_assert(SORT_ITEMS == SORT_WAVES * 1024, "1024 items per wavefront");
+  __shared__ uint32_t off[SORT_WAVES][RADIX_MAX];
+  const int64_t n = counters[NSPLAT_CNT_PAIRS];
+  const int nb = gridDim.x, nd = 1 << bits;
+  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+  if (base >= n) return;
+  const uint32_t mask = (1u << bits) - 1u;
+  const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
+  for (int d = t; d < SORT_WAVES * nd; d += SORT_THREADS) off[d / nd][d % nd] = 0u;
+  __syncthreads();
+  const int64_t wbase = base + (int64_t)wid * 1024;
+  uint32_t key[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t k = wbase + r * 64 + lane;
+    key[r] = k < n ? kin[k] : 0u;
+    if (k < n) atomicAdd(&off[wid][(key[r] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int d = t; d < nd; d += SORT_THREADS) {
+    uint32_t run = hist[(int64_t)d * nb + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < SORT_WAVES; ++q) {
+      const uint32_t c = off[q][d];
+      off[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t k = wbase + r * 64 + lane;
+    const bool active = k < n;
+    const uint32_t dig = (key[r] >> shift) & mask;
+    uint64_t peers = __ballot(active);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t o = off[wid][dig];
+    if (active) {
+      kout[o + rank] = key[r];
+      vout[o + rank] = vin[k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (active && rank == 0) off[wid][dig] = o + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // Stable scatter.  Round i handles items base + i * 256 + t, so ascending
@@ -356,10 +426,10 @@ hipError_t launch_bin(const Launch& L) {
   int32_t* cnt = L.bf->counters;
   const Gauss* gs = (const Gauss*)L.bf->gauss;
   const int gg = grid_for(gcap, 256, 8192);
-  // number of key bits and radix passes (up to 8 bits each)
+  // number of key bits and radix passes (up to RADIX_BITS_MAX bits each)
   int key_bits = 0;
   while (key_bits < 31 && ((int64_t)1 << key_bits) < L.n_tiles) ++key_bits;
-  const int passes = (key_bits + 7) / 8;
+  const int passes = (key_bits + RADIX_BITS_MAX - 1) / RADIX_BITS_MAX;
   const int digit = passes ? (key_bits + passes - 1) / passes : 0;
   uint32_t* idx = (uint32_t*)L.bf->idx;
   // the last pass must land in (keys0, idx)
@@ -389,8 +459,12 @@ hipError_t launch_bin(const Launch& L) {
                            L.w.hist);
         e = launch_scan(L.w.hist, nullptr, (int64_t)(1 << bits) * sb, nullptr, L.w.scan_tmp, L.stream);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout, cnt,
-                           shift, bits, L.w.hist);
+        if (bits > 8)
+          hipLaunchKernelGGL(k_radix_scatter_wide, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout,
+                             cnt, shift, bits, L.w.hist);
+        else
+          hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(SORT_THREADS), 0, L.stream, kin, vin, kout, vout, cnt,
+                             shift, bits, L.w.hist);
       }
       kin = kout;
       vin = vout;

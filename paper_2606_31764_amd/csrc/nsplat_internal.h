@@ -17,6 +17,8 @@ constexpr double LOG2E = 1.4426950408889634074;
 constexpr double LN2 = 0.69314718055994530942;
 constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide scans
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
+constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
+constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
 constexpr int N_WS = 26;                // workspace entries
 

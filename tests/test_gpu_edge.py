@@ -291,3 +291,25 @@ def test_many_tiles_agree(persistent):
     assert outs[8]["ranges"].shape[0] == 10000 and outs[16]["ranges"].shape[0] == 2500
     assert np.abs(outs[8]["image"] - outs[16]["image"]).max() < 2e-6
     assert grad_close(outs[8]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
+
+
+def test_wide_radix_digit_lists_are_sorted_and_agree():
+    """900 tiles (a 240x240 canvas at tile 8) take one radix pass with a
+    10-bit digit (the wavefront-ranked scatter): every tile list must hold
+    ascending Gaussian indices, and the render must agree with the 225-tile
+    form (8-bit digit)."""
+    b = synth.config3(seed=3960, n_paths=10, size=240)
+    p = Params().replace(h=2.0)
+    tb = synth.perturbed(b, seed=4)
+    target = gpu_run(tb, p.replace(tile=16), backward=False)["image"]
+    outs = {t: gpu_run(b, p.replace(tile=t), target=target) for t in (8, 16)}
+    ranges, idx = outs[8]["ranges"], outs[8]["idx"]
+    assert ranges.shape[0] == 900
+    n_pairs = 0
+    for s, e in ranges:
+        if e > s:
+            assert np.all(np.diff(idx[s:e]) > 0)
+            n_pairs += e - s
+    assert n_pairs == len(idx)
+    assert np.abs(outs[8]["image"] - outs[16]["image"]).max() < 2e-6
+    assert grad_close(outs[8]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
