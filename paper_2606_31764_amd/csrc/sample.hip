@@ -19,6 +19,7 @@ namespace nsp {
 namespace {
 
 constexpr int PREP_THREADS = 256;
+constexpr int PREP_KNOTS = 4096;  // knots held in LDS by k_curve_prep (32 KB)
 
 __global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, n
                                                              int32_t* plan, int32_t* counters, int frozen,
                                                              int n_scenes) {
   __shared__ double red[PREP_THREADS / 64];
+  __shared__ double Us[PREP_KNOTS];
   const int c = blockIdx.x;
   const CurveView v = curve_view(cv, w.knots, c);
   int32_t* row = plan + (int64_t)P_STRIDE * c;
@@ -82,34 +84,53 @@ __global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, n
   }
   // Knot vector: U_0 = 0, U_{l+1} = U_l + delta_l with the interval list of
   // Sec. 3.1 (open: p zeros, tau, p zeros; closed: last p tau, tau, first p).
+  // The intervals are gathered in parallel into LDS, one thread sums them in
+  // order (the same additions as a plain running sum), and the block writes
+  // the knots out and evaluates the arc length from the LDS copy.
   double* U = w.knots + v.t0 + (int64_t)c * KNOT_PAD;
-  if (threadIdx.x == 0) {
-    double acc = 0.0;
-    U[0] = 0.0;
-    for (int l = 0; l < v.m; ++l) {
-      double d;
-      if (!v.closed()) d = (l < v.p || l >= v.p + v.nt) ? 0.0 : (double)cv.tau[v.t0 + l - v.p];
-      else {
-        int t = (l - v.p) % v.nt;
-        if (t < 0) t += v.nt;
-        d = (double)cv.tau[v.t0 + t];
+  auto interval = [&](int l) {
+    if (!v.closed()) return (l < v.p || l >= v.p + v.nt) ? 0.0 : (double)cv.tau[v.t0 + l - v.p];
+    int t = (l - v.p) % v.nt;
+    if (t < 0) t += v.nt;
+    return (double)cv.tau[v.t0 + t];
+  };
+  CurveView vk = v;  // the view the quadrature evaluates: knots in LDS when they fit
+  if (v.m + 1 <= PREP_KNOTS) {
+    for (int l = threadIdx.x; l < v.m; l += PREP_THREADS) Us[l + 1] = interval(l);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double acc = 0.0;
+      Us[0] = 0.0;
+      for (int l = 0; l < v.m; ++l) {
+        acc = acc + Us[l + 1];
+        Us[l + 1] = acc;
       }
-      acc = acc + d;
-      U[l + 1] = acc;
     }
+    __syncthreads();
+    for (int l = threadIdx.x; l <= v.m; l += PREP_THREADS) U[l] = Us[l];
+    vk.U = Us;
+  } else {
+    if (threadIdx.x == 0) {
+      double acc = 0.0;
+      U[0] = 0.0;
+      for (int l = 0; l < v.m; ++l) {
+        acc = acc + interval(l);
+        U[l + 1] = acc;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // Eq. 3: L = sum_j ||C'(u_j)|| du over N_L midpoints of [u_p, u_{m-p}].
   const SceneTab* st = w.scenes + s;
   const int n_L = st->n_L;
-  const double a = U[v.p], b = U[v.m - v.p];
+  const double a = vk.U[v.p], b = vk.U[v.m - v.p];
   const double du = (b - a) / (double)n_L;
   double part = 0.0;
   for (int j = 1 + threadIdx.x; j <= n_L; j += PREP_THREADS) {
     const double u = a + ((double)j - 0.5) * du;
-    const int span = find_span(U, v.p, v.m, u);
+    const int span = find_span(vk.U, v.p, v.m, u);
     double pt[3], d[3];
-    curve_point(cv, v, u, span, pt, d);
+    curve_point(cv, vk, u, span, pt, d);
     part += sqrt(d[0] * d[0] + d[1] * d[1]) * du;
   }
   const double L = block_sum(part, red);
