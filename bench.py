@@ -140,15 +140,17 @@ def blend_work(step, tile):
     return ev, hit, hit_fill
 
 
-# Algorithmic FP32 operations per in-support (pixel, Gaussian) pair; an FMA
-# counts 2.  Forward: d^2 (2 sub, mul, fma) 5, exp2 argument and exp2 2,
-# o G and the alpha_max clamp 2, alpha T 1, three colour FMAs 6, 1 - alpha
-# and T (1 - alpha) 2, termination test 1 = 19.  Reverse pass of a fill
-# Gaussian: d^2 5, exp2 2, o G and clamp 2, 1 - alpha and its reciprocal 2,
-# T recovery 1, alpha T 1, dL/dalpha 3 (sub + fma) = 9, colour gradient 3 FMAs
-# 6, colour behind 3 (mul + fma) = 9, gate and scale 1, dL/do_j FMA 2 = 40;
-# a stroke Gaussian adds dL/dmu and dL/dsigma: 14 = 54.
-FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 19, 40, 54
+# Algorithmic FP32 operations per in-support (pixel, Gaussian) pair of the
+# formulation the kernels compute; an FMA counts 2.  Forward: d^2 (2 sub,
+# mul, fma) 5, exp2 argument and exp2 2, o G and the alpha_max clamp 2,
+# alpha T 1, three colour FMAs 6, 1 - alpha and T (1 - alpha) 2, termination
+# test 1 = 19.  Adjoint of a fill Gaussian (front to back inside a chunk):
+# d^2 5, exp2 2, o G and clamp 2, 1 - alpha 1, alpha T 1, sum of alpha T 1,
+# U += K alpha T 2, dL/dalpha = T K - (R - U) rcp(1 - alpha) 5, T (1 - alpha)
+# 1, dL/do_j FMA 2 = 22 (K and the colour gradient are per curve, not per
+# pair); a stroke Gaussian adds dL/dmu and dL/dsigma (14) and its opacity sum
+# (1) = 37.
+FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 19, 22, 37
 # The build disables packed FP32 instructions, so the FP32 vector peak is
 # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s, not the
 # packed 157.3.

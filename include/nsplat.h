@@ -226,8 +226,11 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_sc
                    float* T_final, int32_t* n_last, int persistent, void* stream);
 
 /* Adjoint of nsplat_forward o nsplat_bin o nsplat_sample for the upstream
- * gradient dL_dimage (layout of image).  Walks each pixel's list back to
- * front from n_last, recovering the transmittance as T / (1 - alpha), and
+ * gradient dL_dimage (layout of image).  Must follow the nsplat_forward of
+ * the same buffers: it starts each chunk of 512 list positions from the
+ * per-pixel state that forward stored in the workspace at the chunk's front
+ * boundary (and uses the final accumulated colour it stored), walks the
+ * chunk front to back down to n_last, and
  * chains through the Gaussians into the Cox-de Boor basis (control points,
  * weights, widths, knots -> intervals), the SDF (nearest segment, detached
  * sign), the sample parameters u_j (which depend on the domain ends) and the

@@ -1,14 +1,15 @@
 // nsplat_forward / the first half of nsplat_backward: per-tile alpha
 // compositing (Sec. 3.4, Eq. 8-9) and its adjoint.
 //
-// The unit of work is one wavefront per (tile, quadrant): see TileCfg below.
-// Centres become exact tile-local FP32 coordinates when an entry is loaded
-// (FP64 centre minus the tile origin, rounded once).  The forward stops a
-// pixel once T < eps_T and a wavefront once all its pixels have stopped.  The
-// adjoint walks the same lists back to front from each pixel's stopping
-// position, recovering the transmittance as T * rcp(1 - alpha)
-// (alpha <= alpha_max < 1), sums each Gaussian's gradient across the
-// wavefront with DPP and adds it with one atomic per value and wavefront.
+// The forward's unit of work is one wavefront per (tile, quadrant): see
+// TileCfg below.  Centres become exact tile-local FP32 coordinates when an
+// entry is loaded (FP64 centre minus the tile origin, rounded once).  The
+// forward stops a pixel once T < eps_T and a wavefront once all its pixels
+// have stopped, and stores each pixel's state at every chunk boundary (CK
+// list positions) it passes.  The adjoint runs one wavefront per (tile,
+// quadrant, chunk), front to back from that stored state, parks each
+// Gaussian's per-lane gradient values in LDS and sums sixteen of them at a
+// time, with one atomic per value and wavefront.
 #include "nsplat_internal.h"
 
 namespace nsp {
@@ -18,9 +19,9 @@ namespace {
 // Work decomposition: one wavefront per (tile, quadrant) item.  8x8 tiles are
 // one quadrant; 16x16 and 32x32 tiles have four (8x8 or 16x16 pixels), and
 // each lane owns a BLK x BLK block of its quadrant.  A wavefront walks the
-// tile's list in steps of 64 entries: every lane loads one entry (the next
-// step's loads are issued before the current step is processed), entries
-// whose support square misses the quadrant are dropped, the rest are
+// tile's list in steps of up to 64 E entries: every lane loads E entries (the
+// next step's loads are issued before the current step is processed),
+// entries whose support disc misses the quadrant are dropped, the rest are
 // compacted in order into the wavefront's own LDS arrays and then composited
 // one after another.  Wavefronts never wait for each other.
 template <int TILE>
