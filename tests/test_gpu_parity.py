@@ -23,6 +23,9 @@ def _cases():
         "c3s_h2": (synth.config3(seed=3100, n_paths=10, size=100), Params().replace(h=2.0)),
         "c3s_h1": (synth.config3(seed=3200, n_paths=6, size=72), Params().replace(h=1.0)),
         "c4s": (synth.config4(seed=4100, n_curves=2, n_cp=60, size=200), Params().replace(delta_c=10.0)),
+        # dense cases whose tile lists span several 512-position chunks of the adjoint
+        "c3s_dense": (synth.config3(seed=3300, n_paths=10, size=64), Params().replace(h=0.5)),
+        "c4s_dense": (synth.config4(seed=4200, n_curves=6, n_cp=120, size=96), Params().replace(delta_c=10.0)),
     }
 
 
@@ -101,3 +104,22 @@ def test_persistent_matches_plain(name):
     np.testing.assert_array_equal(a["image"], c["image"])
     np.testing.assert_array_equal(a["n_last"], c["n_last"])
     assert grad_close(c["grads"], a["grads"], rtol=1e-5, atol=1e-7) <= 1.0
+
+
+@pytest.mark.parametrize("name", ["c3s_dense", "c4s_dense"])
+@pytest.mark.parametrize("tile", [16, 32])
+def test_backward_across_chunks(name, tile):
+    """Tile lists longer than two 512-position chunks: the adjoint starts the
+    later chunks from the forward's stored state, and the gradients still
+    match the oracle."""
+    b, p = CASES[name]
+    p = p.replace(tile=tile)
+    target = _target(name)
+    out = gpu_run(b, p, target=target)
+    lens = out["ranges"][:, 1] - out["ranges"][:, 0]
+    print(name, tile, "longest list", int(lens.max()), flush=True)
+    assert lens.max() > 2 * 512
+    _, gref, _, _ = oracle.loss_and_grad(b, target, oracle_params(p))
+    worst = grad_close(out["grads"], gref)
+    print(name, tile, "grad worst ratio", worst, flush=True)
+    assert worst <= 1.0, grad_report(out["grads"], gref)
