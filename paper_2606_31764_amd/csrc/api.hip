@@ -60,6 +60,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(int32_t) * (size_t)(tiles8 + 1),              // item_off
       sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
       sizeof(float) * 3 * (size_t)std::max<int64_t>(n_pix, 1),  // afin
+      sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -99,6 +100,7 @@ Work carve(void* ws, const Layout& lay) {
   w.item_off = (int32_t*)(b + lay.off[23]);
   w.ckbuf = (float*)(b + lay.off[24]);
   w.afin = (float*)(b + lay.off[25]);
+  w.gcol = (float4*)(b + lay.off[26]);
   return w;
 }
 

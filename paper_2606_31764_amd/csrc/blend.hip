@@ -58,17 +58,24 @@ struct Entry {
   int g, fill;
 };
 
-template <int C>
+// Record and colour of Gaussian g.
+__device__ inline void load_rec(const Gauss* __restrict__ gs, const float4* __restrict__ gcol, int g, Entry* e) {
+  e->g = g;
+  e->r = gs[g];
+  const float4 cf = gcol[g];
+  e->c0 = cf.x;
+  e->c1 = cf.y;
+  e->c2 = cf.z;
+  e->fill = cf.w != 0.0f;
+}
+
+// The entry's record and its curve's colour / fill tag (both by Gaussian
+// index, so the two loads go out together once the index has arrived).
 __device__ inline void load_entry(const int32_t* __restrict__ idx, const Gauss* __restrict__ gs,
-                                  const nsplat_curves& cv, int pos, bool ok, Entry* e) {
+                                  const float4* __restrict__ gcol, int pos, bool ok, Entry* e) {
   if (!ok) return;
   e->g = idx[pos];
-  e->r = gs[e->g];
-  const float* col = cv.color + (int64_t)e->r.curve * C;
-  e->c0 = col[0];
-  e->c1 = C == 3 ? col[1] : 0.0f;
-  e->c2 = C == 3 ? col[2] : 0.0f;
-  e->fill = (cv.flags[e->r.curve] & NSPLAT_FILLED) != 0;
+  load_rec(gs, gcol, e->g, e);
 }
 
 // Tile-local centre (relative to the tile's first pixel centre), squared
@@ -165,12 +172,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     // front to back: list positions end-1 down to start, at most `depth` per
     // step and never across a chunk boundary, where the state is stored
     const int ck0 = w.ck_off[tile];
+    // loads run two steps ahead for the list indices and one step ahead for
+    // the records, so a step waits for one round trip, issued a step earlier
     Entry e[E];
+    int gnext[E];  // Gaussian indices of the next step
     int hi = end, lo_s = step_floor(hi, start, depth, end);
+    int nhi = lo_s, nlo = step_floor(nhi, start, depth, end);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
-      load_entry<C>(idx, gs, cv, hi - 1 - k, k < hi - lo_s, &e[u]);
+      load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
+      gnext[u] = k < nhi - nlo ? idx[nhi - 1 - k] : 0;
     }
     while (hi > start) {
       int cnt = 0;
@@ -190,11 +202,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         }
         cnt += __popcll(m);
       }
-      const int nhi = lo_s, nlo = step_floor(nhi, start, depth, end);
+      // next step's records (their indices arrived during this step's
+      // predecessor) and the indices of the step after, in flight while
+      // this step is composited
+      const int n2hi = nlo, n2lo = step_floor(n2hi, start, depth, end);
 #pragma unroll
-      for (int u = 0; u < E; ++u) {  // next step, in flight while this one is composited
+      for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
-        load_entry<C>(idx, gs, cv, nhi - 1 - k, k < nhi - nlo, &e[u]);
+        if (k < nhi - nlo) load_rec(gs, w.gcol, gnext[u], &e[u]);
+        gnext[u] = k < n2hi - n2lo ? idx[n2hi - 1 - k] : 0;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -233,6 +249,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       }
       hi = nhi;
       lo_s = nlo;
+      nhi = n2hi;
+      nlo = n2lo;
       if (hi > start && (end - hi) % CK == 0) {
         // state in front of chunk (end - hi) / CK: T and the accumulated colour
         float* ckp = w.ckbuf + (int64_t)(ck0 + (end - hi) / CK - 1) * (4 * TILE * TILE);
@@ -473,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
-      load_entry<C>(idx, gs, cv, hi - 1 - k, k < hi - lo_s, &e[u]);
+      load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
     }
     while (hi > lo) {
       int cnt = 0;
@@ -499,7 +517,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
 #pragma unroll
       for (int u = 0; u < E; ++u) {  // next step, in flight while this one is processed
         const int k = u * 64 + lane;
-        load_entry<C>(idx, gs, cv, nhi - 1 - k, k < nhi - nlo, &e[u]);
+        load_entry(idx, gs, w.gcol, nhi - 1 - k, k < nhi - nlo, &e[u]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();

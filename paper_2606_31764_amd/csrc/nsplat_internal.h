@@ -20,7 +20,7 @@ constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 26;                // workspace entries
+constexpr int N_WS = 27;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -66,6 +66,7 @@ struct Work {
   int32_t* item_off;   // [tiles at the smallest tile size + 1] first adjoint item of each tile in blend order (scan)
   float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries
   float* afin;         // [pixels][3] accumulated colour at each pixel's end of compositing
+  float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and 1 for fill Gaussians
 };
 
 // The compositing lists are cut into chunks of CK list positions, counted

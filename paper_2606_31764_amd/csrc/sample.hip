@@ -405,6 +405,13 @@ __device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, int n
   return sqrt(best);
 }
 
+// (colour channels of curve c, zero-padded to three; `tag` in w): the
+// compositing kernels read it by Gaussian index, beside the record.
+__device__ inline float4 curve_colour(const nsplat_curves& cv, int c, float tag) {
+  const float* col = cv.color + (int64_t)c * cv.channels;
+  return make_float4(col[0], cv.channels == 3 ? col[1] : 0.0f, cv.channels == 3 ? col[2] : 0.0f, tag);
+}
+
 // One lane per Gaussian.  Emission order per curve: open strokes kappa copies
 // of sample 0, samples 0..M-1, kappa copies of sample M-1; closed strokes
 // samples 0..M-1; fills the lattice window row by row.
@@ -482,10 +489,12 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
       if (gp < G) {  // a capped (overflowing) emission may map past the capacity
         w.aux[gp] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
         out[gp] = r;
+        w.gcol[gp] = curve_colour(cv, c, 1.0f);
       }
       continue;
     }
     out[g] = r;
+    w.gcol[g] = curve_colour(cv, c, 0.0f);
   }
 }
 
