@@ -38,11 +38,16 @@ __device__ inline bool tile_rect(const Gauss& gs, float k_sigma, float inv_tile,
   return true;
 }
 
+// Also clears the tile ranges (n_ranges entries) that k_tile_ranges fills in
+// after the sort.
 __global__ __launch_bounds__(256) void k_bin_count(nsplat_curves cv, nsplat_params pr, Work w,
                                                    const Gauss* __restrict__ gs, const int32_t* counters,
-                                                   uint32_t* __restrict__ cnt) {
+                                                   uint32_t* __restrict__ cnt, int32_t* __restrict__ ranges,
+                                                   int64_t n_ranges) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const float inv = 1.0f / (float)pr.tile;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_ranges; i += (int64_t)gridDim.x * blockDim.x)
+    ranges[i] = 0;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
     const Gauss r = gs[g];
     const SceneTab st = w.scenes[cv.scene[r.curve]];
@@ -53,8 +58,8 @@ __global__ __launch_bounds__(256) void k_bin_count(nsplat_curves cv, nsplat_para
   }
 }
 
-__global__ void k_pairs_total(int32_t* counters, const uint32_t* total, int64_t cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Pair count from the scan total, its capped value, and the capacity flag.
+__device__ inline void pairs_total(int32_t* counters, const uint32_t* total, int64_t cap) {
   const uint32_t t = *total;
   counters[NSPLAT_CNT_PAIRS_REQ] = t > 0x7fffffffu ? 0x7fffffff : (int32_t)t;
   counters[NSPLAT_CNT_PAIRS] = (int32_t)((int64_t)t < cap ? (int64_t)t : cap);
@@ -63,10 +68,14 @@ __global__ void k_pairs_total(int32_t* counters, const uint32_t* total, int64_t 
   counters[NSPLAT_CNT_STATUS] = st;
 }
 
+// Thread 0 also publishes the pair count (off[G_cap] holds the scan total);
+// no thread of this kernel reads it.
 __global__ __launch_bounds__(256) void k_bin_emit(nsplat_curves cv, nsplat_params pr, Work w,
-                                                  const Gauss* __restrict__ gs, const int32_t* counters,
-                                                  const uint32_t* __restrict__ off, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals, int64_t cap) {
+                                                  const Gauss* __restrict__ gs, int32_t* counters,
+                                                  const uint32_t* __restrict__ off, const uint32_t* total,
+                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                  int64_t cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap);
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const float inv = 1.0f / (float)pr.tile;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
@@ -438,12 +447,12 @@ hipError_t launch_bin(const Launch& L) {
   hipError_t e;
   {
     Phase ph(L, NSPLAT_T_BIN);
-    hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt);
+    hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt,
+                       L.bf->ranges, 2 * L.n_tiles);
     e = launch_scan(L.w.gcnt, cnt + NSPLAT_CNT_GAUSS, gcap, L.w.gcnt + gcap, L.w.scan_tmp, L.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, L.stream, cnt, L.w.gcnt + gcap, pcap);
-    hipLaunchKernelGGL(k_bin_emit, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt, ek, ev,
-                       pcap);
+    hipLaunchKernelGGL(k_bin_emit, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt,
+                       L.w.gcnt + gcap, ek, ev, pcap);
   }
   {
     Phase ph(L, NSPLAT_T_SORT);
@@ -472,8 +481,6 @@ hipError_t launch_bin(const Launch& L) {
   }
   {
     Phase ph(L, NSPLAT_T_RANGES);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.n_tiles, 256, 4096)), dim3(256), 0, L.stream,
-                       L.bf->ranges, 0, 2 * L.n_tiles);
     hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
                        L.bf->ranges);
     const int nt = (int)L.n_tiles, ob = (nt + 255) / 256;

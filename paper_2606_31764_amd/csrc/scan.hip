@@ -1,5 +1,6 @@
-// Device-wide exclusive prefix sums (one block for small arrays, else
-// reduce / scan-top / scan-down with wavefront scans inside each block), fills, and the small helper kernels
+// Device-wide exclusive prefix sums (one block for small arrays; else block
+// sums, then the down-sweep, with the scan of the block sums done by a block
+// of its own when there are many), fills, and the small helper kernels
 // (grid-step annealing of Eq. 14, L2 loss gradient).
 #include "nsplat_internal.h"
 
@@ -91,6 +92,50 @@ __global__ void k_scan_down(uint32_t* __restrict__ data, const int32_t* n_dev, i
   }
   uint32_t tot;
   uint32_t run = block_excl_scan(s, &tot) + tmp[blockIdx.x];
+  for (int i = 0; i < SCAN_PER_THREAD; ++i) {
+    buf[threadIdx.x * SCAN_PER_THREAD + i] = run;
+    run += loc[i];
+  }
+  __syncthreads();
+  for (int i = 0; i < SCAN_PER_THREAD; ++i) {
+    const int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+    if (k < n) data[k] = buf[i * SCAN_THREADS + threadIdx.x];
+  }
+}
+
+// k_scan_down with the scan of the block sums folded in, for up to
+// FUSED_BLOCKS blocks: each block adds up the sums of the blocks in front of
+// it, and block 0 adds up all of them for the total.
+constexpr int64_t FUSED_BLOCKS = 1024;
+
+__global__ void k_scan_down_fused(uint32_t* __restrict__ data, const int32_t* n_dev, int64_t n_cap,
+                                  const uint32_t* __restrict__ tmp, int64_t nb, uint32_t* total_out) {
+  __shared__ uint32_t buf[SCAN_ITEMS];
+  const int64_t n = n_dev ? (int64_t)min((int64_t)*n_dev, n_cap) : n_cap;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_ITEMS;
+  const int64_t lim = blockIdx.x == 0 ? nb : (int64_t)blockIdx.x;
+  uint32_t s = 0;
+  for (int64_t i = threadIdx.x; i < lim; i += SCAN_THREADS) s += tmp[i];
+  uint32_t front;
+  block_excl_scan(s, &front);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0 && total_out) *total_out = front;
+    front = 0;
+  }
+  if (base >= n) return;
+  for (int i = 0; i < SCAN_PER_THREAD; ++i) {
+    const int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+    buf[i * SCAN_THREADS + threadIdx.x] = k < n ? data[k] : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[SCAN_PER_THREAD];
+  uint32_t t = 0;
+  for (int i = 0; i < SCAN_PER_THREAD; ++i) {
+    loc[i] = buf[threadIdx.x * SCAN_PER_THREAD + i];
+    t += loc[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan(t, &tot) + front;
   for (int i = 0; i < SCAN_PER_THREAD; ++i) {
     buf[threadIdx.x * SCAN_PER_THREAD + i] = run;
     run += loc[i];
@@ -197,6 +242,11 @@ hipError_t launch_scan(uint32_t* data, const int32_t* n_dev, int64_t n_cap, uint
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n_dev, n_cap, tmp);
+  if (nb <= FUSED_BLOCKS) {
+    hipLaunchKernelGGL(k_scan_down_fused, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n_dev, n_cap, tmp, nb,
+                       total_out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, tmp, nb, total_out);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, data, n_dev, n_cap, tmp);
   return hipGetLastError();
