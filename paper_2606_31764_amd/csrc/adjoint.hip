@@ -301,19 +301,17 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
         const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
         const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
         const int nb = row[P_NSAMP];
-        const int32_t ax = w.aux[g];
-        const int ib = ax & 0x7fffffff;
-        const double sgn = ax < 0 ? -1.0 : 1.0;
-        const double2* bp = w.bpts + row[P_BOFF];
+        const int32_t xa = w.aux[g];
+        const int ib = xa & 0x7fffffff;
+        const double sgn = xa < 0 ? -1.0 : 1.0;
+        // the nearest segment's record, with the arithmetic of the emission
+        const double* sr = w.segs + SEG_WORDS * (seg_base(row[P_BOFF], c) + ib);
         const int jb = ib + 1 < nb ? ib + 1 : 0;
-        const double2 A = bp[ib], Bq = bp[jb];
-        const double ex = Bq.x - A.x, ey = Bq.y - A.y;
-        const double ee = ex * ex + ey * ey;
-        const double rx = qx - A.x, ry = qy - A.y;
-        double t = 0.0;
-        if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+        const double ax = sr[0], ay = sr[1], ex = sr[2], ey = sr[3], inv = sr[4];
+        const double rx = qx - ax, ry = qy - ay;
+        double t = (rx * ex + ry * ey) * inv;
         t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+        const double px = ax + t * ex - qx, py = ay + t * ey - qy;
         const double d = sqrt(px * px + py * py);
         const double z = gh * (sgn * d);
         const double sz = 1.0 / (1.0 + exp(-z));

@@ -61,6 +61,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
       sizeof(float) * 3 * (size_t)std::max<int64_t>(n_pix, 1),  // afin
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
+      sizeof(double) * SEG_WORDS * (size_t)(bcap + (SDF_CHUNK - 1) * N + 1),  // segs
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -101,6 +102,7 @@ Work carve(void* ws, const Layout& lay) {
   w.ckbuf = (float*)(b + lay.off[24]);
   w.afin = (float*)(b + lay.off[25]);
   w.gcol = (float4*)(b + lay.off[26]);
+  w.segs = (double*)(b + lay.off[27]);
   return w;
 }
 

@@ -20,7 +20,7 @@ constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 27;                // workspace entries
+constexpr int N_WS = 28;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -67,6 +67,7 @@ struct Work {
   float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries
   float* afin;         // [pixels][3] accumulated colour at each pixel's end of compositing
   float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and 1 for fill Gaussians
+  double* segs;        // [caps.boundary + (SDF_CHUNK - 1) * n_curves][SEG_WORDS] fill SDF segment records
 };
 
 // The compositing lists are cut into chunks of CK list positions, counted
@@ -84,6 +85,16 @@ __host__ __device__ inline int n_chunks(int len) { return (len + CK - 1) / CK; }
 // SDF_CHUNK segments.
 constexpr int SDF_CHUNK = 8;
 __host__ __device__ inline int64_t cbox_base(int64_t boff, int c) { return boff / SDF_CHUNK + 2 * (int64_t)c; }
+
+// Segment records of the fill SDF, SEG_WORDS doubles each: for segment i of
+// a filled curve (b_nb = b_0) the start point b_i, the edge e = b_{i+1} - b_i,
+// 1 / |e|^2 (0 for a zero-length edge) and the end point's y.  Curve c's
+// records start at seg_base(boff, c) and fill whole chunks of SDF_CHUNK:
+// records past its nb segments are zero-length edges at SEG_FAR, which are
+// never nearest (they follow a real segment of their chunk) and never cross.
+constexpr int SEG_WORDS = 6;
+constexpr double SEG_FAR = 1e100;
+__host__ __device__ inline int64_t seg_base(int64_t boff, int c) { return boff + (int64_t)(SDF_CHUNK - 1) * c; }
 
 constexpr int GG = 4;  // floats per Gaussian in Work::ggrad
 

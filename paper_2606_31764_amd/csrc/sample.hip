@@ -269,6 +269,29 @@ __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsp
       }
       box[k] = r;
     }
+    // segment records, padded to whole chunks
+    double* sg = w.segs + SEG_WORDS * seg_base(boff, c);
+    for (int i = threadIdx.x; i < K * SDF_CHUNK; i += PREP_THREADS) {
+      double* o = sg + SEG_WORDS * (int64_t)i;
+      if (i < nb) {
+        const double2 A = bp[i], B = bp[i + 1 < nb ? i + 1 : 0];
+        const double ex = B.x - A.x, ey = B.y - A.y;
+        const double ee = ex * ex + ey * ey;
+        o[0] = A.x;
+        o[1] = A.y;
+        o[2] = ex;
+        o[3] = ey;
+        o[4] = ee > 0.0 ? 1.0 / ee : 0.0;
+        o[5] = B.y;
+      } else {
+        o[0] = SEG_FAR;
+        o[1] = SEG_FAR;
+        o[2] = 0.0;
+        o[3] = 0.0;
+        o[4] = 0.0;
+        o[5] = SEG_FAR;
+      }
+    }
   }
   const int t = threadIdx.x;
   if ((t & 63) == 0) {
@@ -339,7 +362,7 @@ __device__ inline double4 ld_box(P p, int i) {
 }
 
 template <class P>
-__device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, int nb, int* arg, double* targ,
+__device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, P segd, int nb, int* arg, double* targ,
                                       double* sgn_out) {
   const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
   const double4 hb = ld_box(boxd, 0);  // the whole boundary's box
@@ -372,29 +395,27 @@ __device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, int n
       }
     }
     if (visit) {
-      double2 A = ld_pt(bpd, i0);
-      for (int i = i0; i < i1; ++i) {
-        const double2 B = ld_pt(bpd, i + 1 < nb ? i + 1 : 0);
-        const double ex = B.x - A.x, ey = B.y - A.y;
-        const double ee = ex * ex + ey * ey;
-        const double rx = qx - A.x, ry = qy - A.y;
-        double t = 0.0;
-        if (ee > 0.0) t = (rx * ex + ry * ey) / ee;
+      // the chunk's SDF_CHUNK records (padding included), t = (r . e) / |e|^2
+      // taken as a product with the stored reciprocal
+#pragma unroll
+      for (int j = 0; j < SDF_CHUNK; ++j) {
+        const int i = i0 + j;
+        const int64_t o = (int64_t)SEG_WORDS * i;
+        const double ax = segd[o], ay = segd[o + 1], ex = segd[o + 2], ey = segd[o + 3];
+        const double inv = segd[o + 4], by = segd[o + 5];
+        const double rx = qx - ax, ry = qy - ay;
+        double t = (rx * ex + ry * ey) * inv;
         t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double px = A.x + t * ex - qx, py = A.y + t * ey - qy;
+        const double px = ax + t * ex - qx, py = ay + t * ey - qy;
         const double d2 = px * px + py * py;
-        if (d2 < best) {
-          best = d2;
-          ibest = i;
-          tbest = t;
-        }
-        const double cr = ex * ry - rx * ey;  // > 0: q left of A->B
-        if (A.y <= qy) {
-          if (B.y > qy && cr > 0.0) ++wk;
-        } else {
-          if (B.y <= qy && cr < 0.0) --wk;
-        }
-        A = B;
+        const bool nearer = d2 < best;
+        best = nearer ? d2 : best;
+        ibest = nearer ? i : ibest;
+        tbest = nearer ? t : tbest;
+        const double cr = ex * ry - rx * ey;  // > 0: q left of a -> b
+        const bool below = ay <= qy;
+        wk += (below && by > qy && cr > 0.0) ? 1 : 0;
+        wk -= (!below && by <= qy && cr < 0.0) ? 1 : 0;
       }
     }
     wn += wk;
@@ -475,11 +496,13 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
         // the constant address space with uniform indices (scalar loads)
         typedef const __attribute__((address_space(4))) double* cdp;
         const int32_t* ru = plan + (int64_t)P_STRIDE * cu;
-        d = polyline_sdf(qx, qy, (cdp)(w.bpts + ru[P_BOFF]), (cdp)(w.cbox + cbox_base(ru[P_BOFF], cu)), ru[P_NSAMP],
-                         &arg, &t, &sgn);
+        d = polyline_sdf(qx, qy, (cdp)(w.bpts + ru[P_BOFF]), (cdp)(w.cbox + cbox_base(ru[P_BOFF], cu)),
+                         (cdp)(w.segs + SEG_WORDS * seg_base(ru[P_BOFF], cu)), ru[P_NSAMP], &arg, &t, &sgn);
       } else {
         d = polyline_sdf(qx, qy, (const double*)(w.bpts + row[P_BOFF]),
-                         (const double*)(w.cbox + cbox_base(row[P_BOFF], c)), row[P_NSAMP], &arg, &t, &sgn);
+                         (const double*)(w.cbox + cbox_base(row[P_BOFF], c)),
+                         (const double*)(w.segs + SEG_WORDS * seg_base(row[P_BOFF], c)), row[P_NSAMP], &arg, &t,
+                         &sgn);
       }
       const double z = ((double)pr.gamma / h) * (sgn * d);
       r.mx = qx;
