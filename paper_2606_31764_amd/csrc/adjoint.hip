@@ -476,21 +476,21 @@ struct ZeroSet {
   int64_t n[4];
 };
 
-__global__ void k_zero_f64(ZeroSet z) {
+// Clears the per-Gaussian adjoints (min(*count, cap) * mult floats at p) and
+// the FP64 arrays of z, in one launch.
+__global__ void k_zero_grads(float* p, const int32_t* count, int64_t mult, int64_t cap, ZeroSet z) {
+  int64_t n = (int64_t)*count;
+  n = (n < cap ? n : cap) * mult;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < n; i += stride) p[i] = 0.0f;
   const int64_t total = z.n[0] + z.n[1] + z.n[2] + z.n[3];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = i0; i < total; i += stride) {
     int64_t j = i;
     int a = 0;
     while (a < 3 && j >= z.n[a]) j -= z.n[a++];
     z.p[a][j] = 0.0;
   }
-}
-
-__global__ void k_zero_dev(float* p, const int32_t* count, int64_t mult, int64_t cap) {
-  int64_t n = (int64_t)*count;
-  n = (n < cap ? n : cap) * mult;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -955,8 +955,6 @@ hipError_t launch_zero_grads(const Launch& L) {
   const nsplat_curves& cv = *L.cv;
   const int64_t ncp = (int64_t)cv.n_keys + (int64_t)cv.n_curves * CP_PAD;
   const int64_t nkn = (int64_t)cv.n_taus + (int64_t)cv.n_curves * KNOT_PAD;
-  hipLaunchKernelGGL(k_zero_dev, dim3(grid_for(L.bf->caps.gauss * GG, 256, 8192)), dim3(256), 0, L.stream,
-                     L.w.ggrad, L.bf->counters + NSPLAT_CNT_GAUSS, (int64_t)GG, (int64_t)L.bf->caps.gauss);
   ZeroSet z;
   z.p[0] = L.w.gcp;
   z.n[0] = 4 * ncp;
@@ -967,7 +965,9 @@ hipError_t launch_zero_grads(const Launch& L) {
   z.p[3] = (double*)L.w.gb;
   z.n[3] = L.bf->caps.boundary > 0 ? 2 * L.bf->caps.boundary : 0;
   const int64_t total = z.n[0] + z.n[1] + z.n[2] + z.n[3];
-  if (total > 0) hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(total, 256, 4096)), dim3(256), 0, L.stream, z);
+  const int64_t most = std::max<int64_t>(L.bf->caps.gauss * GG, total);
+  hipLaunchKernelGGL(k_zero_grads, dim3(grid_for(most, 256, 8192)), dim3(256), 0, L.stream, L.w.ggrad,
+                     L.bf->counters + NSPLAT_CNT_GAUSS, (int64_t)GG, (int64_t)L.bf->caps.gauss, z);
   return hipGetLastError();
 }
 

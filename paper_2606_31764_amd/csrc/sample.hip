@@ -18,7 +18,7 @@ namespace nsp {
 
 namespace {
 
-constexpr int PREP_THREADS = 256;
+constexpr int PREP_THREADS = 256;  // k_boundary, and k_curve_prep for many curves
 constexpr int PREP_KNOTS = 4096;  // knots held in LDS by k_curve_prep (32 KB)
 
 __global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st) {
@@ -44,6 +44,7 @@ __global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st) 
   st[sc.n_scenes] = e;
 }
 
+template <int THREADS>
 __device__ inline double block_sum(double v, double* red) {
   const int t = threadIdx.x;
 #pragma unroll
@@ -51,7 +52,7 @@ __device__ inline double block_sum(double v, double* red) {
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   double s = 0.0;
-  for (int i = 0; i < PREP_THREADS / 64; ++i) s += red[i];
+  for (int i = 0; i < THREADS / 64; ++i) s += red[i];
   __syncthreads();
   return s;
 }
@@ -64,10 +65,12 @@ __device__ inline int count_rule(double delta, double L, int floor_min) {
   return (int)M;
 }
 
-__global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, nsplat_params pr, Work w,
-                                                             int32_t* plan, int32_t* counters, int frozen,
-                                                             int n_scenes) {
-  __shared__ double red[PREP_THREADS / 64];
+// THREADS lanes per curve: 1024 when there are few curves, so that the N_L
+// midpoints of a curve are spread over more wavefronts.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat_params pr, Work w, int32_t* plan,
+                                                        int32_t* counters, int frozen, int n_scenes) {
+  __shared__ double red[THREADS / 64];
   __shared__ double Us[PREP_KNOTS];
   const int c = blockIdx.x;
   const CurveView v = curve_view(cv, w.knots, c);
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, n
   };
   CurveView vk = v;  // the view the quadrature evaluates: knots in LDS when they fit
   if (v.m + 1 <= PREP_KNOTS) {
-    for (int l = threadIdx.x; l < v.m; l += PREP_THREADS) Us[l + 1] = interval(l);
+    for (int l = threadIdx.x; l < v.m; l += THREADS) Us[l + 1] = interval(l);
     __syncthreads();
     if (threadIdx.x == 0) {
       double acc = 0.0;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, n
       }
     }
     __syncthreads();
-    for (int l = threadIdx.x; l <= v.m; l += PREP_THREADS) U[l] = Us[l];
+    for (int l = threadIdx.x; l <= v.m; l += THREADS) U[l] = Us[l];
     vk.U = Us;
   } else {
     if (threadIdx.x == 0) {
@@ -126,14 +129,14 @@ __global__ __launch_bounds__(PREP_THREADS) void k_curve_prep(nsplat_curves cv, n
   const double a = vk.U[v.p], b = vk.U[v.m - v.p];
   const double du = (b - a) / (double)n_L;
   double part = 0.0;
-  for (int j = 1 + threadIdx.x; j <= n_L; j += PREP_THREADS) {
+  for (int j = 1 + threadIdx.x; j <= n_L; j += THREADS) {
     const double u = a + ((double)j - 0.5) * du;
     const int span = find_span(vk.U, v.p, v.m, u);
     double pt[3], d[3];
     curve_point(cv, vk, u, span, pt, d);
     part += sqrt(d[0] * d[0] + d[1] * d[1]) * du;
   }
-  const double L = block_sum(part, red);
+  const double L = block_sum<THREADS>(part, red);
   if (threadIdx.x == 0) {
     w.L[c] = L;
     if (!frozen) {
@@ -688,8 +691,12 @@ hipError_t launch_sample(const Launch& L, int frozen) {
   int32_t* cnt = L.bf->counters;
   {
   Phase ph(L, NSPLAT_T_PLAN);
-  hipLaunchKernelGGL(k_curve_prep, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan, cnt, frozen,
-                     L.sc->n_scenes);
+  if (n < 1024)
+    hipLaunchKernelGGL(k_curve_prep<1024>, dim3(n), dim3(1024), 0, L.stream, *L.cv, *L.pr, L.w, plan, cnt, frozen,
+                       L.sc->n_scenes);
+  else
+    hipLaunchKernelGGL(k_curve_prep<PREP_THREADS>, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
+                       cnt, frozen, L.sc->n_scenes);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
                      (int64_t)L.bf->caps.boundary);
   hipLaunchKernelGGL(k_boundary, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
