@@ -53,6 +53,11 @@ extern "C" {
 #define NSPLAT_FILLED 2     /* curve flag: filled interior (requires CLOSED) */
 #define NSPLAT_MAX_DEGREE 5
 
+/* Version of the structure layouts below; nsplat_abi_version() returns the
+ * value the library was built with, so a binding can refuse a library whose
+ * structures it would misread. */
+#define NSPLAT_ABI_VERSION 2
+
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
 #define NSPLAT_CNT_PAIRS 1      /* (tile, Gaussian) pairs produced           */
@@ -103,6 +108,11 @@ typedef struct {
   int32_t channels;        /* (host) 1 or 3                                  */
   int32_t n_keys;          /* (host) total key points K                      */
   int32_t n_taus;          /* (host) total knot intervals                    */
+  int32_t max_degree;      /* (host) an upper bound on every degree[c] in
+                              [1, NSPLAT_MAX_DEGREE]; any other value means
+                              NSPLAT_MAX_DEGREE.  A curve above it counts as
+                              invalid data.  A bound of 3 or less selects
+                              adjoint kernels with smaller register arrays */
   const int32_t* scene;    /* (dev) [n_curves] scene of each curve           */
   const int32_t* degree;   /* (dev) [n_curves] p                             */
   const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED */
@@ -176,9 +186,10 @@ typedef struct {
   float* opacity; /* [n_curves] */
 } nsplat_grads;
 
-/* Context: binds the library to device `device` (made current by the caller's
- * thread for every later call).  Holds the last error message and the
- * autotuner's choices. */
+/* NSPLAT_ABI_VERSION as built (no device work).  Context: binds the library
+ * to device `device` (made current by the caller's thread for every later
+ * call).  Holds the last error message and the autotuner's choices. */
+int nsplat_abi_version(void);
 int nsplat_create(nsplat_ctx** ctx, int device);
 int nsplat_destroy(nsplat_ctx* ctx);
 const char* nsplat_last_error(const nsplat_ctx* ctx);

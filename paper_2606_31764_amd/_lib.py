@@ -12,6 +12,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nsplat.h")
 OK, EINVAL, ECAPACITY, EHIP = 0, 1, 2, 3
 CLOSED, FILLED = 1, 2
 MAX_DEGREE = 5
+ABI_VERSION = 2  # NSPLAT_ABI_VERSION of include/nsplat.h
 CNT_GAUSS, CNT_PAIRS, CNT_STATUS, CNT_GAUSS_REQ, CNT_PAIRS_REQ, CNT_BOUND_REQ, CNT_BOUND = range(7)
 NUM_COUNTERS = 16
 STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA = 1, 2, 4, 8
@@ -22,7 +23,7 @@ vp = ctypes.c_void_p
 
 class Curves(ctypes.Structure):
     _fields_ = [("n_curves", ctypes.c_int32), ("channels", ctypes.c_int32), ("n_keys", ctypes.c_int32),
-                ("n_taus", ctypes.c_int32)] + [(n, vp) for n in (
+                ("n_taus", ctypes.c_int32), ("max_degree", ctypes.c_int32)] + [(n, vp) for n in (
                     "scene", "degree", "flags", "key_off", "tau_off", "key_xy", "key_w", "key_s", "tau",
                     "color", "opacity")]
 
@@ -69,6 +70,7 @@ class Adam(ctypes.Structure):
 
 
 _SIGS = {
+    "nsplat_abi_version": (ctypes.c_int, []),
     "nsplat_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
     "nsplat_destroy": (ctypes.c_int, [vp]),
     "nsplat_last_error": (ctypes.c_char_p, [vp]),
@@ -107,6 +109,10 @@ def load():
         for name, (res, args) in _SIGS.items():
             f = getattr(lib, name)
             f.restype, f.argtypes = res, args
+        # the structures below are laid out for this version only
+        if lib.nsplat_abi_version() != ABI_VERSION:
+            raise RuntimeError("libnsplat.so has ABI version %d, this binding expects %d: rebuild it"
+                               % (lib.nsplat_abi_version(), ABI_VERSION))
         _lib = lib
     return _lib
 

@@ -28,26 +28,32 @@ namespace nsp {
 
 namespace {
 
-constexpr int TRI = (MAXP + 1) * (MAXP + 2) / 2;
+// The point and derivative adjoints below hold basis functions and control
+// points in register arrays sized for degree PD, the batch's degree bound (3,
+// or NSPLAT_MAX_DEGREE): smaller arrays for the usual quadratic and cubic
+// curves keep more wavefronts resident.
+constexpr int tri_n(int d) { return (d + 1) * (d + 2) / 2; }
 
+template <int PD>
 struct PtAdj {
-  double cp[MAXP + 1][4];  // (x, y, w, s) of control points span-p..span
-  double knot[2 * MAXP];   // slot k <-> knot index span - MAXP + 1 + k
+  double cp[PD + 1][4];  // (x, y, w, s) of control points span-p..span
+  double knot[2 * PD];   // slot k <-> knot index span - PD + 1 + k
   double ubar;
 };
 
 // Reverse-mode adjoint of the rational point (x, y, s) at u on `span` for the
 // upstream gradient ab[3].
+template <int PD>
 __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v, double u, int span,
-                                     const double (&ab)[3], PtAdj& out) {
+                                     const double (&ab)[3], PtAdj<PD>& out) {
   const double* U = v.U;
   const int p = v.p;
-  double tri[TRI];
-  double N[MAXP + 1], left[MAXP + 1], right[MAXP + 1];
+  double tri[tri_n(PD)];
+  double N[PD + 1], left[PD + 1], right[PD + 1];
   N[0] = 1.0;
   tri[0] = 1.0;
 #pragma unroll
-  for (int d = 1; d <= MAXP; ++d) {
+  for (int d = 1; d <= PD; ++d) {
     if (d > p) break;
     left[d] = u - U[span + 1 - d];
     right[d] = U[span + d] - u;
@@ -63,10 +69,10 @@ __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v
     for (int r = 0; r <= d; ++r) tri[d * (d + 1) / 2 + r] = N[r];
   }
   // C = S / W over the span's control points
-  double P[MAXP + 1][3], wt[MAXP + 1];
+  double P[PD + 1][3], wt[PD + 1];
   double S[3] = {0.0, 0.0, 0.0}, W = 0.0;
 #pragma unroll
-  for (int r = 0; r <= MAXP; ++r) {
+  for (int r = 0; r <= PD; ++r) {
     if (r > p) break;
     const int k = v.k0 + v.key_of_cp(span - p + r);
     wt[r] = (double)cv.key_w[k];
@@ -80,9 +86,9 @@ __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v
   }
   const double invW = 1.0 / W;
   const double Cp[3] = {S[0] * invW, S[1] * invW, S[2] * invW};
-  double Nb[MAXP + 1];
+  double Nb[PD + 1];
 #pragma unroll
-  for (int r = 0; r <= MAXP; ++r) {
+  for (int r = 0; r <= PD; ++r) {
     Nb[r] = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) out.cp[r][q] = 0.0;
@@ -99,13 +105,13 @@ __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v
   //                          + (U_{i+d+1} - u)/(U_{i+d+1} - U_{i+1}) N_{i+1,d-1}
   double ub = 0.0;
 #pragma unroll
-  for (int k = 0; k < 2 * MAXP; ++k) out.knot[k] = 0.0;
+  for (int k = 0; k < 2 * PD; ++k) out.knot[k] = 0.0;
 #pragma unroll
-  for (int d = MAXP; d >= 1; --d) {
+  for (int d = PD; d >= 1; --d) {
     if (d > p) continue;
-    double Np[MAXP + 1];
+    double Np[PD + 1];
 #pragma unroll
-    for (int r = 0; r <= MAXP; ++r) Np[r] = 0.0;
+    for (int r = 0; r <= PD; ++r) Np[r] = 0.0;
 #pragma unroll
     for (int r = 0; r <= d; ++r) {
       const double nb = Nb[r];
@@ -117,8 +123,8 @@ __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v
         Np[r - 1] += nb * al;
         const double g = nb * tri[(d - 1) * d / 2 + r - 1];
         ub += g / D;
-        out.knot[MAXP - 1 - d + r] -= g * (Uid - u) / (D * D);
-        out.knot[MAXP - 1 + r] -= g * (u - Ui) / (D * D);
+        out.knot[PD - 1 - d + r] -= g * (Uid - u) / (D * D);
+        out.knot[PD - 1 + r] -= g * (u - Ui) / (D * D);
       }
       if (r <= d - 1) {
         const double Ui1 = U[i + 1], Uid1 = U[i + d + 1];
@@ -127,12 +133,12 @@ __device__ inline void point_adjoint(const nsplat_curves& cv, const CurveView& v
         Np[r] += nb * be;
         const double g = nb * tri[(d - 1) * d / 2 + r];
         ub -= g / D;
-        out.knot[MAXP + r] += g * (u - Ui1) / (D * D);
-        out.knot[MAXP - d + r] += g * (Uid1 - u) / (D * D);
+        out.knot[PD + r] += g * (u - Ui1) / (D * D);
+        out.knot[PD - d + r] += g * (Uid1 - u) / (D * D);
       }
     }
 #pragma unroll
-    for (int r = 0; r <= MAXP; ++r) Nb[r] = Np[r];
+    for (int r = 0; r <= PD; ++r) Nb[r] = Np[r];
   }
   out.ubar = ub;
 }
@@ -167,23 +173,24 @@ __device__ inline bool seg_head(int64_t key) {
 
 // Wave-cooperative accumulation of point adjoints into the FP64 control-point
 // and knot buffers.  Every lane of the wavefront must call it.
+template <int PD>
 __device__ inline void accumulate_points(const Work& w, int64_t key, int c, const CurveView& v, int span,
-                                         PtAdj& pa, bool any) {
+                                         PtAdj<PD>& pa, bool any) {
   if (!any) return;
-  constexpr int NCP = 4 * (MAXP + 1);
-  double buf[NCP + 2 * MAXP];
+  constexpr int NCP = 4 * (PD + 1);
+  double buf[NCP + 2 * PD];
 #pragma unroll
-  for (int r = 0; r <= MAXP; ++r)
+  for (int r = 0; r <= PD; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) buf[4 * r + q] = pa.cp[r][q];
 #pragma unroll
-  for (int k = 0; k < 2 * MAXP; ++k) buf[NCP + k] = pa.knot[k];
+  for (int k = 0; k < 2 * PD; ++k) buf[NCP + k] = pa.knot[k];
   seg_reduce(key, buf);
   if (seg_head(key)) {
     double* gcp = w.gcp + 4 * ((int64_t)v.k0 + (int64_t)c * CP_PAD);
     double* gk = w.gknot + (int64_t)v.t0 + (int64_t)c * KNOT_PAD;
 #pragma unroll
-    for (int r = 0; r <= MAXP; ++r) {
+    for (int r = 0; r <= PD; ++r) {
       if (r > v.p) break;
       const int j = span - v.p + r;
 #pragma unroll
@@ -191,9 +198,9 @@ __device__ inline void accumulate_points(const Work& w, int64_t key, int c, cons
         if (buf[4 * r + q] != 0.0) unsafeAtomicAdd(gcp + 4 * j + q, buf[4 * r + q]);
     }
 #pragma unroll
-    for (int k = 0; k < 2 * MAXP; ++k) {
-      if (k < MAXP - v.p || k > MAXP + v.p - 1) continue;
-      if (buf[NCP + k] != 0.0) unsafeAtomicAdd(gk + span - MAXP + 1 + k, buf[NCP + k]);
+    for (int k = 0; k < 2 * PD; ++k) {
+      if (k < PD - v.p || k > PD + v.p - 1) continue;
+      if (buf[NCP + k] != 0.0) unsafeAtomicAdd(gk + span - PD + 1 + k, buf[NCP + k]);
     }
   }
 }
@@ -213,6 +220,7 @@ __device__ inline void accumulate_curve(const Work& w, int64_t key, int c, const
 }
 
 // Stroke Gaussians: dL/d(mu, sigma) -> the curve point adjoint at u_j.
+template <int PD>
 __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_params pr, Work w,
                                                     const int32_t* plan, const int32_t* counters,
                                                     const Gauss* __restrict__ gs) {
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_par
     const int64_t g = base + lane;
     int64_t kspan = -1 - lane, kcur = -1 - lane;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    PtAdj pa;
+    PtAdj<PD> pa;
     int c = 0, span = 0;
     CurveView v;
     v.p = 0;
@@ -253,11 +261,11 @@ __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_par
     }
     if (!stroke) {
 #pragma unroll
-      for (int r = 0; r <= MAXP; ++r)
+      for (int r = 0; r <= PD; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) pa.cp[r][q] = 0.0;
 #pragma unroll
-      for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+      for (int k = 0; k < 2 * PD; ++k) pa.knot[k] = 0.0;
     }
     const bool any = __ballot(stroke) != 0ull;
     accumulate_points(w, kspan, c, v, span, pa, any);
@@ -344,6 +352,7 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
   }
 }
 
+template <int PD>
 __global__ __launch_bounds__(256) void k_adj_boundary(nsplat_curves cv, Work w, const int32_t* plan,
                                                       const int32_t* counters) {
   const int64_t NB = counters[NSPLAT_CNT_BOUND];
@@ -355,13 +364,13 @@ __global__ __launch_bounds__(256) void k_adj_boundary(nsplat_curves cv, Work w, 
     const int64_t b = base + lane;
     bool act = false;
     int64_t kspan = -1 - lane, kcur = -1 - lane;
-    PtAdj pa;
+    PtAdj<PD> pa;
 #pragma unroll
-    for (int r = 0; r <= MAXP; ++r)
+    for (int r = 0; r <= PD; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) pa.cp[r][q] = 0.0;
 #pragma unroll
-    for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+    for (int k = 0; k < 2 * PD; ++k) pa.knot[k] = 0.0;
     pa.ubar = 0.0;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int c = 0, span = 0;
@@ -510,17 +519,18 @@ constexpr int MAXR = 3;  // highest derivative order of the derivative loss
 //   C^(k) = (A^(k) - sum_{i=1..k} binom(k, i) W^(i) C^(k-i)) / W, (A, W) = S.
 // Reverse: the same steps backwards, with the adjoint of the degree p - k
 // basis functions entering the Cox-de Boor triangle at its level p - k.
+template <int PD>
 __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView& v, double u, int span, int r,
-                                       double scale, PtAdj& out) {
+                                       double scale, PtAdj<PD>& out) {
   const double* U = v.U;
   const int p = v.p;
   const int R = r < p ? r : p;
-  double tri[TRI];
-  double N[MAXP + 1], left[MAXP + 1], right[MAXP + 1];
+  double tri[tri_n(PD)];
+  double N[PD + 1], left[PD + 1], right[PD + 1];
   N[0] = 1.0;
   tri[0] = 1.0;
 #pragma unroll
-  for (int d = 1; d <= MAXP; ++d) {
+  for (int d = 1; d <= PD; ++d) {
     if (d > p) break;
     left[d] = u - U[span + 1 - d];
     right[d] = U[span + d] - u;
@@ -535,10 +545,10 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
 #pragma unroll
     for (int q = 0; q <= d; ++q) tri[d * (d + 1) / 2 + q] = N[q];
   }
-  double X[MAXP + 1], Y[MAXP + 1], Wt[MAXP + 1];
-  double PK[MAXR + 1][MAXP + 1][3];
+  double X[PD + 1], Y[PD + 1], Wt[PD + 1];
+  double PK[MAXR + 1][PD + 1][3];
 #pragma unroll
-  for (int j = 0; j <= MAXP; ++j) {
+  for (int j = 0; j <= PD; ++j) {
     X[j] = Y[j] = Wt[j] = 0.0;
     if (j > p) continue;
     const int k = v.k0 + v.key_of_cp(span - p + j);
@@ -553,7 +563,7 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
   for (int k = 1; k <= MAXR; ++k) {
     if (k > R) break;
 #pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
+    for (int j = 0; j < PD; ++j) {
       if (j > p - k) break;
       const double c = (double)(p - k + 1) / (U[span + j + 1] - U[span - p + j + k]);
 #pragma unroll
@@ -568,7 +578,7 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
     S[k][0] = S[k][1] = S[k][2] = 0.0;
     if (k > R) continue;
 #pragma unroll
-    for (int d = 0; d <= MAXP; ++d) {
+    for (int d = 0; d <= PD; ++d) {
       if (d != p - k) continue;
 #pragma unroll
       for (int j = 0; j <= d; ++j) {
@@ -621,11 +631,11 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
     dS[0][2] -= gx * Cx[k] + gy * Cy[k];
   }
   // reverse: S^(k) = sum_j N_{p-k}[j] PK_k[j]
-  double dPK[MAXR + 1][MAXP + 1][3], dN[MAXR + 1][MAXP + 1];
+  double dPK[MAXR + 1][PD + 1][3], dN[MAXR + 1][PD + 1];
 #pragma unroll
   for (int k = 0; k <= MAXR; ++k)
 #pragma unroll
-    for (int j = 0; j <= MAXP; ++j) {
+    for (int j = 0; j <= PD; ++j) {
       dN[k][j] = 0.0;
       dPK[k][j][0] = dPK[k][j][1] = dPK[k][j][2] = 0.0;
     }
@@ -633,7 +643,7 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
   for (int k = 0; k <= MAXR; ++k) {
     if (k > R) continue;
 #pragma unroll
-    for (int d = 0; d <= MAXP; ++d) {
+    for (int d = 0; d <= PD; ++d) {
       if (d != p - k) continue;
 #pragma unroll
       for (int j = 0; j <= d; ++j) {
@@ -644,14 +654,14 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
       }
     }
   }
-  // reverse: derivative control points; knot slot s <-> knot index span - MAXP + 1 + s
+  // reverse: derivative control points; knot slot s <-> knot index span - PD + 1 + s
 #pragma unroll
-  for (int k = 0; k < 2 * MAXP; ++k) out.knot[k] = 0.0;
+  for (int k = 0; k < 2 * PD; ++k) out.knot[k] = 0.0;
 #pragma unroll
   for (int k = MAXR; k >= 1; --k) {
     if (k > R) continue;
 #pragma unroll
-    for (int j = 0; j < MAXP; ++j) {
+    for (int j = 0; j < PD; ++j) {
       if (j > p - k) break;
       const int hi = span + j + 1, lo = span - p + j + k;
       const double D = U[hi] - U[lo];
@@ -664,15 +674,15 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
         dD -= dPK[k][j][q] * PK[k][j][q];
       }
       dD /= D;
-      out.knot[j + MAXP] += dD;  // slot of knot hi = span + j + 1
+      out.knot[j + PD] += dD;  // slot of knot hi = span + j + 1
 #pragma unroll
-      for (int sl = 0; sl < 2 * MAXP; ++sl)
-        if (sl == lo - span + MAXP - 1) out.knot[sl] -= dD;
+      for (int sl = 0; sl < 2 * PD; ++sl)
+        if (sl == lo - span + PD - 1) out.knot[sl] -= dD;
     }
   }
   // homogeneous control points -> (x, y, w); the width does not enter
 #pragma unroll
-  for (int j = 0; j <= MAXP; ++j) {
+  for (int j = 0; j <= PD; ++j) {
     out.cp[j][0] = out.cp[j][1] = out.cp[j][2] = out.cp[j][3] = 0.0;
     if (j > p) continue;
     out.cp[j][0] = Wt[j] * dPK[0][j][0];
@@ -681,22 +691,22 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
   }
   // reverse through the Cox-de Boor triangle (as point_adjoint), the degree
   // p - k adjoint dN[k] joining at level p - k
-  double Nb[MAXP + 1];
+  double Nb[PD + 1];
 #pragma unroll
-  for (int q = 0; q <= MAXP; ++q) Nb[q] = dN[0][q];
+  for (int q = 0; q <= PD; ++q) Nb[q] = dN[0][q];
   double ub = 0.0;
 #pragma unroll
-  for (int d = MAXP; d >= 1; --d) {
+  for (int d = PD; d >= 1; --d) {
     if (d > p) continue;
 #pragma unroll
     for (int k = 1; k <= MAXR; ++k)
       if (k <= R && d == p - k) {
 #pragma unroll
-        for (int q = 0; q <= MAXP; ++q) Nb[q] += dN[k][q];
+        for (int q = 0; q <= PD; ++q) Nb[q] += dN[k][q];
       }
-    double Np[MAXP + 1];
+    double Np[PD + 1];
 #pragma unroll
-    for (int q = 0; q <= MAXP; ++q) Np[q] = 0.0;
+    for (int q = 0; q <= PD; ++q) Np[q] = 0.0;
 #pragma unroll
     for (int q = 0; q <= d; ++q) {
       const double nb = Nb[q];
@@ -707,8 +717,8 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
         Np[q - 1] += nb * (u - Ui) / D;
         const double g = nb * tri[(d - 1) * d / 2 + q - 1];
         ub += g / D;
-        out.knot[MAXP - 1 - d + q] -= g * (Uid - u) / (D * D);
-        out.knot[MAXP - 1 + q] -= g * (u - Ui) / (D * D);
+        out.knot[PD - 1 - d + q] -= g * (Uid - u) / (D * D);
+        out.knot[PD - 1 + q] -= g * (u - Ui) / (D * D);
       }
       if (q <= d - 1) {
         const double Ui1 = U[i + 1], Uid1 = U[i + d + 1];
@@ -716,12 +726,12 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
         Np[q] += nb * (Uid1 - u) / D;
         const double g = nb * tri[(d - 1) * d / 2 + q];
         ub -= g / D;
-        out.knot[MAXP + q] += g * (u - Ui1) / (D * D);
-        out.knot[MAXP - d + q] += g * (Uid1 - u) / (D * D);
+        out.knot[PD + q] += g * (u - Ui1) / (D * D);
+        out.knot[PD - d + q] += g * (Uid1 - u) / (D * D);
       }
     }
 #pragma unroll
-    for (int q = 0; q <= MAXP; ++q) Nb[q] = Np[q];
+    for (int q = 0; q <= PD; ++q) Nb[q] = Np[q];
   }
   out.ubar = ub;
   return value;
@@ -816,7 +826,8 @@ __device__ inline void block_loss(double a, double b, float* loss) {
 // Stroke samples (one lane per stroke Gaussian; endpoint copies skipped): the
 // box gradient joins the Gaussian's centre adjoint, the derivative loss goes
 // straight to the control points, knots and domain ends.
-__global__ __launch_bounds__(256) void k_reg_stroke(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
+template <int PD>
+__global__ __launch_bounds__(256, PD <= 3 ? 2 : 1) void k_reg_stroke(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
                                                     const int32_t* counters, const Gauss* __restrict__ gs,
                                                     int kappa) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
@@ -828,7 +839,7 @@ __global__ __launch_bounds__(256) void k_reg_stroke(nsplat_curves cv, Work w, Re
     const int64_t g = base + lane;
     int64_t kspan = -1 - lane, kcur = -1 - lane;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    PtAdj pa;
+    PtAdj<PD> pa;
     int c = 0, span = 0;
     CurveView v;
     v.p = 0;
@@ -866,11 +877,11 @@ __global__ __launch_bounds__(256) void k_reg_stroke(nsplat_curves cv, Work w, Re
     }
     if (!act) {
 #pragma unroll
-      for (int q = 0; q <= MAXP; ++q)
+      for (int q = 0; q <= PD; ++q)
 #pragma unroll
         for (int k = 0; k < 4; ++k) pa.cp[q][k] = 0.0;
 #pragma unroll
-      for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+      for (int k = 0; k < 2 * PD; ++k) pa.knot[k] = 0.0;
     }
     const bool any = __ballot(act) != 0ull;
     accumulate_points(w, kspan, c, v, span, pa, any);
@@ -881,7 +892,8 @@ __global__ __launch_bounds__(256) void k_reg_stroke(nsplat_curves cv, Work w, Re
 
 // Fill boundary samples (one lane per boundary point): the box gradient joins
 // the boundary-point adjoint, the derivative loss goes straight to the curve.
-__global__ __launch_bounds__(256) void k_reg_boundary(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
+template <int PD>
+__global__ __launch_bounds__(256, PD <= 3 ? 2 : 1) void k_reg_boundary(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
                                                       const int32_t* counters) {
   const int64_t NB = counters[NSPLAT_CNT_BOUND];
   const int lane = __lane_id();
@@ -893,7 +905,7 @@ __global__ __launch_bounds__(256) void k_reg_boundary(nsplat_curves cv, Work w, 
     const int64_t bi = base + lane;
     int64_t kspan = -1 - lane, kcur = -1 - lane;
     double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    PtAdj pa;
+    PtAdj<PD> pa;
     int c = 0, span = 0;
     CurveView v;
     v.p = 0;
@@ -935,11 +947,11 @@ __global__ __launch_bounds__(256) void k_reg_boundary(nsplat_curves cv, Work w, 
     }
     if (!act) {
 #pragma unroll
-      for (int q = 0; q <= MAXP; ++q)
+      for (int q = 0; q <= PD; ++q)
 #pragma unroll
         for (int k = 0; k < 4; ++k) pa.cp[q][k] = 0.0;
 #pragma unroll
-      for (int k = 0; k < 2 * MAXP; ++k) pa.knot[k] = 0.0;
+      for (int k = 0; k < 2 * PD; ++k) pa.knot[k] = 0.0;
     }
     const bool any = __ballot(act) != 0ull;
     accumulate_points(w, kspan, c, v, span, pa, any);
@@ -971,6 +983,31 @@ hipError_t launch_zero_grads(const Launch& L) {
   return hipGetLastError();
 }
 
+// Array bound of the point and derivative adjoints: 3 when the batch declares
+// no degree above 3 (curve_valid rejects any curve above the bound).
+inline bool low_degree(const Launch& L) { return L.cv->max_degree >= 1 && L.cv->max_degree <= 3; }
+
+template <int PD>
+void launch_reg_d(const Launch& L, const RegArgs& ra) {
+  hipLaunchKernelGGL(k_reg_stroke<PD>, dim3(grid_for(L.bf->caps.gauss, 256, 4096)), dim3(256), 0, L.stream, *L.cv,
+                     L.w, ra, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss, L.pr->kappa);
+  if (L.bf->caps.boundary > 0)
+    hipLaunchKernelGGL(k_reg_boundary<PD>, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
+                       *L.cv, L.w, ra, L.bf->plan, L.bf->counters);
+}
+
+template <int PD>
+void launch_adj_stroke_d(const Launch& L) {
+  hipLaunchKernelGGL(k_adj_stroke<PD>, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                     *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+}
+
+template <int PD>
+void launch_adj_boundary_d(const Launch& L) {
+  hipLaunchKernelGGL(k_adj_boundary<PD>, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
+                     *L.cv, L.w, L.bf->plan, L.bf->counters);
+}
+
 hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
   Phase ph(L, NSPLAT_T_REG);
   RegArgs ra;
@@ -980,26 +1017,23 @@ hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
   ra.deriv_order = reg->deriv_order;
   ra.bbox = reg->bbox;
   ra.loss = reg->loss;
-  hipLaunchKernelGGL(k_reg_stroke, dim3(grid_for(L.bf->caps.gauss, 256, 4096)), dim3(256), 0, L.stream, *L.cv, L.w,
-                     ra, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss, L.pr->kappa);
-  if (L.bf->caps.boundary > 0)
-    hipLaunchKernelGGL(k_reg_boundary, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
-                       *L.cv, L.w, ra, L.bf->plan, L.bf->counters);
+  if (low_degree(L)) launch_reg_d<3>(L, ra);
+  else launch_reg_d<MAXP>(L, ra);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g) {
   {
     Phase ph(L, NSPLAT_T_ADJ_GAUSS);
-    hipLaunchKernelGGL(k_adj_stroke, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
-                       *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+    if (low_degree(L)) launch_adj_stroke_d<3>(L);
+    else launch_adj_stroke_d<MAXP>(L);
     hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
                        *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
   }
   if (L.bf->caps.boundary > 0) {
     Phase ph(L, NSPLAT_T_ADJ_BOUND);
-    hipLaunchKernelGGL(k_adj_boundary, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
-                       *L.cv, L.w, L.bf->plan, L.bf->counters);
+    if (low_degree(L)) launch_adj_boundary_d<3>(L);
+    else launch_adj_boundary_d<MAXP>(L);
   }
   Phase ph(L, NSPLAT_T_FOLD);
   if (L.cv->n_curves > 0)

@@ -253,6 +253,8 @@ int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, c
 
 extern "C" {
 
+int nsplat_abi_version(void) { return NSPLAT_ABI_VERSION; }
+
 int nsplat_create(nsplat_ctx** out, int device) {
   if (!out) return NSPLAT_EINVAL;
   *out = nullptr;

@@ -40,7 +40,7 @@ class _Fake:
     def __init__(self, n_curves=2, channels=3, hw=((64, 48),)):
         self.hw = np.ascontiguousarray(hw, np.int32)
         fake = ctypes.c_void_p(0x1000)
-        self.curves = L.Curves(n_curves, channels, 16, 10, *([fake] * 11))
+        self.curves = L.Curves(n_curves, channels, 16, 10, 0, *([fake] * 11))
         self.scenes = L.Scenes(len(self.hw), ctypes.c_void_p(self.hw.ctypes.data), fake, fake)
         self.params = L.Params(10, 0.5, 2, 1.5, 5, 3, 0.1, 1.0, 6.0, 0.99, 1e-6, 4, 16, 64, None)
         self.caps = L.Caps(1000, 4000, 100)
@@ -99,3 +99,36 @@ def test_small_workspace_and_null_context(lib):
                               ctypes.byref(_bufs(lib, f)[0]), None, None, None, 0, None) == L.EINVAL
     assert lib.nsplat_anneal_h(h, None, None, 0, 10, 8.0, 1.0, 0.1, 0.8, None) == L.EINVAL
     lib.nsplat_destroy(h)
+
+
+def test_abi_version_matches_header(lib):
+    import re
+    txt = open(L.HEADER).read()
+    v = int(re.search(r"#define NSPLAT_ABI_VERSION (\d+)", txt).group(1))
+    assert L.ABI_VERSION == v
+    assert lib.nsplat_abi_version() == v
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets of the ctypes structures against the C compiler's
+    # view of include/nsplat.h (a binding that misreads a structure hands the
+    # library shifted device pointers)
+    import os
+    structs = {"nsplat_curves": L.Curves, "nsplat_scenes": L.Scenes, "nsplat_params": L.Params,
+               "nsplat_caps": L.Caps, "nsplat_buffers": L.Buffers, "nsplat_grads": L.Grads, "nsplat_reg": L.Reg,
+               "nsplat_values": L.Values, "nsplat_adam": L.Adam}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "nsplat.h"', "int main(void) {"]
+    expect = []
+    for cname, cls in structs.items():
+        lines.append('  printf("%%zu\\n", sizeof(%s));' % cname)
+        expect.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            lines.append('  printf("%%zu\\n", offsetof(%s, %s));' % (cname, f[0]))
+            expect.append(getattr(cls, f[0]).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(L.HEADER), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).decode().split()]
+    assert got == expect

@@ -126,6 +126,45 @@ def test_invalid_curves_set_status_and_are_skipped():
     np.testing.assert_array_equal(out["image"], ref["image"])
 
 
+def test_declared_degree_bound_rejects_higher_degrees():
+    # a batch that declares degree <= 3 but holds a degree-4 curve: that curve
+    # is invalid data (no Gaussians, status bit), the rest renders and
+    # differentiates as without it, through the degree-3 adjoint kernels
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    rng = np.random.default_rng(41)
+    good = [_part(rng.uniform(6, 42, (6, 2)), p=3, seed=1, color=(0.9, 0.2, 0.1)),
+            _part(rng.uniform(6, 42, (5, 2)), p=2, closed=True, seed=2, color=(0.1, 0.3, 0.8))]
+    high = _part(rng.uniform(6, 42, (7, 2)), p=4, seed=3)
+    p = Params().replace(delta_c=2.0)
+    b_good = _batch(good)
+    b_all = _batch(good + [high])
+    op = oracle_params(p)
+    target = oracle.render(synth.perturbed(b_good, seed=8), op)[0]
+    r = Renderer(b_all, p)
+    assert r.meta.max_degree == 4
+    r.meta.max_degree = 3
+    t = param_tensors(b_all)
+    img = r.run_forward(t).clone()
+    counters = r.read_counters()
+    plan = r.plan_np()
+    assert counters[2] & 8  # NSPLAT_STATUS_DATA
+    assert plan[2, 0] == 0 and plan[0, 0] > 0 and plan[1, 0] > 0
+    img_ref, _, _ = oracle.render(b_good, op)
+    assert np.abs(img.cpu().numpy() - img_ref).max() <= IMG_TOL
+    grads = r.backward(t, 2.0 * (img - torch.as_tensor(target, dtype=torch.float32, device="cuda")))
+    torch.cuda.synchronize()
+    from helpers import PARAM_NAMES
+    g = {n: x.cpu().numpy().astype(np.float64) for n, x in zip(PARAM_NAMES, grads)}
+    _, gref, _, _ = oracle.loss_and_grad(b_good, target, op)
+    nk, nt = int(b_good.key_off[-1]), int(b_good.tau_off[-1])
+    cut = dict(key_xy=2 * nk, key_w=nk, key_s=nk, tau=nt, color=3 * len(good), opacity=len(good))
+    mine = {n: g[n].ravel()[:cut[n]] for n in PARAM_NAMES}
+    assert grad_close(mine, gref) <= 1.0, grad_report(mine, gref)
+    for n in PARAM_NAMES:
+        assert np.all(g[n].ravel()[cut[n]:] == 0.0), n
+
+
 def test_capacity_growth_gives_same_result():
     b = synth.config3(seed=3700, n_paths=5, size=64)
     p = Params().replace(h=2.0)
