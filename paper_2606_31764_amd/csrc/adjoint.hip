@@ -224,6 +224,7 @@ template <int PD>
 __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_params pr, Work w,
                                                     const int32_t* plan, const int32_t* counters,
                                                     const Gauss* __restrict__ gs) {
+  if (w.queue[Q_NSTROKE] == 0) return;  // no Gaussians of this kind
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const int lane = __lane_id();
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_par
 // d(d)/db = -t n at the projection, n the unit vector from it to q).
 __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
                                                   const int32_t* counters, const Gauss* __restrict__ gs) {
+  if (w.queue[Q_NFILL] == 0) return;  // no Gaussians of this kind
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const int lane = __lane_id();
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
@@ -830,6 +832,7 @@ template <int PD>
 __global__ __launch_bounds__(256, PD <= 3 ? 2 : 1) void k_reg_stroke(nsplat_curves cv, Work w, RegArgs ra, const int32_t* plan,
                                                     const int32_t* counters, const Gauss* __restrict__ gs,
                                                     int kappa) {
+  if (w.queue[Q_NSTROKE] == 0) return;  // no Gaussians of this kind
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const int lane = __lane_id();
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;

@@ -300,8 +300,7 @@ int nsplat_sample(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes*
   Launch L;
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
-  hipError_t h = launch_fill_u32((uint32_t*)bf->counters, 0u, NSPLAT_NUM_COUNTERS, L.stream);
-  if (h == hipSuccess) h = launch_scene_setup(L);
+  hipError_t h = launch_scene_setup(L, bf->counters);
   if (h == hipSuccess && cv->n_curves > 0) h = launch_sample(L, frozen);
   if (h == hipSuccess && cv->n_curves == 0) h = launch_fill_u32((uint32_t*)L.w.goff, 0u, 1, L.stream);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_sample");
@@ -313,7 +312,7 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   Launch L;
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
-  hipError_t h = launch_scene_setup(L);
+  hipError_t h = launch_scene_setup(L, nullptr);
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
   return NSPLAT_OK;

@@ -6,7 +6,8 @@
 //   radix passes  stable LSD radix sort on the key (histogram, scan, scatter
 //                 with wavefront match-ranking), so each tile keeps ascending
 //                 Gaussian order
-//   k_tile_ranges [begin, end) of every tile's slice
+//   k_tile_ranges [begin, end) of every tile's slice (after a one-pass sort the
+//                 tile plan reads them off the scanned digit counts instead)
 //   k_order_*     the blend kernels' tile order, longest lists first
 //   k_chunk_counts, k_item_counts + scans: checkpoint slots per tile and the
 //                 adjoint's (tile, quadrant, chunk) items in blend order
@@ -347,13 +348,29 @@ __device__ inline uint32_t plan_wave_scan(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(const int32_t* __restrict__ ranges, int n_tiles,
-                                                            int quads, int32_t* __restrict__ order,
-                                                            int32_t* __restrict__ ck_off,
-                                                            int32_t* __restrict__ item_off) {
+// With `hist` (the scanned digit counts of a one-pass sort, `sb` blocks per
+// digit, `nd` digits) it first writes every tile's range: tile t is digit t,
+// its slice starts at the digit's first offset and ends where digit t + 1
+// starts (or at the pair count); empty tiles get [0, 0).
+__global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict__ ranges, int n_tiles, int quads,
+                                                            int32_t* __restrict__ order, int32_t* __restrict__ ck_off,
+                                                            int32_t* __restrict__ item_off,
+                                                            const uint32_t* __restrict__ hist, int sb, int nd,
+                                                            const int32_t* counters) {
   __shared__ int h[32], base[32];
   __shared__ uint32_t wsum[2][PLAN_THREADS / 64];
   const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  if (hist) {
+    const uint32_t total = (uint32_t)counters[NSPLAT_CNT_PAIRS];
+    for (int t = tid; t < n_tiles; t += PLAN_THREADS) {
+      const uint32_t s0 = hist[(int64_t)t * sb];
+      const uint32_t s1 = t + 1 < nd ? hist[(int64_t)(t + 1) * sb] : total;
+      const bool any = s1 > s0;
+      ranges[2 * t] = any ? (int32_t)s0 : 0;
+      ranges[2 * t + 1] = any ? (int32_t)s1 : 0;
+    }
+    __syncthreads();
+  }
   if (tid < 32) h[tid] = 0;
   __syncthreads();
   for (int t = tid; t < n_tiles; t += PLAN_THREADS) atomicAdd(&h[len_class(ranges, t)], 1);
@@ -481,12 +498,17 @@ hipError_t launch_bin(const Launch& L) {
   }
   {
     Phase ph(L, NSPLAT_T_RANGES);
-    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
-                       L.bf->ranges);
     const int nt = (int)L.n_tiles, ob = (nt + 255) / 256;
+    // a one-pass sort's scanned digit counts are the tile ranges already
+    const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
+    const bool from_hist = passes == 1 && sb > 0 && nt > 0 && nt <= SMALL_TILES;
+    if (!from_hist)
+      hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
+                         L.bf->ranges);
     if (nt > 0 && nt <= SMALL_TILES) {
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, nt,
-                         L.pr->tile == 8 ? 1 : 4, L.w.order, L.w.ck_off, L.w.item_off);
+                         L.pr->tile == 8 ? 1 : 4, L.w.order, L.w.ck_off, L.w.item_off,
+                         from_hist ? (const uint32_t*)L.w.hist : nullptr, sb, 1 << key_bits, cnt);
     } else if (nt > 0) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
       hipLaunchKernelGGL(k_order_count, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin);

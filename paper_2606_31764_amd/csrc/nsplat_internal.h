@@ -56,7 +56,7 @@ struct Work {
   double* gknot;       // [n_taus + n_curves * KNOT_PAD]
   double* gcurve;      // [n_curves][4] (opacity, colour 0..2)
   double2* gb;         // [caps.boundary] boundary-point adjoints
-  int32_t* queue;      // [4] work-queue counters of the persistent kernels
+  int32_t* queue;      // [64] work-queue counters of the persistent kernels (0-3), Gaussians by kind (Q_*)
   int32_t* aux;        // [caps.gauss] fill Gaussians: nearest boundary segment, sign in bit 31
   double4* cbox;       // [caps.boundary / SDF_CHUNK + 2 * n_curves + 2] fill SDF chunk boxes
   int32_t* order;      // [tiles at the smallest tile size] tiles by decreasing list length
@@ -97,6 +97,11 @@ constexpr double SEG_FAR = 1e100;
 __host__ __device__ inline int64_t seg_base(int64_t boff, int c) { return boff + (int64_t)(SDF_CHUNK - 1) * c; }
 
 constexpr int GG = 4;  // floats per Gaussian in Work::ggrad
+
+// Work::queue slots with the number of fill and of stroke Gaussians the
+// sampling pass asked for (written with the Gaussian offsets), which lets the
+// per-kind adjoint kernels return at once when there are none.
+constexpr int Q_NFILL = 8, Q_NSTROKE = 9;
 
 struct Layout {
   size_t off[N_WS];
@@ -344,7 +349,8 @@ struct Launch {
   int n_cu;
 };
 
-hipError_t launch_scene_setup(const Launch& L);
+// Scene table; also clears the NSPLAT_NUM_COUNTERS counters when given.
+hipError_t launch_scene_setup(const Launch& L, int32_t* clear_counters);
 hipError_t launch_sample(const Launch& L, int frozen);
 hipError_t launch_bin(const Launch& L);
 hipError_t launch_blend_fwd(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent);

@@ -21,7 +21,9 @@ namespace {
 constexpr int PREP_THREADS = 256;  // k_boundary, and k_curve_prep for many curves
 constexpr int PREP_KNOTS = 4096;  // knots held in LDS by k_curve_prep (32 KB)
 
-__global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st) {
+__global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st, int32_t* clear_counters) {
+  if (clear_counters && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < NSPLAT_NUM_COUNTERS; i += blockDim.x) clear_counters[i] = 0;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int32_t toff = 0, poff = 0;
   for (int s = 0; s < sc.n_scenes; ++s) {
@@ -155,21 +157,32 @@ __global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat
 // Exclusive scan over curves of one plan column into another (single block).
 // which == 0: boundary points of filled curves -> P_BOFF, total to
 // counters[BOUND_REQ]; which == 1: Gaussians -> P_GOFF and goff[], total to
-// counters[GAUSS_REQ], capped total to counters[GAUSS].
+// counters[GAUSS_REQ], capped total to counters[GAUSS], and the number of
+// fill and of stroke Gaussians to kinds[0], kinds[1].
 __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* plan, int32_t* goff,
-                                                     int32_t* counters, int which, int64_t cap) {
+                                                     int32_t* counters, int which, int64_t cap, int32_t* kinds) {
   __shared__ int64_t wsum[16];
+  __shared__ int64_t fsum[16];
   const int n = cv.n_curves;
   const int per = (n + 1023) / 1024;
   const int c0 = threadIdx.x * per;
-  int64_t s = 0;
+  int64_t s = 0, sf = 0;
   for (int i = 0; i < per; ++i) {
     const int c = c0 + i;
     if (c < n) {
       const int32_t* row = plan + (int64_t)P_STRIDE * c;
-      if (which == 0) s += ((cv.flags[c] & NSPLAT_FILLED) && row[P_NSAMP] > 0) ? row[P_NSAMP] : 0;
-      else s += row[P_COUNT];
+      if (which == 0) {
+        s += ((cv.flags[c] & NSPLAT_FILLED) && row[P_NSAMP] > 0) ? row[P_NSAMP] : 0;
+      } else {
+        s += row[P_COUNT];
+        if (cv.flags[c] & NSPLAT_FILLED) sf += row[P_COUNT];
+      }
     }
+  }
+  if (which == 1) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sf += __shfl_xor(sf, off);
+    if (__lane_id() == 0) fsum[threadIdx.x >> 6] = sf;
   }
   // block exclusive scan of s
   int64_t incl = s;
@@ -209,6 +222,10 @@ __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* 
       if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_BOUND_CAP);
     } else {
       goff[n] = t32;
+      int64_t fills = 0;
+      for (int i = 0; i < 16; ++i) fills += fsum[i];
+      kinds[0] = fills > 0x7fffffff ? 0x7fffffff : (int32_t)fills;
+      kinds[1] = tot - fills > 0x7fffffff ? 0x7fffffff : (int32_t)(tot - fills);
       counters[NSPLAT_CNT_GAUSS_REQ] = t32;
       counters[NSPLAT_CNT_GAUSS] = (int32_t)(tot < cap ? tot : cap);
       if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_GAUSS_CAP);
@@ -680,8 +697,8 @@ hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const floa
   return hipGetLastError();
 }
 
-hipError_t launch_scene_setup(const Launch& L) {
-  hipLaunchKernelGGL(k_scene_setup, dim3(1), dim3(64), 0, L.stream, *L.sc, *L.pr, L.w.scenes);
+hipError_t launch_scene_setup(const Launch& L, int32_t* clear_counters) {
+  hipLaunchKernelGGL(k_scene_setup, dim3(1), dim3(64), 0, L.stream, *L.sc, *L.pr, L.w.scenes, clear_counters);
   return hipGetLastError();
 }
 
@@ -698,11 +715,11 @@ hipError_t launch_sample(const Launch& L, int frozen) {
     hipLaunchKernelGGL(k_curve_prep<PREP_THREADS>, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
                        cnt, frozen, L.sc->n_scenes);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
-                     (int64_t)L.bf->caps.boundary);
+                     (int64_t)L.bf->caps.boundary, L.w.queue + Q_NFILL);
   hipLaunchKernelGGL(k_boundary, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
                      (int64_t)L.bf->caps.boundary, frozen);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 1,
-                     (int64_t)L.bf->caps.gauss);
+                     (int64_t)L.bf->caps.gauss, L.w.queue + Q_NFILL);
   }
   Phase ph(L, NSPLAT_T_EMIT);
   hipLaunchKernelGGL(k_emit, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv, *L.pr,

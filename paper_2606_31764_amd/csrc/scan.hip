@@ -206,12 +206,32 @@ __global__ void k_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t 
 
 // One atomic per block: same-address float atomics serialise in L2, so the
 // loss partials are reduced across the block first (and the grid is kept
-// to a few hundred blocks, each thread taking many elements).
+// to a few hundred blocks, each thread taking many elements).  VEC: a, b and
+// out are 16-byte aligned and read and written four floats at a time.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_l2(const float* __restrict__ a, const float* __restrict__ b,
                                             float* __restrict__ out, float* loss, int64_t n) {
   __shared__ float red[4];
   float s = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n4 = 0;
+  if (VEC) {
+    n4 = n >> 2;
+    const float4* a4 = (const float4*)a;
+    const float4* b4 = (const float4*)b;
+    float4* o4 = (float4*)out;
+    for (int64_t i = i0; i < n4; i += stride) {
+      const float4 x = a4[i], y = b4[i];
+      const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z, d3 = x.w - y.w;
+      o4[i] = make_float4(2.0f * d0, 2.0f * d1, 2.0f * d2, 2.0f * d3);
+      s = __builtin_fmaf(d0, d0, s);
+      s = __builtin_fmaf(d1, d1, s);
+      s = __builtin_fmaf(d2, d2, s);
+      s = __builtin_fmaf(d3, d3, s);
+    }
+  }
+  for (int64_t i = 4 * n4 + i0; i < n; i += stride) {
     const float d = a[i] - b[i];
     out[i] = 2.0f * d;
     s = __builtin_fmaf(d, d, s);
@@ -260,7 +280,11 @@ hipError_t launch_anneal(float* h_dev, int32_t* step_dev, int32_t step, int32_t 
 
 hipError_t launch_l2(const float* a, const float* b, float* out, float* loss, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_l2, dim3(grid_for((n + 15) / 16, 256, 512)), dim3(256), 0, s, a, b, out, loss, n);
+  const bool vec = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)out) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_l2<true>, dim3(grid_for((n + 15) / 16, 256, 512)), dim3(256), 0, s, a, b, out, loss, n);
+  else
+    hipLaunchKernelGGL(k_l2<false>, dim3(grid_for((n + 15) / 16, 256, 512)), dim3(256), 0, s, a, b, out, loss, n);
   return hipGetLastError();
 }
 
