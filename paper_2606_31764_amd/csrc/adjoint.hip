@@ -290,12 +290,10 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
   for (int64_t base = wave0; base < G; base += stride) {
     const int64_t g = base + lane;
     int64_t kcur = -1 - lane;
-    double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double dop[1] = {0.0};  // dL/d(curve opacity): the only curve-level sum of a fill Gaussian
     int64_t skey = -1 - lane, sj = 0;  // boundary segment (start, end point) this lane's SDF gradient goes to
     double sv[4] = {0.0, 0.0, 0.0, 0.0};
     int c = 0;
-    CurveView v;
-    v.p = 0;
     bool fill = false;
     if (g < G) {
       const Gauss r = gs[g];
@@ -303,7 +301,6 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
       if (cv.flags[c] & NSPLAT_FILLED) {
         fill = true;
         kcur = c;
-        v = curve_view(cv, w.knots, c);
         const double dO = (double)w.ggrad[g * GG + 3];
         const int32_t* row = plan + (int64_t)P_STRIDE * c;
         const int nx = row[P_NX];
@@ -325,7 +322,7 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
         const double d = sqrt(px * px + py * py);
         const double z = gh * (sgn * d);
         const double sz = 1.0 / (1.0 + exp(-z));
-        cur[0] = dO * sz;
+        dop[0] = dO * sz;
         const double ds = sz * (1.0 - sz);
         if (d > 0.0 && dO != 0.0 && ds > 1e-18) {
           const double dd = dO * (double)cv.opacity[c] * ds * gh * sgn;  // dL/dd
@@ -350,7 +347,18 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
         unsafeAtomicAdd(&w.gb[sj].y, sv[3]);
       }
     }
-    if (__ballot(fill) != 0ull) accumulate_curve(w, kcur, c, v, cur);
+    if (__ballot(fill) != 0ull) {
+      const int64_t k0 = __builtin_amdgcn_readfirstlane((int)kcur);
+      if (__ballot(kcur != k0) == 0ull) {  // one curve across the wavefront: a plain sum
+        double s = dop[0];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0 && s != 0.0) unsafeAtomicAdd(w.gcurve + 4 * k0, s);
+      } else {
+        seg_reduce(kcur, dop);
+        if (seg_head(kcur) && dop[0] != 0.0) unsafeAtomicAdd(w.gcurve + 4 * (int64_t)c, dop[0]);
+      }
+    }
   }
 }
 
