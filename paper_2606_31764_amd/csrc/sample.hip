@@ -381,12 +381,66 @@ __device__ inline double4 ld_box(P p, int i) {
   return make_double4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
 }
 
+// One chunk k of polyline_sdf for the point q: the lower bound of its box
+// against thr = min(ub, best) decides whether its segments are visited;
+// otherwise its crossings are counted in closed form where the box allows.
+template <class P>
+__device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P segd, int nb, double ub,
+                                 double abs_margin, double mx, double* best, int* ibest, double* tbest, int* wn) {
+  const double4 b = ld_box(boxd, 1 + k);  // x0, x1, y0, y1
+  const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
+  const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
+  const double lb = ex0 * ex0 + ey0 * ey0;
+  const double thr = fmin(ub, *best);
+  bool visit = lb <= thr + 1e-8 * thr + abs_margin;
+  const int i0 = k * SDF_CHUNK;
+  const int i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
+  int wk = 0;
+  if (!visit && b.z <= qy && qy < b.w) {
+    if (b.x > qx + mx) {
+      const double2 E = ld_pt(bpd, i1 < nb ? i1 : 0);
+      wk = (E.y > qy ? 1 : 0) - (ld_pt(bpd, i0).y > qy ? 1 : 0);
+    } else if (!(b.y < qx - mx)) {
+      visit = true;
+    }
+  }
+  if (visit) {
+    // the chunk's SDF_CHUNK records (padding included), t = (r . e) / |e|^2
+    // taken as a product with the stored reciprocal
+#pragma unroll
+    for (int j = 0; j < SDF_CHUNK; ++j) {
+      const int i = i0 + j;
+      const int64_t o = (int64_t)SEG_WORDS * i;
+      const double ax = segd[o], ay = segd[o + 1], ex = segd[o + 2], ey = segd[o + 3];
+      const double inv = segd[o + 4], by = segd[o + 5];
+      const double rx = qx - ax, ry = qy - ay;
+      double t = (rx * ex + ry * ey) * inv;
+      t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+      const double px = ax + t * ex - qx, py = ay + t * ey - qy;
+      const double d2 = px * px + py * py;
+      const bool nearer = d2 < *best;
+      *best = nearer ? d2 : *best;
+      *ibest = nearer ? i : *ibest;
+      *tbest = nearer ? t : *tbest;
+      const double cr = ex * ry - rx * ey;  // > 0: q left of a -> b
+      const bool below = ay <= qy;
+      wk += (below && by > qy && cr > 0.0) ? 1 : 0;
+      wk -= (!below && by <= qy && cr < 0.0) ? 1 : 0;
+    }
+  }
+  *wn += wk;
+}
+
+__device__ inline double sdf_scale(double ax, double ay, const double4& hb) {
+  return 1.0 + ax + ay + 2.0 * fmax(fmax(fabs(hb.x), fabs(hb.y)), fmax(fabs(hb.z), fabs(hb.w)));
+}
+
 template <class P>
 __device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, P segd, int nb, int* arg, double* targ,
                                       double* sgn_out) {
   const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
   const double4 hb = ld_box(boxd, 0);  // the whole boundary's box
-  const double scale = 1.0 + fabs(qx) + fabs(qy) + 2.0 * fmax(fmax(fabs(hb.x), fabs(hb.y)), fmax(fabs(hb.z), fabs(hb.w)));
+  const double scale = sdf_scale(fabs(qx), fabs(qy), hb);
   double ub = INFINITY;
   for (int k = 0; k < K; ++k) {
     const double2 V = ld_pt(bpd, k * SDF_CHUNK);
@@ -396,49 +450,84 @@ __device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, P seg
   const double abs_margin = 1e-18 * scale * scale, mx = 1e-9 * scale;
   double best = INFINITY, tbest = 0.0;
   int ibest = 0, wn = 0;
-  for (int k = 0; k < K; ++k) {
-    const double4 b = ld_box(boxd, 1 + k);  // x0, x1, y0, y1
-    const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
-    const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
-    const double lb = ex0 * ex0 + ey0 * ey0;
-    const double thr = fmin(ub, best);
-    bool visit = lb <= thr + 1e-8 * thr + abs_margin;
-    const int i0 = k * SDF_CHUNK;
-    const int i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
-    int wk = 0;
-    if (!visit && b.z <= qy && qy < b.w) {
-      if (b.x > qx + mx) {
-        const double2 E = ld_pt(bpd, i1 < nb ? i1 : 0);
-        wk = (E.y > qy ? 1 : 0) - (ld_pt(bpd, i0).y > qy ? 1 : 0);
-      } else if (!(b.y < qx - mx)) {
-        visit = true;
-      }
-    }
-    if (visit) {
-      // the chunk's SDF_CHUNK records (padding included), t = (r . e) / |e|^2
-      // taken as a product with the stored reciprocal
+  for (int k = 0; k < K; ++k) sdf_chunk(k, qx, qy, bpd, boxd, segd, nb, ub, abs_margin, mx, &best, &ibest, &tbest, &wn);
+  *arg = ibest;
+  *targ = tbest;
+  *sgn_out = wn >= 1 ? 1.0 : -1.0;
+  return sqrt(best);
+}
+
+__device__ inline double wave_min_f64(double v) {
 #pragma unroll
-      for (int j = 0; j < SDF_CHUNK; ++j) {
-        const int i = i0 + j;
-        const int64_t o = (int64_t)SEG_WORDS * i;
-        const double ax = segd[o], ay = segd[o + 1], ex = segd[o + 2], ey = segd[o + 3];
-        const double inv = segd[o + 4], by = segd[o + 5];
-        const double rx = qx - ax, ry = qy - ay;
-        double t = (rx * ex + ry * ey) * inv;
-        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double px = ax + t * ex - qx, py = ay + t * ey - qy;
-        const double d2 = px * px + py * py;
-        const bool nearer = d2 < best;
-        best = nearer ? d2 : best;
-        ibest = nearer ? i : ibest;
-        tbest = nearer ? t : tbest;
-        const double cr = ex * ry - rx * ey;  // > 0: q left of a -> b
-        const bool below = ay <= qy;
-        wk += (below && by > qy && cr > 0.0) ? 1 : 0;
-        wk -= (!below && by <= qy && cr < 0.0) ? 1 : 0;
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+
+// polyline_sdf for a full wavefront of points on one curve, inside the box
+// [wx0, wx1] x [wy0, wy1] (lane values; the boundary arrays are read through
+// the constant address space).  The chunk scan is shared: the wavefront's
+// upper bound ubW is the least, over chunk starts V, of the distance from V
+// to the farthest corner of the box, which bounds every lane's minimum; the
+// lanes then classify one chunk each against the box.  A chunk that some
+// lane would visit (its box within a lane's bound, or a lane's crossing test
+// needing its segments) is in the visited list, because the box distance and
+// ubW bound the lanes' own values and rounding is monotone; a chunk wholly
+// right of the box with rows in the box's y-range adds its crossings in
+// closed form; every other chunk adds nothing to any lane.  The visited
+// chunks run sdf_chunk in order with ub = ubW, so each lane's result is that
+// of polyline_sdf (and of the plain loop).
+template <class P>
+__device__ inline double polyline_sdf_wave(double qx, double qy, double wx0, double wx1, double wy0, double wy1,
+                                           P bpd, P boxd, P segd, int nb, int* arg, double* targ, double* sgn_out) {
+  const int K = (nb + SDF_CHUNK - 1) / SDF_CHUNK;
+  const int lane = __lane_id();
+  typedef const double* gdp;
+  const gdp bpv = (gdp)bpd, boxv = (gdp)boxd;  // per-lane (vector) reads
+  double u = INFINITY;
+  for (int k = lane; k < K; k += 64) {
+    const double vx = bpv[2 * k * SDF_CHUNK], vy = bpv[2 * k * SDF_CHUNK + 1];
+    const double dx = fmax(fabs(vx - wx0), fabs(vx - wx1)), dy = fmax(fabs(vy - wy0), fabs(vy - wy1));
+    u = fmin(u, dx * dx + dy * dy);
+  }
+  const double ubW = wave_min_f64(u);
+  const double4 hb = ld_box(boxd, 0);
+  const double scale = sdf_scale(fabs(qx), fabs(qy), hb);
+  const double abs_margin = 1e-18 * scale * scale, mx = 1e-9 * scale;
+  const double scaleW = sdf_scale(fmax(fabs(wx0), fabs(wx1)), fmax(fabs(wy0), fabs(wy1)), hb);
+  const double amW = 1e-18 * scaleW * scaleW, mxW = 1e-9 * scaleW;
+  double best = INFINITY, tbest = 0.0;
+  int ibest = 0, wn = 0;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    bool full = false, endp = false;
+    if (k < K) {
+      const double b0 = boxv[4 * (1 + k)], b1 = boxv[4 * (1 + k) + 1], b2 = boxv[4 * (1 + k) + 2],
+                   b3 = boxv[4 * (1 + k) + 3];  // x0, x1, y0, y1
+      const double ex0 = fmax(fmax(b0 - wx1, wx0 - b1), 0.0);
+      const double ey0 = fmax(fmax(b2 - wy1, wy0 - b3), 0.0);
+      const bool cand = ex0 * ex0 + ey0 * ey0 <= ubW + 1e-8 * ubW + amW;
+      const bool yov = b2 <= wy1 && wy0 < b3;
+      const bool right = b0 > wx1 + mxW, left = b1 < wx0 - mxW;
+      full = cand || (yov && !right && !left);
+      endp = !full && yov && right;
+    }
+    const uint64_t fm = __ballot(full), em = __ballot(endp);
+    uint64_t m = fm | em;
+    while (m) {
+      const int bit = __builtin_ctzll(m);
+      m &= m - 1;
+      const int kk = k0 + bit;
+      if ((fm >> bit) & 1ull) {
+        sdf_chunk(kk, qx, qy, bpd, boxd, segd, nb, ubW, abs_margin, mx, &best, &ibest, &tbest, &wn);
+      } else {
+        const double4 b = ld_box(boxd, 1 + kk);
+        if (b.z <= qy && qy < b.w) {
+          const int i0 = kk * SDF_CHUNK, i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
+          const double2 E = ld_pt(bpd, i1 < nb ? i1 : 0);
+          wn += (E.y > qy ? 1 : 0) - (ld_pt(bpd, i0).y > qy ? 1 : 0);
+        }
       }
     }
-    wn += wk;
   }
   *arg = ibest;
   *targ = tbest;
@@ -516,8 +605,25 @@ __global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr
         // the constant address space with uniform indices (scalar loads)
         typedef const __attribute__((address_space(4))) double* cdp;
         const int32_t* ru = plan + (int64_t)P_STRIDE * cu;
-        d = polyline_sdf(qx, qy, (cdp)(w.bpts + ru[P_BOFF]), (cdp)(w.cbox + cbox_base(ru[P_BOFF], cu)),
-                         (cdp)(w.segs + SEG_WORDS * seg_base(ru[P_BOFF], cu)), ru[P_NSAMP], &arg, &t, &sgn);
+        const cdp bp = (cdp)(w.bpts + ru[P_BOFF]), bx = (cdp)(w.cbox + cbox_base(ru[P_BOFF], cu)),
+                  sg = (cdp)(w.segs + SEG_WORDS * seg_base(ru[P_BOFF], cu));
+        if (!capped && __ballot(true) == ~0ull) {
+          // all 64 lanes: the chunk scan is shared over the lattice box of
+          // the wavefront (the same formula as qx, qy at the extreme indices)
+          int ix0 = ix, ix1 = ix, iy0 = iy, iy1 = iy;
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            ix0 = min(ix0, __shfl_xor(ix0, off));
+            ix1 = max(ix1, __shfl_xor(ix1, off));
+            iy0 = min(iy0, __shfl_xor(iy0, off));
+            iy1 = max(iy1, __shfl_xor(iy1, off));
+          }
+          const double wx0 = ((double)(row[P_IX0] + ix0) + 0.5) * h, wx1 = ((double)(row[P_IX0] + ix1) + 0.5) * h;
+          const double wy0 = ((double)(row[P_IY0] + iy0) + 0.5) * h, wy1 = ((double)(row[P_IY0] + iy1) + 0.5) * h;
+          d = polyline_sdf_wave(qx, qy, wx0, wx1, wy0, wy1, bp, bx, sg, ru[P_NSAMP], &arg, &t, &sgn);
+        } else {
+          d = polyline_sdf(qx, qy, bp, bx, sg, ru[P_NSAMP], &arg, &t, &sgn);
+        }
       } else {
         d = polyline_sdf(qx, qy, (const double*)(w.bpts + row[P_BOFF]),
                          (const double*)(w.cbox + cbox_base(row[P_BOFF], c)),
