@@ -316,10 +316,10 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
         const int jb = ib + 1 < nb ? ib + 1 : 0;
         const double ax = sr[0], ay = sr[1], ex = sr[2], ey = sr[3], inv = sr[4];
         const double rx = qx - ax, ry = qy - ay;
-        double t = (rx * ex + ry * ey) * inv;
+        double t = __builtin_fma(rx, ex, ry * ey) * inv;
         t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double px = ax + t * ex - qx, py = ay + t * ey - qy;
-        const double d = sqrt(px * px + py * py);
+        const double px = __builtin_fma(t, ex, -rx), py = __builtin_fma(t, ey, -ry);
+        const double d = sqrt(__builtin_fma(px, px, py * py));
         const double z = gh * (sgn * d);
         const double sz = 1.0 / (1.0 + exp(-z));
         dop[0] = dO * sz;

@@ -413,16 +413,17 @@ __device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P s
       const int64_t o = (int64_t)SEG_WORDS * i;
       const double ax = segd[o], ay = segd[o + 1], ex = segd[o + 2], ey = segd[o + 3];
       const double inv = segd[o + 4], by = segd[o + 5];
+      // fused forms: p - q = t e - r, one rounding each
       const double rx = qx - ax, ry = qy - ay;
-      double t = (rx * ex + ry * ey) * inv;
+      double t = __builtin_fma(rx, ex, ry * ey) * inv;
       t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-      const double px = ax + t * ex - qx, py = ay + t * ey - qy;
-      const double d2 = px * px + py * py;
+      const double px = __builtin_fma(t, ex, -rx), py = __builtin_fma(t, ey, -ry);
+      const double d2 = __builtin_fma(px, px, py * py);
       const bool nearer = d2 < *best;
       *best = nearer ? d2 : *best;
       *ibest = nearer ? i : *ibest;
       *tbest = nearer ? t : *tbest;
-      const double cr = ex * ry - rx * ey;  // > 0: q left of a -> b
+      const double cr = __builtin_fma(ex, ry, -(rx * ey));  // > 0: q left of a -> b
       const bool below = ay <= qy;
       wk += (below && by > qy && cr > 0.0) ? 1 : 0;
       wk -= (!below && by <= qy && cr < 0.0) ? 1 : 0;
