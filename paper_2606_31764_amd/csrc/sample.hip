@@ -546,7 +546,7 @@ __device__ inline float4 curve_colour(const nsplat_curves& cv, int c, float tag)
 // One lane per Gaussian.  Emission order per curve: open strokes kappa copies
 // of sample 0, samples 0..M-1, kappa copies of sample M-1; closed strokes
 // samples 0..M-1; fills the lattice window row by row.
-__global__ __launch_bounds__(256) void k_emit(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
+__global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
                                               const int32_t* counters, Gauss* __restrict__ out) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const bool capped = (int64_t)counters[NSPLAT_CNT_GAUSS_REQ] > G;
