@@ -109,14 +109,16 @@ constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, 
 // The adjoint parks the per-lane gradient values it still has to sum over
 // the wavefront in LDS rows of 64 floats, one row per value (three for a
 // stroke Gaussian, one for a fill Gaussian), each with its (Gaussian, value
-// index) target, and sums RB rows at a time (see flush_rows).  Rows are
-// padded to 68 floats so that the flush's reads of the RB rows fall into
-// different banks.
-constexpr int RB = 16;
-constexpr int RB_ROW = 68;            // floats per parked row
-constexpr size_t BWD_PARK_BYTES = (size_t)RB * RB_ROW * 4 + (size_t)RB * 8;
-__host__ __device__ constexpr size_t bwd_wave_bytes(int E) {
-  return ((size_t)64 * E * BWD_ENTRY_BYTES + BWD_PARK_BYTES + 15) / 16 * 16;
+// index) target, and sums park_rows rows at a time (see flush_rows).  Rows
+// are padded to 68 floats so that the flush's reads fall into different
+// banks.  One-pixel-per-lane adjoints at depth 64 park 12 rows, which keeps a
+// wavefront's LDS slice small enough for six wavefronts per SIMD; the others
+// (held to fewer wavefronts by their registers) park 16.
+constexpr int RB_ROW = 68;  // floats per parked row
+__host__ __device__ constexpr bool bwd_six_waves(int tile, int E) { return tile <= 16 && E == 1; }
+__host__ __device__ constexpr int park_rows(int tile, int E) { return bwd_six_waves(tile, E) ? 12 : 16; }
+__host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E) {
+  return ((size_t)64 * E * BWD_ENTRY_BYTES + (size_t)park_rows(tile, E) * (RB_ROW * 4 + 8) + 15) / 16 * 16;
 }
 
 // Lower end of the step that starts at list position h (walking down from
@@ -350,18 +352,22 @@ __device__ inline void flush_curve(double* gcurve, int c, bool fill, const float
 // Sums the first n (<= RB) parked rows over the 64 lanes and adds each total
 // to its target ggrad[g * GG + value] (tgt[row] = (g, value)).  Lane (r, part)
 // = (lane / 4, lane % 4) adds up floats part, part + 4, ..., part + 60 of row
-// r; two DPP row shifts finish the sum in the quad's last lane, which issues
-// the atomic.  Every lane of the wavefront must call it.
+// r (lanes of rows past RB add nothing); two DPP row shifts finish the sum in
+// the quad's last lane, which issues the atomic.  Every lane of the wavefront
+// must call it.
+template <int RB>
 __device__ inline void flush_rows(const float* park, const int2* tgt, int n, float* __restrict__ ggrad) {
-  static_assert(RB * 4 == 64, "four lanes per parked row");
+  static_assert(RB <= 16, "four lanes per parked row");
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int lane = __lane_id(), r = lane >> 2, part = lane & 3;
   const float* row = park + r * RB_ROW + part;
   float t = 0.0f;
+  if (r < RB) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) t += row[4 * j];
+    for (int j = 0; j < 16; ++j) t += row[4 * j];
+  }
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x111, 0xf, 0xf, true));  // row_shr:1
   t += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x112, 0xf, 0xf, true));  // row_shr:2
   if (part == 3 && r < n && t != 0.0f) {
@@ -387,7 +393,7 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // running per-curve sums that are flushed when the curve changes along the
 // list or every FLUSH entries.
 template <int C, int TILE, int E>
-__global__ __launch_bounds__(BLOCK) void k_blend_bwd(
+__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : 1) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
@@ -400,7 +406,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(E);
+  constexpr int RB = park_rows(TILE, E);
+  char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(TILE, E);
   float4* wgeo = (float4*)mine_lds;
   float4* wpc = wgeo + 64 * E;
   int4* wmeta = (int4*)(wpc + 64 * E);  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
@@ -579,7 +586,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         // park the values still to be summed over the wavefront
         const int need = fill ? 1 : 3;
         if (n_rows + need > RB) {
-          flush_rows(park, ptgt, n_rows, ggrad);
+          flush_rows<RB>(park, ptgt, n_rows, ggrad);
           n_rows = 0;
         }
         if (fill) {
@@ -598,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
       lo_s = nlo;
     }
     if (n_rows > 0) {
-      flush_rows(park, ptgt, n_rows, ggrad);
+      flush_rows<RB>(park, ptgt, n_rows, ggrad);
       n_rows = 0;
     }
     if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, sumaT, accO);
@@ -643,7 +650,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
   const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * (L.bf->caps.pairs / CK + L.n_tiles);
-  const size_t lds = (size_t)WPB * bwd_wave_bytes(E);
+  const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {
     grid = resident_grid(k_blend_bwd<C, TILE, E>, grid, L.n_cu, lds);
