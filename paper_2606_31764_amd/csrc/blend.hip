@@ -393,7 +393,9 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // running per-curve sums that are flushed when the curve changes along the
 // list or every FLUSH entries.
 template <int C, int TILE, int E>
-__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : 1) void k_blend_bwd(
+// occupancy: six wavefronts per SIMD for one pixel per lane at depth 64,
+// five for 32 x 32 tiles at depth 64 (96 VGPRs), registers decide otherwise
+__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 5 : 1)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
