@@ -391,10 +391,10 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // opacity carries the SDF); colour gradients (and a stroke curve's opacity
 // gradient, its o_j all being o) belong to the curve, so each lane keeps
 // running per-curve sums that are flushed when the curve changes along the
-// list or every FLUSH entries.
+// list or every FLUSH entries.  Occupancy: six wavefronts per SIMD for one
+// pixel per lane at depth 64, five for 32 x 32 tiles at depth 64 (96 VGPRs);
+// elsewhere the registers decide.
 template <int C, int TILE, int E>
-// occupancy: six wavefronts per SIMD for one pixel per lane at depth 64,
-// five for 32 x 32 tiles at depth 64 (96 VGPRs), registers decide otherwise
 __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 5 : 1)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
