@@ -406,8 +406,9 @@ __device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P s
   }
   if (visit) {
     // the chunk's SDF_CHUNK records (padding included), t = (r . e) / |e|^2
-    // taken as a product with the stored reciprocal
-#pragma unroll
+    // taken as a product with the stored reciprocal; two records per step keep
+    // the scalar registers free enough for five wavefronts per SIMD unspilled
+#pragma unroll 2
     for (int j = 0; j < SDF_CHUNK; ++j) {
       const int i = i0 + j;
       const int64_t o = (int64_t)SEG_WORDS * i;
