@@ -132,3 +132,11 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(L.HEADER), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).decode().split()]
     assert got == expect
+
+
+def test_binding_refuses_other_abi_version(lib, monkeypatch):
+    # a library whose structure layout differs must not be driven at all
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "ABI_VERSION", L.ABI_VERSION + 1)
+    with pytest.raises(RuntimeError, match="ABI version"):
+        L.load()
