@@ -328,21 +328,27 @@ __device__ inline int wave_min(int v) {
 
 // Flushes one wavefront's running per-curve sums into the FP64 per-curve
 // accumulators: the colour gradient sum_q dL/dI_c(q) sum(alpha T) of each
-// channel, and the opacity gradient of a stroke curve.
+// channel, and the opacity gradient of a stroke curve.  Over a run of entries
+// sum(alpha T) = T at the run's start - T now (alpha_j T_j = T_j - T_{j+1}),
+// so each pixel keeps only Tst, its T where the run began, reset here.
 template <int C, int PPT>
 __device__ inline void flush_curve(double* gcurve, int c, bool fill, const float (&gI)[PPT][3],
-                                   float (&sumaT)[PPT], float& accO) {
+                                   const float (&T)[PPT], float (&Tst)[PPT], float& accO) {
   float v[C + 1];
   v[0] = fill ? 0.0f : accO;
+  float aT[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    aT[q] = Tst[q] - T[q];
+    Tst[q] = T[q];
+  }
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) {
     float a = 0.0f;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) a = __builtin_fmaf(gI[q][ch], sumaT[q], a);
+    for (int q = 0; q < PPT; ++q) a = __builtin_fmaf(gI[q][ch], aT[q], a);
     v[1 + ch] = a;
   }
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) sumaT[q] = 0.0f;
   accO = 0.0f;
   const float t = wave_totals_to_lanes<C + 1>(v);
   const int lane = __lane_id();
@@ -386,7 +392,7 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // accumulated in front (U += K alpha T), Eq. 8 gives
 //   dL/dalpha = T K - (R - U) / (1 - alpha),   R = sum_c dL/dI_c I_c,
 // R - U being the loss-weighted colour still to come behind the entry (the
-// back layers and the background).  Per Gaussian it accumulates dL/dmu and
+// back layers and the background), which each pixel carries as V = R - U.  Per Gaussian it accumulates dL/dmu and
 // dL/dsigma for stroke Gaussians and dL/do_j for fill Gaussians (whose own
 // opacity carries the SDF); colour gradients (and a stroke curve's opacity
 // gradient, its o_j all being o) belong to the curve, so each lane keeps
@@ -488,11 +494,17 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
     }
     int cur = -1, since = 0;
     bool cur_fill = false;
-    // per pixel: K = sum_c dL/dI_c col_c of the current curve, and the sum of
-    // alpha T over its entries (the curve's colour gradient is dL/dI_c times it)
-    float Kc[PPT], sumaT[PPT], accO = 0.0f;
+    // per pixel: K = sum_c dL/dI_c col_c of the current curve, V = R - U
+    // (the loss-weighted colour still to come), and T where the current
+    // curve's run began (the curve's colour gradient is dL/dI_c times the
+    // run's sum of alpha T)
+    float Kc[PPT], V[PPT], Tst[PPT], accO = 0.0f;
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) Kc[q] = sumaT[q] = 0.0f;
+    for (int q = 0; q < PPT; ++q) {
+      Kc[q] = 0.0f;
+      V[q] = R[q] - U[q];
+      Tst[q] = T[q];
+    }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
     // front to back over the chunk's positions c_hi - 1 down to lo
     Entry e[E];
@@ -539,7 +551,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         const int c_k = __builtin_amdgcn_readfirstlane(mt.y);
         const bool fill = gsig < 0;
         if (c_k != cur || since >= FLUSH) {
-          if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, sumaT, accO);
+          if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, T, Tst, accO);
           if (c_k != cur) {
             const float col[3] = {pc.y, pc.z, pc.w};
 #pragma unroll
@@ -571,9 +583,8 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           const float onem = 1.0f - alpha;
           const float aT = alpha * T[q];
           const float K = Kc[q];
-          sumaT[q] += aT;
-          U[q] = __builtin_fmaf(K, aT, U[q]);
-          const float dLda = (in && oG < amax) ? T[q] * K - (R[q] - U[q]) * __builtin_amdgcn_rcpf(onem) : 0.0f;
+          V[q] = __builtin_fmaf(-K, aT, V[q]);
+          const float dLda = (in && oG < amax) ? __builtin_fmaf(-V[q], __builtin_amdgcn_rcpf(onem), T[q] * K) : 0.0f;
           T[q] = T[q] * onem;
           v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
           if (!fill) {
@@ -610,7 +621,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       flush_rows<RB>(park, ptgt, n_rows, ggrad);
       n_rows = 0;
     }
-    if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, sumaT, accO);
+    if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, T, Tst, accO);
   }
 }
 
