@@ -104,7 +104,7 @@ __device__ inline uint64_t lanes_below() {
 }
 
 // LDS bytes per wavefront for a step of `depth` entries.
-constexpr int FWD_ENTRY_BYTES = 36;   // geometry, opacity + colour, list position
+constexpr int FWD_ENTRY_BYTES = 40;   // geometry, opacity + colour, list position, curve
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
 // The adjoint parks the per-lane gradient values it still has to sum over
 // the wavefront in LDS rows of 64 floats, one row per value (three for a
@@ -144,6 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
   float4* wgeo = (float4*)mine_lds;
   float4* wpc = wgeo + 64 * E;
   int* wpos = (int*)(wpc + 64 * E);
+  int* wcur = wpos + 64 * E;
   const uint64_t below = lanes_below();
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
@@ -154,9 +155,18 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     const SceneTab st = w.scenes[s];
     const int lt = tile - st.tile_off;
     const int x0 = (lt % st.tiles_x) * TILE, y0 = (lt / st.tiles_x) * TILE;
-    float px[PPT], py[PPT], T[PPT], acc[PPT][3];
+    // The colour is accumulated per run of entries of one curve (one
+    // colour): over a run, sum alpha_j T_j = T at its start - T now
+    // (alpha_j T_j = T_j - T_{j+1}), so each pixel keeps Tst, its T where the
+    // run began, and adds col (Tst - T) where the run ends.  Runs end where
+    // the curve changes between consecutive composited entries, at chunk
+    // boundaries and at the end, all fixed by the list, so the result does not
+    // depend on the batch depth.
+    float px[PPT], py[PPT], T[PPT], Tst[PPT], acc[PPT][3];
     int stop[PPT];
     bool done[PPT];
+    int run_curve = -1;
+    float rc0 = 0.0f, rc1 = 0.0f, rc2 = 0.0f;  // the run's colour
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -165,6 +175,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       px[q] = (float)lx;
       py[q] = (float)ly;
       T[q] = 1.0f;
+      Tst[q] = 1.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[q][c] = 0.0f;
       stop[q] = start;
@@ -201,6 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           wgeo[dst] = geo;
           wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
           wpos[dst] = mypos;
+          wcur[dst] = e[u].r.curve;
         }
         cnt += __popcll(m);
       }
@@ -220,27 +232,58 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       int jstop[PPT];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) jstop[q] = -1;
-#pragma unroll 4
-      for (int j = 0; j < cnt; ++j) {
-        const float4 gm = wgeo[j];
-        const float4 pc = wpc[j];
+      // composited entries that begin a run (their curve differs from the
+      // entry before, the first one compared with the previous step's run)
+      uint64_t rs[E];
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-          const float dx = px[q] - gm.x, dy = py[q] - gm.y;
-          const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-          const float G = __builtin_amdgcn_exp2f(gm.w * d2);
-          const bool in = (d2 <= gm.z) && !done[q];
-          const float alpha = in ? fminf(amax, pc.x * G) : 0.0f;
-          const float wgt = alpha * T[q];
-          acc[q][0] = __builtin_fmaf(pc.y, wgt, acc[q][0]);
-          if (C == 3) {
-            acc[q][1] = __builtin_fmaf(pc.z, wgt, acc[q][1]);
-            acc[q][2] = __builtin_fmaf(pc.w, wgt, acc[q][2]);
+      for (int g = 0; g < E; ++g) {
+        const int i = 64 * g + lane;
+        const int prev = i == 0 ? run_curve : wcur[i > 0 ? i - 1 : 0];
+        rs[g] = __ballot(i < cnt && wcur[i < cnt ? i : 0] != prev);
+      }
+      for (int j = 0; j < cnt;) {
+        // this segment: j up to the next run start (or the step's end)
+        int jend = cnt;
+#pragma unroll
+        for (int g = E - 1; g >= 0; --g) {
+          const int b = j + 1 - 64 * g;  // first bit of group g after j
+          const uint64_t m = b <= 0 ? rs[g] : (b < 64 ? rs[g] & (~0ull << b) : 0ull);
+          if (m) jend = 64 * g + __builtin_ctzll(m);
+        }
+        if ((rs[j >> 6] >> (j & 63)) & 1ull) {  // a new run: close the previous one
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) {
+            const float a = Tst[q] - T[q];
+            acc[q][0] = __builtin_fmaf(rc0, a, acc[q][0]);
+            if (C == 3) {
+              acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
+              acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+            }
+            Tst[q] = T[q];
           }
-          T[q] = T[q] * (1.0f - alpha);
-          const bool now = in && (T[q] < eps);
-          jstop[q] = now ? j : jstop[q];
-          done[q] = done[q] || now;
+          const float4 pc = wpc[j];
+          rc0 = pc.y;
+          rc1 = pc.z;
+          rc2 = pc.w;
+          run_curve = wcur[j];
+        }
+        const float* wop = (const float*)wpc;  // opacities
+#pragma unroll 4
+        for (; j < jend; ++j) {
+          const float4 gm = wgeo[j];
+          const float op = wop[4 * j];
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) {
+            const float dx = px[q] - gm.x, dy = py[q] - gm.y;
+            const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+            const float G = __builtin_amdgcn_exp2f(gm.w * d2);
+            const bool in = (d2 <= gm.z) && !done[q];
+            const float alpha = in ? fminf(amax, op * G) : 0.0f;
+            T[q] = T[q] * (1.0f - alpha);
+            const bool now = in && (T[q] < eps);
+            jstop[q] = now ? j : jstop[q];
+            done[q] = done[q] || now;
+          }
         }
       }
       bool mine = true;
@@ -254,8 +297,19 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       nhi = n2hi;
       nlo = n2lo;
       if (hi > start && (end - hi) % CK == 0) {
-        // state in front of chunk (end - hi) / CK: T and the accumulated colour
+        // state in front of chunk (end - hi) / CK: T and the accumulated
+        // colour, with the current run closed at the boundary
         float* ckp = w.ckbuf + (int64_t)(ck0 + (end - hi) / CK - 1) * (4 * TILE * TILE);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const float a = Tst[q] - T[q];
+          acc[q][0] = __builtin_fmaf(rc0, a, acc[q][0]);
+          if (C == 3) {
+            acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
+            acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+          }
+          Tst[q] = T[q];
+        }
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
           const int slot = (quad * PPT + q) * 64 + lane;
@@ -266,6 +320,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       }
       __builtin_amdgcn_wave_barrier();
       if (__ballot(!mine) == 0ull) break;  // every pixel of the quadrant has stopped
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {  // close the last run
+      const float a = Tst[q] - T[q];
+      acc[q][0] = __builtin_fmaf(rc0, a, acc[q][0]);
+      if (C == 3) {
+        acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
+        acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
