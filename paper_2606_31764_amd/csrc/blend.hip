@@ -557,15 +557,16 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
     }
     int cur = -1, since = 0;
     bool cur_fill = false;
-    // per pixel: K = sum_c dL/dI_c col_c of the current curve, V = R - U
-    // (the loss-weighted colour still to come), and T where the current
-    // curve's run began (the curve's colour gradient is dL/dI_c times the
-    // run's sum of alpha T)
-    float Kc[PPT], V[PPT], Tst[PPT], accO = 0.0f;
+    // per pixel: K = sum_c dL/dI_c col_c of the current curve; V = R - U
+    // (the loss-weighted colour still to come), which over a run of one
+    // curve is Vc + K T (U grows by K alpha T = K (T - T')), so only Vc is
+    // kept, fixed where the run begins; and T where the run began (the
+    // curve's colour gradient is dL/dI_c times the run's sum of alpha T)
+    float Kc[PPT], Vc[PPT], Tst[PPT], accO = 0.0f;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       Kc[q] = 0.0f;
-      V[q] = R[q] - U[q];
+      Vc[q] = R[q] - U[q];
       Tst[q] = T[q];
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
@@ -622,6 +623,8 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               float K = 0.0f;
 #pragma unroll
               for (int c = 0; c < C; ++c) K = __builtin_fmaf(gI[q][c], col[c], K);
+              // V now, re-expressed with the new curve's K
+              Vc[q] = __builtin_fmaf(-K, T[q], __builtin_fmaf(Kc[q], T[q], Vc[q]));
               Kc[q] = K;
             }
           }
@@ -644,11 +647,11 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           const float oG = pc.x * G;
           const float alpha = in ? fminf(amax, oG) : 0.0f;
           const float onem = 1.0f - alpha;
-          const float aT = alpha * T[q];
           const float K = Kc[q];
-          V[q] = __builtin_fmaf(-K, aT, V[q]);
-          const float dLda = (in && oG < amax) ? __builtin_fmaf(-V[q], __builtin_amdgcn_rcpf(onem), T[q] * K) : 0.0f;
-          T[q] = T[q] * onem;
+          const float Tn = T[q] * onem;
+          const float V = __builtin_fmaf(K, Tn, Vc[q]);  // R - U after this entry
+          const float dLda = (in && oG < amax) ? __builtin_fmaf(-V, __builtin_amdgcn_rcpf(onem), T[q] * K) : 0.0f;
+          T[q] = Tn;
           v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
           if (!fill) {
             const float dG = dLda * pc.x;
