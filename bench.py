@@ -143,14 +143,14 @@ def blend_work(step, tile):
 # Algorithmic FP32 operations per in-support (pixel, Gaussian) pair of the
 # formulation the kernels compute; an FMA counts 2.  Forward: d^2 (2 sub,
 # mul, fma) 5, exp2 argument and exp2 2, o G and the alpha_max clamp 2,
-# alpha T 1, three colour FMAs 6, 1 - alpha and T (1 - alpha) 2, termination
-# test 1 = 19.  Adjoint of a fill Gaussian (front to back inside a chunk):
-# d^2 5, exp2 2, o G and clamp 2, 1 - alpha 1, alpha T 1, sum of alpha T 1,
-# U += K alpha T 2, dL/dalpha = T K - (R - U) rcp(1 - alpha) 5, T (1 - alpha)
-# 1, dL/do_j FMA 2 = 22 (K and the colour gradient are per curve, not per
-# pair); a stroke Gaussian adds dL/dmu and dL/dsigma (14) and its opacity sum
-# (1) = 37.
-FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 19, 22, 37
+# 1 - alpha and T (1 - alpha) 2, termination test 1 = 12 (the colour is added
+# once per run of one curve's entries, as col (T at the run's start - T), not
+# per pair).  Adjoint of a fill Gaussian (front to back inside a chunk): d^2 5,
+# exp2 2, o G and clamp 2, 1 - alpha 1, T (1 - alpha) 1, dL/dalpha =
+# -Vc rcp(1 - alpha) 2, dL/do_j FMA 2 = 15 (K, Vc and the colour gradient are
+# per curve run, not per pair); a stroke Gaussian adds dL/dmu and dL/dsigma
+# (14) and its opacity sum (1) = 30.
+FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 12, 15, 30
 # The build disables packed FP32 instructions, so the FP32 vector peak is
 # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s, not the
 # packed 157.3.

@@ -455,7 +455,9 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // accumulated in front (U += K alpha T), Eq. 8 gives
 //   dL/dalpha = T K - (R - U) / (1 - alpha),   R = sum_c dL/dI_c I_c,
 // R - U being the loss-weighted colour still to come behind the entry (the
-// back layers and the background), which each pixel carries as V = R - U.  Per Gaussian it accumulates dL/dmu and
+// back layers and the background).  Over a run of one curve's entries K is
+// fixed and R - U = Vc + K T after each entry, so dL/dalpha = -Vc / (1 - alpha)
+// with Vc set where the run begins.  Per Gaussian it accumulates dL/dmu and
 // dL/dsigma for stroke Gaussians and dL/do_j for fill Gaussians (whose own
 // opacity carries the SDF); colour gradients (and a stroke curve's opacity
 // gradient, its o_j all being o) belong to the curve, so each lane keeps
@@ -647,11 +649,10 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           const float oG = pc.x * G;
           const float alpha = in ? fminf(amax, oG) : 0.0f;
           const float onem = 1.0f - alpha;
-          const float K = Kc[q];
-          const float Tn = T[q] * onem;
-          const float V = __builtin_fmaf(K, Tn, Vc[q]);  // R - U after this entry
-          const float dLda = (in && oG < amax) ? __builtin_fmaf(-V, __builtin_amdgcn_rcpf(onem), T[q] * K) : 0.0f;
-          T[q] = Tn;
+          // with R - U = Vc + K T (1 - alpha) after this entry,
+          // dL/dalpha = T K - (R - U) / (1 - alpha) = -Vc / (1 - alpha)
+          const float dLda = (in && oG < amax) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
+          T[q] = T[q] * onem;
           v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
           if (!fill) {
             const float dG = dLda * pc.x;
