@@ -462,7 +462,9 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // opacity carries the SDF); colour gradients (and a stroke curve's opacity
 // gradient, its o_j all being o) belong to the curve, so each lane keeps
 // running per-curve sums that are flushed when the curve changes along the
-// list or every FLUSH entries.  Occupancy: six wavefronts per SIMD for one
+// list (and for strokes every FLUSH entries).  The entries of a step are cut
+// into runs of one curve with one ballot, and each run is composited by a loop
+// for its kind, with no per-entry curve test.  Occupancy: six wavefronts per SIMD for one
 // pixel per lane at depth 64, five for 32 x 32 tiles at depth 64 (96 VGPRs);
 // elsewhere the registers decide.
 template <int C, int TILE, int E>
@@ -609,76 +611,125 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int j = 0; j < cnt; ++j) {
-        const int4 mt = wmeta[j];
-        const float4 gm = wgeo[j];
-        const float4 pc = wpc[j];
-        const int gsig = __builtin_amdgcn_readfirstlane(mt.x);
-        const int c_k = __builtin_amdgcn_readfirstlane(mt.y);
-        const bool fill = gsig < 0;
-        if (c_k != cur || since >= FLUSH) {
+      // composited entries that begin a run (their curve differs from the
+      // entry before, the first one compared with the previous step's curve)
+      uint64_t rs[E];
+#pragma unroll
+      for (int g = 0; g < E; ++g) {
+        const int i = 64 * g + lane;
+        const int prev = i == 0 ? cur : wmeta[i > 0 ? i - 1 : 0].y;
+        rs[g] = __ballot(i < cnt && wmeta[i < cnt ? i : 0].y != prev);
+      }
+      const float* wop = (const float*)wpc;  // opacities
+      for (int j = 0; j < cnt;) {
+        // this segment: j up to the next run start (or the step's end)
+        int jend = cnt;
+#pragma unroll
+        for (int g = E - 1; g >= 0; --g) {
+          const int b = j + 1 - 64 * g;  // first bit of group g after j
+          const uint64_t m = b <= 0 ? rs[g] : (b < 64 ? rs[g] & (~0ull << b) : 0ull);
+          if (m) jend = 64 * g + __builtin_ctzll(m);
+        }
+        if ((rs[j >> 6] >> (j & 63)) & 1ull) {  // a new curve: close the previous one
           if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, T, Tst, accO);
-          if (c_k != cur) {
-            const float col[3] = {pc.y, pc.z, pc.w};
+          const int4 mt = wmeta[j];
+          const float4 pc = wpc[j];
+          const float col[3] = {pc.y, pc.z, pc.w};
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-              float K = 0.0f;
+          for (int q = 0; q < PPT; ++q) {
+            float K = 0.0f;
 #pragma unroll
-              for (int c = 0; c < C; ++c) K = __builtin_fmaf(gI[q][c], col[c], K);
-              // V now, re-expressed with the new curve's K
-              Vc[q] = __builtin_fmaf(-K, T[q], __builtin_fmaf(Kc[q], T[q], Vc[q]));
-              Kc[q] = K;
-            }
+            for (int c = 0; c < C; ++c) K = __builtin_fmaf(gI[q][c], col[c], K);
+            // V now, re-expressed with the new curve's K
+            Vc[q] = __builtin_fmaf(-K, T[q], __builtin_fmaf(Kc[q], T[q], Vc[q]));
+            Kc[q] = K;
           }
-          cur = c_k;
-          cur_fill = fill;
+          cur = __builtin_amdgcn_readfirstlane(mt.y);
+          cur_fill = __builtin_amdgcn_readfirstlane(mt.x) < 0;
           since = 0;
         }
-        ++since;
-        const int pos = mt.z;
-        const float is3 = __int_as_float(mt.w);
-        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        bool act = false;
+        if (cur_fill) {
+          // fill Gaussians: one value each (dL/do_j), parked in one row
+          for (; j < jend; ++j) {
+            const float4 gm = wgeo[j];
+            const float op = wop[4 * j];
+            const int4 mt = wmeta[j];
+            float v3 = 0.0f;
+            bool act = false;
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-          const float dx = px[q] - gm.x, dy = py[q] - gm.y;
-          const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-          const bool in = (pos >= stop[q]) && (d2 <= gm.z);
-          act = act || in;
-          const float G = __builtin_amdgcn_exp2f(gm.w * d2);
-          const float oG = pc.x * G;
-          const float alpha = in ? fminf(amax, oG) : 0.0f;
-          const float onem = 1.0f - alpha;
-          // with R - U = Vc + K T (1 - alpha) after this entry,
-          // dL/dalpha = T K - (R - U) / (1 - alpha) = -Vc / (1 - alpha)
-          const float dLda = (in && oG < amax) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
-          T[q] = T[q] * onem;
-          v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
-          if (!fill) {
-            const float dG = dLda * pc.x;
-            const float dd2 = dG * G * gm.w * ln2;  // d exp2(a d2) / d d2 = G a ln 2
-            v[0] = __builtin_fmaf(-2.0f * dx, dd2, v[0]);
-            v[1] = __builtin_fmaf(-2.0f * dy, dd2, v[1]);
-            v[2] = __builtin_fmaf(dG * G, d2 * is3, v[2]);
+            for (int q = 0; q < PPT; ++q) {
+              const float dx = px[q] - gm.x, dy = py[q] - gm.y;
+              const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+              const bool in = (mt.z >= stop[q]) && (d2 <= gm.z);
+              act = act || in;
+              const float G = __builtin_amdgcn_exp2f(gm.w * d2);
+              const float oG = op * G;
+              const bool lt = oG < amax;
+              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float onem = 1.0f - alpha;
+              // with R - U = Vc + K T (1 - alpha) after this entry,
+              // dL/dalpha = T K - (R - U) / (1 - alpha) = -Vc / (1 - alpha)
+              const float dLda = (in && lt) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
+              T[q] = T[q] * onem;
+              v3 = __builtin_fmaf(dLda, G, v3);  // dL/do_j
+            }
+            if (__ballot(act) == 0ull) continue;
+            if (n_rows + 1 > RB) {
+              flush_rows<RB>(park, ptgt, n_rows, ggrad);
+              n_rows = 0;
+            }
+            park[n_rows * RB_ROW + lane] = v3;
+            if (lane == 0) ptgt[n_rows] = make_int2(~mt.x, 3);
+            n_rows = __builtin_amdgcn_readfirstlane(n_rows + 1);
+          }
+        } else {
+          // stroke Gaussians: dL/dmu (2) and dL/dsigma parked in three rows;
+          // dL/do_j summed per lane into the curve's opacity gradient, which
+          // is flushed every FLUSH entries to keep that FP32 sum short
+          for (; j < jend; ++j) {
+            if (since >= FLUSH) {
+              flush_curve<C, PPT>(w.gcurve, cur, false, gI, T, Tst, accO);
+              since = 0;
+            }
+            ++since;
+            const float4 gm = wgeo[j];
+            const float op = wop[4 * j];
+            const int4 mt = wmeta[j];
+            const float is3 = __int_as_float(mt.w);
+            float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            bool act = false;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+              const float dx = px[q] - gm.x, dy = py[q] - gm.y;
+              const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+              const bool in = (mt.z >= stop[q]) && (d2 <= gm.z);
+              act = act || in;
+              const float G = __builtin_amdgcn_exp2f(gm.w * d2);
+              const float oG = op * G;
+              const bool lt = oG < amax;
+              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float onem = 1.0f - alpha;
+              const float dLda = (in && lt) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
+              T[q] = T[q] * onem;
+              v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
+              const float dG = dLda * op;
+              const float dd2 = dG * G * gm.w * ln2;  // d exp2(a d2) / d d2 = G a ln 2
+              v[0] = __builtin_fmaf(-2.0f * dx, dd2, v[0]);
+              v[1] = __builtin_fmaf(-2.0f * dy, dd2, v[1]);
+              v[2] = __builtin_fmaf(dG * G, d2 * is3, v[2]);
+            }
+            if (__ballot(act) == 0ull) continue;
+            if (n_rows + 3 > RB) {
+              flush_rows<RB>(park, ptgt, n_rows, ggrad);
+              n_rows = 0;
+            }
+            accO += v[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) park[(n_rows + i) * RB_ROW + lane] = v[i];
+            if (lane < 3) ptgt[n_rows + lane] = make_int2(mt.x, lane);
+            n_rows = __builtin_amdgcn_readfirstlane(n_rows + 3);
           }
         }
-        if (__ballot(act) == 0ull) continue;
-        // park the values still to be summed over the wavefront
-        const int need = fill ? 1 : 3;
-        if (n_rows + need > RB) {
-          flush_rows<RB>(park, ptgt, n_rows, ggrad);
-          n_rows = 0;
-        }
-        if (fill) {
-          park[n_rows * RB_ROW + lane] = v[3];
-          if (lane == 0) ptgt[n_rows] = make_int2(~gsig, 3);
-        } else {
-          accO += v[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) park[(n_rows + i) * RB_ROW + lane] = v[i];
-          if (lane < 3) ptgt[n_rows + lane] = make_int2(gsig, lane);
-        }
-        n_rows = __builtin_amdgcn_readfirstlane(n_rows + need);
       }
       __builtin_amdgcn_wave_barrier();
       hi = nhi;
