@@ -383,10 +383,16 @@ __device__ inline float wave_totals_to_lanes(const float (&v)[N]) {
   return out;
 }
 
+// Minimum over the wavefront: running minima inside each row of 16 lanes by
+// DPP row shifts (a lane with no source keeps its own value), then the four
+// rows' last lanes.  Needs no per-lane shuffle addresses.
 __device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-  return __builtin_amdgcn_readfirstlane(v);
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
 // Flushes one wavefront's running per-curve sums into the FP64 per-curve
@@ -464,11 +470,11 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // running per-curve sums that are flushed when the curve changes along the
 // list (and for strokes every FLUSH entries).  The entries of a step are cut
 // into runs of one curve with one ballot, and each run is composited by a loop
-// for its kind, with no per-entry curve test.  Occupancy: six wavefronts per SIMD for one
-// pixel per lane at depth 64, five for 32 x 32 tiles at depth 64 (96 VGPRs);
-// elsewhere the registers decide.
+// for its kind, with no per-entry curve test.  Occupancy: six wavefronts per
+// SIMD for one pixel per lane at depth 64, four for 32 x 32 tiles at depth 64
+// (128 VGPRs, unspilled); elsewhere the registers decide.
 template <int C, int TILE, int E>
-__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 5 : 1)) void k_blend_bwd(
+__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 4 : 1)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
