@@ -104,7 +104,14 @@ __device__ inline uint64_t lanes_below() {
 }
 
 // LDS bytes per wavefront for a step of `depth` entries.
-constexpr int FWD_ENTRY_BYTES = 40;   // geometry, opacity + colour, list position, curve
+// A forward entry: what every composited pixel reads, in one 32-byte record
+// (one LDS address per entry), and the colour, read where a run begins.
+struct FwdRec {
+  float4 geo;          // tile-local centre, squared support radius, exp2 coefficient
+  float op;            // opacity
+  int pos, curve, pad;  // list position, curve
+};
+constexpr int FWD_ENTRY_BYTES = sizeof(FwdRec) + 16;
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
 // The adjoint parks the per-lane gradient values it still has to sum over
 // the wavefront in LDS rows of 64 floats, one row per value (three for a
@@ -141,10 +148,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
   const float amax = pr.alpha_max, eps = pr.eps_T, ks = pr.k_sigma;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   char* mine_lds = smem + (size_t)wv * (64 * E) * FWD_ENTRY_BYTES;
-  float4* wgeo = (float4*)mine_lds;
-  float4* wpc = wgeo + 64 * E;
-  int* wpos = (int*)(wpc + 64 * E);
-  int* wcur = wpos + 64 * E;
+  FwdRec* wrec = (FwdRec*)mine_lds;
+  float4* wcol = (float4*)(wrec + 64 * E);  // colour
   const uint64_t below = lanes_below();
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
@@ -209,10 +214,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         const uint64_t m = __ballot(keep);
         if (keep) {
           const int dst = cnt + __popcll(m & below);
-          wgeo[dst] = geo;
-          wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
-          wpos[dst] = mypos;
-          wcur[dst] = e[u].r.curve;
+          FwdRec rec;
+          rec.geo = geo;
+          rec.op = e[u].r.opacity;
+          rec.pos = mypos;
+          rec.curve = e[u].r.curve;
+          rec.pad = 0;
+          wrec[dst] = rec;
+          wcol[dst] = make_float4(e[u].c0, e[u].c1, e[u].c2, 0.0f);
         }
         cnt += __popcll(m);
       }
@@ -229,17 +238,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      int jstop[PPT];
-#pragma unroll
-      for (int q = 0; q < PPT; ++q) jstop[q] = -1;
       // composited entries that begin a run (their curve differs from the
       // entry before, the first one compared with the previous step's run)
       uint64_t rs[E];
 #pragma unroll
       for (int g = 0; g < E; ++g) {
         const int i = 64 * g + lane;
-        const int prev = i == 0 ? run_curve : wcur[i > 0 ? i - 1 : 0];
-        rs[g] = __ballot(i < cnt && wcur[i < cnt ? i : 0] != prev);
+        const int prev = i == 0 ? run_curve : wrec[i > 0 ? i - 1 : 0].curve;
+        rs[g] = __ballot(i < cnt && wrec[i < cnt ? i : 0].curve != prev);
       }
       for (int j = 0; j < cnt;) {
         // this segment: j up to the next run start (or the step's end)
@@ -261,17 +267,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
             }
             Tst[q] = T[q];
           }
-          const float4 pc = wpc[j];
-          rc0 = pc.y;
-          rc1 = pc.z;
-          rc2 = pc.w;
-          run_curve = wcur[j];
+          const float4 pc = wcol[j];
+          rc0 = pc.x;
+          rc1 = pc.y;
+          rc2 = pc.z;
+          run_curve = wrec[j].curve;
         }
-        const float* wop = (const float*)wpc;  // opacities
 #pragma unroll 4
         for (; j < jend; ++j) {
-          const float4 gm = wgeo[j];
-          const float op = wop[4 * j];
+          const float4 gm = wrec[j].geo;
+          const float op = wrec[j].op;
+          const int pos = wrec[j].pos;
 #pragma unroll
           for (int q = 0; q < PPT; ++q) {
             const float dx = px[q] - gm.x, dy = py[q] - gm.y;
@@ -281,17 +287,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
             const float alpha = in ? fminf(amax, op * G) : 0.0f;
             T[q] = T[q] * (1.0f - alpha);
             const bool now = in && (T[q] < eps);
-            jstop[q] = now ? j : jstop[q];
+            stop[q] = now ? pos : stop[q];  // the pixel's last composited position
             done[q] = done[q] || now;
           }
         }
       }
       bool mine = true;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        if (jstop[q] >= 0) stop[q] = wpos[jstop[q]];
-        mine = mine && done[q];
-      }
+      for (int q = 0; q < PPT; ++q) mine = mine && done[q];
       hi = nhi;
       lo_s = nlo;
       nhi = n2hi;
