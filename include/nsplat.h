@@ -146,7 +146,7 @@ typedef struct {
   float h;          /* fill grid step in px (1); see h_dev                   */
   float k_sigma;    /* support radius in sigmas (6)                          */
   float alpha_max;  /* per-pixel opacity clamp (0.99)                        */
-  float eps_T;      /* a pixel stops once its transmittance drops below (1e-6) */
+  float eps_T;      /* a pixel stops once its transmittance drops below, in [0, 1] (1e-6) */
   int32_t kappa;    /* extra copies of each open-curve endpoint Gaussian (4) */
   int32_t tile;     /* tile side in px: 8, 16 or 32                          */
   int32_t batch;    /* Gaussians staged in LDS per block step: 32..256       */

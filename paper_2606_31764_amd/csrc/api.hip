@@ -208,7 +208,8 @@ int check_params(nsplat_ctx* ctx, const nsplat_params* pr) {
   if (!(pr->alpha_max > 0.f && pr->alpha_max < 1.f))
     return fail(ctx, NSPLAT_EINVAL, "alpha_max must be in (0, 1) (got %g)", (double)pr->alpha_max);
   if (!(pr->k_sigma > 0.f)) return fail(ctx, NSPLAT_EINVAL, "k_sigma must be > 0");
-  if (!(pr->eps_T >= 0.f)) return fail(ctx, NSPLAT_EINVAL, "eps_T must be >= 0");
+  if (!(pr->eps_T >= 0.f && pr->eps_T <= 1.f))
+    return fail(ctx, NSPLAT_EINVAL, "eps_T must be in [0, 1] (got %g)", (double)pr->eps_T);
   if (pr->kappa < 0) return fail(ctx, NSPLAT_EINVAL, "kappa must be >= 0");
   if (!(pr->fill_pad >= 0.f)) return fail(ctx, NSPLAT_EINVAL, "fill_pad must be >= 0");
   return NSPLAT_OK;

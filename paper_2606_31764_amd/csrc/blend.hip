@@ -169,7 +169,6 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     // depend on the batch depth.
     float px[PPT], py[PPT], T[PPT], Tst[PPT], acc[PPT][3];
     int stop[PPT];
-    bool done[PPT];
     int run_curve = -1;
     float rc0 = 0.0f, rc1 = 0.0f, rc2 = 0.0f;  // the run's colour
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -179,12 +178,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       pixel_of<TILE>(quad, lane, q, &lx, &ly);
       px[q] = (float)lx;
       py[q] = (float)ly;
-      T[q] = 1.0f;
-      Tst[q] = 1.0f;
+      // a pixel is live while T >= eps_T (0 <= eps_T <= 1): T only falls,
+      // and it falls below eps_T exactly at the entry where the pixel stops;
+      // pixels outside the image start at T = 0
+      T[q] = (x0 + lx < st.W && y0 + ly < st.H) ? 1.0f : 0.0f;
+      Tst[q] = T[q];
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[q][c] = 0.0f;
       stop[q] = start;
-      done[q] = !(x0 + lx < st.W && y0 + ly < st.H);
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
     // front to back: list positions end-1 down to start, at most `depth` per
@@ -283,18 +284,16 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
             const float dx = px[q] - gm.x, dy = py[q] - gm.y;
             const float d2 = __builtin_fmaf(dx, dx, dy * dy);
             const float G = __builtin_amdgcn_exp2f(gm.w * d2);
-            const bool in = (d2 <= gm.z) && !done[q];
-            const float alpha = in ? fminf(amax, op * G) : 0.0f;
-            T[q] = T[q] * (1.0f - alpha);
-            const bool now = in && (T[q] < eps);
-            stop[q] = now ? pos : stop[q];  // the pixel's last composited position
-            done[q] = done[q] || now;
+            const bool in = (d2 <= gm.z) && (T[q] >= eps);
+            const float Tn = T[q] * (1.0f - fminf(amax, op * G));
+            stop[q] = (in && Tn < eps) ? pos : stop[q];  // the pixel's last composited position
+            T[q] = in ? Tn : T[q];
           }
         }
       }
       bool mine = true;
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) mine = mine && done[q];
+      for (int q = 0; q < PPT; ++q) mine = mine && !(T[q] >= eps);
       hi = nhi;
       lo_s = nlo;
       nhi = n2hi;

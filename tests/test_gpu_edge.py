@@ -352,3 +352,23 @@ def test_wide_radix_digit_lists_are_sorted_and_agree():
     assert n_pairs == len(idx)
     assert np.abs(outs[8]["image"] - outs[16]["image"]).max() < 2e-6
     assert grad_close(outs[8]["grads"], outs[16]["grads"], rtol=2e-5, atol=1e-7) <= 1.0
+
+
+def test_transmittance_threshold_range():
+    # a high threshold stops pixels after a few layers: images and gradients
+    # against the oracle; eps_T = 1 (each pixel stops at its first Gaussian
+    # with alpha > 0) is accepted, a threshold above 1 is rejected on the host
+    from paper_2606_31764_amd._lib import NSplatError
+    rng = np.random.default_rng(43)
+    parts = [_part(rng.uniform(6, 42, (6, 2)), p=3, seed=1, color=(0.9, 0.2, 0.1)),
+             _part(rng.uniform(6, 42, (5, 2)), p=2, closed=True, filled=True, seed=2, color=(0.1, 0.3, 0.8)),
+             _part(rng.uniform(6, 42, (6, 2)), p=3, closed=True, seed=3, color=(0.2, 0.7, 0.3))]
+    b = _batch(parts)
+    _full_parity(b, Params().replace(delta_c=2.0, eps_T=0.5))
+    p1 = Params().replace(delta_c=2.0, eps_T=1.0)
+    one = gpu_run(b, p1, backward=False)
+    # one Gaussian at most per pixel: T >= 1 - alpha_max everywhere
+    assert one["T"].min() >= 1.0 - p1.alpha_max - 1e-6
+    assert one["T"].min() < 0.5  # and the curves do cover pixels
+    with pytest.raises(NSplatError, match="eps_T"):
+        gpu_run(b, Params().replace(delta_c=2.0, eps_T=1.5), backward=False)
