@@ -274,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           rc2 = pc.z;
           run_curve = wrec[j].curve;
         }
-#pragma unroll 4
+#pragma unroll 8
         for (; j < jend; ++j) {
           const float4 gm = wrec[j].geo;
           const float op = wrec[j].op;
