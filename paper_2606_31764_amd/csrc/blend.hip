@@ -657,13 +657,16 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           since = 0;
         }
         if (cur_fill) {
-          // fill Gaussians: one value each (dL/do_j), parked in one row
-          for (; j < jend; ++j) {
-            const float4 gm = wgeo[j];
-            const float op = wop[4 * j];
-            const int4 mt = wmeta[j];
-            float v3 = 0.0f;
-            bool act = false;
+          // fill Gaussians: one value each (dL/do_j), parked in one row;
+          // entries are evaluated two at a time (independent work of the
+          // pair overlaps) and parked in order
+          auto fill_eval = [&](int jj, float& v3, bool& act, int& gneg) {
+            const float4 gm = wgeo[jj];
+            const float op = wop[4 * jj];
+            const int4 mt = wmeta[jj];
+            gneg = mt.x;
+            v3 = 0.0f;
+            act = false;
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
               const float dx = px[q] - gm.x, dy = py[q] - gm.y;
@@ -681,14 +684,33 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               T[q] = T[q] * onem;
               v3 = __builtin_fmaf(dLda, G, v3);  // dL/do_j
             }
-            if (__ballot(act) == 0ull) continue;
+          };
+          auto fill_park = [&](float v3, bool act, int gneg) {
+            if (__ballot(act) == 0ull) return;
             if (n_rows + 1 > RB) {
               flush_rows<RB>(park, ptgt, n_rows, ggrad);
               n_rows = 0;
             }
             park[n_rows * RB_ROW + lane] = v3;
-            if (lane == 0) ptgt[n_rows] = make_int2(~mt.x, 3);
+            if (lane == 0) ptgt[n_rows] = make_int2(~gneg, 3);
             n_rows = __builtin_amdgcn_readfirstlane(n_rows + 1);
+          };
+          for (; j + 1 < jend; j += 2) {
+            float va, vb;
+            bool aa, ab;
+            int ga, gb;
+            fill_eval(j, va, aa, ga);
+            fill_eval(j + 1, vb, ab, gb);
+            fill_park(va, aa, ga);
+            fill_park(vb, ab, gb);
+          }
+          if (j < jend) {
+            float va;
+            bool aa;
+            int ga;
+            fill_eval(j, va, aa, ga);
+            fill_park(va, aa, ga);
+            ++j;
           }
         } else {
           // stroke Gaussians: dL/dmu (2) and dL/dsigma parked in three rows;
