@@ -30,7 +30,13 @@
  *     work is issued.  Value errors that only the device can see (a curve with
  *     degree outside [1, NSPLAT_MAX_DEGREE], too few key points, a filled
  *     curve that is not closed, a wrong interval count) set
- *     NSPLAT_STATUS_DATA; such a curve produces no Gaussians.
+ *     NSPLAT_STATUS_DATA; such a curve produces no Gaussians.  Values outside
+ *     the domain of Sec. 3.1 (a rational weight w_i <= 0, a stroke width
+ *     <= 0, a knot interval < 0, intervals that sum to 0 so that the curve
+ *     has no parameter domain, or a non-finite key point, weight, width,
+ *     interval, colour or opacity) set NSPLAT_STATUS_VALUE, and such a curve
+ *     too produces no Gaussians and receives zero gradients.  Both mark the
+ *     curve NSPLAT_PLAN_INVALID in the plan.
  *   - Coordinates are pixels, y pointing down; pixel (x, y) has its centre at
  *     (x + 1/2, y + 1/2); a canvas spans [0, W] x [0, H].
  */
@@ -56,7 +62,7 @@ extern "C" {
 /* Version of the structure layouts below; nsplat_abi_version() returns the
  * value the library was built with, so a binding can refuse a library whose
  * structures it would misread. */
-#define NSPLAT_ABI_VERSION 2
+#define NSPLAT_ABI_VERSION 3
 
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
@@ -72,6 +78,7 @@ extern "C" {
 #define NSPLAT_STATUS_PAIR_CAP 2    /* pair capacity exceeded                 */
 #define NSPLAT_STATUS_BOUND_CAP 4   /* boundary-point capacity exceeded       */
 #define NSPLAT_STATUS_DATA 8        /* invalid curve data (see above)         */
+#define NSPLAT_STATUS_VALUE 16      /* a curve with invalid values (see above) */
 
 /* Timed phases (nsplat_timing_read); each is one kernel unless noted. */
 #define NSPLAT_T_PLAN 0        /* knots, arc length, counts, boundary, scans (5 kernels) */
@@ -87,7 +94,7 @@ extern "C" {
 #define NSPLAT_T_REG 10        /* geometric regularisers (nsplat_backward_reg)  */
 #define NSPLAT_NUM_TIMERS 11
 
-/* plan[] row layout (dev int32[n_curves][8]) */
+/* plan[] row layout (dev int32[n_curves][NSPLAT_PLAN_STRIDE]) */
 #define NSPLAT_PLAN_COUNT 0   /* Gaussians of the curve                        */
 #define NSPLAT_PLAN_NSAMP 1   /* contour samples M (Sec. 3.2) or boundary points (Sec. 3.3) */
 #define NSPLAT_PLAN_IX0 2     /* fill lattice window: first column index       */
@@ -96,7 +103,17 @@ extern "C" {
 #define NSPLAT_PLAN_NY 5      /*                      rows                     */
 #define NSPLAT_PLAN_GOFF 6    /* index of the curve's first Gaussian           */
 #define NSPLAT_PLAN_BOFF 7    /* index of the curve's first boundary point     */
-#define NSPLAT_PLAN_STRIDE 8
+#define NSPLAT_PLAN_FLAGS 8   /* NSPLAT_PLAN_NEAR_INT | NSPLAT_PLAN_INVALID    */
+#define NSPLAT_PLAN_STRIDE 9
+
+/* Plan flags of a curve, rewritten by every nsplat_sample (frozen or not).
+ * NEAR_INT: delta L (delta_c L for strokes, delta_b L for fills) lies within
+ * 1e-9 of an integer, so the count M = ceil(delta L) of Sec. 3.2 / 3.3 could
+ * round to either side under another summation order of the arc length.
+ * INVALID: the curve has invalid data or values and produces no Gaussians
+ * (its counts are set to 0, also under frozen != 0). */
+#define NSPLAT_PLAN_NEAR_INT 1
+#define NSPLAT_PLAN_INVALID 2
 
 typedef struct nsplat_ctx nsplat_ctx;
 
@@ -176,7 +193,9 @@ typedef struct {
   nsplat_caps caps;
 } nsplat_buffers;
 
-/* Parameter gradients (dev FP32, same shapes as the inputs; overwritten). */
+/* Parameter gradients (dev FP32, same shapes as the inputs; overwritten).  A
+ * NULL pointer leaves that group out: it is not written (e.g. weights or knot
+ * intervals held fixed, as in the ablations of Table 1). */
 typedef struct {
   float* key_xy;  /* [K][2] */
   float* key_w;   /* [K]    */
@@ -227,7 +246,8 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes
  * alpha = min(alpha_max, o exp(-|x - mu|^2 / (2 sigma^2))) for |x - mu| <=
  * k_sigma sigma, colour += c alpha T, T *= 1 - alpha, stop once T < eps_T;
  * image = colour + T bg.  Uses the tile lists and scene table built by the
- * last nsplat_bin on these buffers (same params.tile).  image is per scene [channels][H][W], concatenated
+ * last nsplat_bin on these buffers; NSPLAT_EINVAL if that call (on this
+ * context) used another params.tile (the same holds for nsplat_backward).  image is per scene [channels][H][W], concatenated
  * over scenes; T_final and n_last are per scene [H][W]: the final
  * transmittance and the idx position where the pixel stopped.
  * persistent != 0 runs one resident grid that pulls tiles from a device work
@@ -367,8 +387,9 @@ int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bufs, int32_t* h
 
 /* Autotuner: times nsplat_bin + nsplat_forward + nsplat_backward on the given
  * state for every tile side in {8, 16, 32} and batch depth in
- * {32, 64, 128, 256} (after one warm-up each), and returns the fastest in
- * *best_tile / *best_batch.  The buffers must be sized for the largest tile
+ * {32, 64, 128, 256} (after one warm-up each), returns the fastest in
+ * *best_tile / *best_batch, and leaves the buffers, image and gradients as
+ * nsplat_bin + nsplat_forward + nsplat_backward at that setting leave them.  The buffers must be sized for the largest tile
  * count (tile 8) and pair count (tile 8 has the most pairs).  times_ms, if
  * non-NULL, receives the 12 timings in (tile, batch) row-major order. */
 int nsplat_autotune(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,

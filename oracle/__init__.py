@@ -33,6 +33,7 @@ DEFAULTS = dict(delta_c=10.0, delta_b=0.5, rho=2.0, eta=1.5, gamma=5.0, nl_facto
                 fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=6.0, kappa=4)
 
 P_COUNT, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_FLAG = range(8)
+FLAG_NEAR_INT, FLAG_INVALID = 1, 2
 KIND = dict(key_x=1, key_y=2, key_w=3, key_s=4, tau=5, opacity=6, color0=7, color1=8, color2=9)
 
 
@@ -104,6 +105,14 @@ def _p(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else None
 
 
+def _plan_rows(pl, n_curves):
+    """A plan in the oracle's own layout: int32 [n_curves][8]."""
+    pl = np.ascontiguousarray(pl, np.int32)
+    if pl.shape != (n_curves, 8):
+        raise ValueError("oracle plan must be int32 [%d][8] (got %s)" % (n_curves, pl.shape))
+    return pl
+
+
 class _Batch:
     """FP64 / int32 copies of a curve batch, kept alive with the ctypes views."""
 
@@ -134,8 +143,9 @@ class _Batch:
 
 
 def plan(batch, params=None):
-    """Per-curve plan [N][8] (count, n_samples, ix0, iy0, nx, ny, g_offset, near-int flag),
-    arc lengths L [N], and the total number of Gaussians."""
+    """Per-curve plan [N][8] (count, n_samples, ix0, iy0, nx, ny, g_offset, flags:
+    1 = delta L within 1e-9 of an integer, 2 = values outside the domain of
+    Sec. 3.1, no Gaussians), arc lengths L [N], and the total number of Gaussians."""
     B = _Batch(batch, params)
     pl = np.zeros((B.n_curves, 8), np.int32)
     L = np.zeros(B.n_curves, np.float64)
@@ -149,7 +159,7 @@ def gaussians(batch, params=None, frozen_plan=None):
     if frozen_plan is None:
         pl, L, G = plan(batch, params)
     else:
-        pl = np.ascontiguousarray(frozen_plan, np.int32)
+        pl = _plan_rows(frozen_plan, B.n_curves)
         L = None
         G = int(pl[:, P_COUNT].sum())
     mu = np.zeros((G, 2)); sg = np.zeros(G); op = np.zeros(G)
@@ -325,7 +335,7 @@ def reg_loss_grad(batch, plan_rows, params=None, **reg):
     out = dict(key_xy=np.zeros_like(k["key_xy"]), key_w=np.zeros_like(k["key_w"]),
                key_s=np.zeros_like(k["key_s"]), tau=np.zeros_like(k["tau"]),
                color=np.zeros_like(k["color"]), opacity=np.zeros_like(k["opacity"]))
-    total = lib().or_reg_grad_full(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), ctypes.byref(rg),
+    total = lib().or_reg_grad_full(*B.refs(), _p(_plan_rows(plan_rows, B.n_curves)), ctypes.byref(rg),
                                    *[_p(out[n]) for n in ("key_xy", "key_w", "key_s", "tau")])
     del keep_bb
     return float(total), out
@@ -335,7 +345,7 @@ def reg_loss(batch, plan_rows, params=None, **reg):
     """Value only (no gradient seeds)."""
     B = _Batch(batch, params)
     rg, keep_bb = _reg(**reg)
-    v = lib().or_reg_loss(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), ctypes.byref(rg), 0,
+    v = lib().or_reg_loss(*B.refs(), _p(_plan_rows(plan_rows, B.n_curves)), ctypes.byref(rg), 0,
                           None, None)
     del keep_bb
     return float(v)
@@ -364,7 +374,7 @@ def udf_loss(batch, plan_rows, image, target, tau, sel=None, params=None):
     npix = int(sum(int(h) * int(w) for h, w in batch.hw))
     dist = np.zeros(npix)
     sl = None if sel is None else np.ascontiguousarray(sel, np.int32)
-    v = lib().or_udf_loss(*B.refs(), _p(np.ascontiguousarray(plan_rows, np.int32)), _p(sl), float(tau), _p(img),
+    v = lib().or_udf_loss(*B.refs(), _p(_plan_rows(plan_rows, B.n_curves)), _p(sl), float(tau), _p(img),
                           _p(tgt), _p(dL), _p(dist))
     return float(v), dL, dist
 

@@ -280,6 +280,31 @@ T sample_u(const Curve<T>& cv, int j, int M, bool closed) {
   return a + T((double)j) * step;
 }
 
+// Sec. 3.1 fixes the value domain of a curve: rational weights w_i > 0 and
+// knot intervals tau_j >= 0 (the knot vector is their cumulative sum) whose
+// sum, the length of the parameter domain, is positive; a stroke's widths are
+// the third coordinate of its control points and set sigma = s / rho > 0.  A
+// curve outside that domain (or with a non-finite input) is rendered as
+// absent.
+bool values_in_domain(const or_curves* in, int c) {
+  const bool filled = (in->flags[c] & F_FILLED) != 0;
+  for (int k = in->key_off[c]; k < in->key_off[c + 1]; ++k) {
+    if (!std::isfinite(in->key_xy[2 * k]) || !std::isfinite(in->key_xy[2 * k + 1])) return false;
+    if (!(in->key_w[k] > 0.0) || !std::isfinite(in->key_w[k])) return false;
+    if (!filled && (!(in->key_s[k] > 0.0) || !std::isfinite(in->key_s[k]))) return false;
+  }
+  double sum = 0.0;
+  for (int t = in->tau_off[c]; t < in->tau_off[c + 1]; ++t) {
+    if (!(in->tau[t] >= 0.0) || !std::isfinite(in->tau[t])) return false;
+    sum += in->tau[t];
+  }
+  if (!(sum > 0.0)) return false;
+  if (!std::isfinite(in->opacity[c])) return false;
+  for (int ch = 0; ch < in->channels; ++ch)
+    if (!std::isfinite(in->color[in->channels * c + ch])) return false;
+  return true;
+}
+
 // Count rule of Sec. 3.2 / 3.3: ceil(delta L) with a floor (2 for open
 // strokes, 3 for closed strokes and for fill boundaries).  Flags values that
 // are within 1e-9 of an integer (two FP64 evaluations could round apart).
@@ -393,10 +418,11 @@ template <class T>
 void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* pr, int c,
                      const int32_t* plan_row, int seed_kind, int seed_index, std::vector<Gauss<T>>& out,
                      const std::vector<char>* need = nullptr) {
+  out.clear();
+  const int count = plan_row[P_COUNT], ns = plan_row[P_NSAMP];
+  if (count <= 0 || ns <= 0) return;  // no Gaussians (e.g. a curve outside the value domain)
   const Curve<T> cv = build_curve<T>(in, c, seed_kind, seed_index);
   const T o = lift<T>(in->opacity[c], seed_kind == S_OPACITY);
-  const int count = plan_row[P_COUNT], ns = plan_row[P_NSAMP];
-  out.clear();
   if (!cv.filled) {
     const int kap = cv.closed ? 0 : pr->kappa;
     std::vector<Gauss<T>> smp(ns);
@@ -426,7 +452,6 @@ void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* 
       }
   }
   (void)sc;
-  (void)count;
 }
 
 // Scene ranges of the Gaussian array (curves are grouped by scene).
@@ -613,14 +638,21 @@ std::vector<double> curves_per_scene(const or_curves* in, const or_scenes* sc) {
 
 extern "C" {
 
-// Plan: per curve {count, n_samples, ix0, iy0, nx, ny, g_offset, near-int flag}
-// and the arc length L.  Returns the total number of Gaussians.
+// Plan: per curve {count, n_samples, ix0, iy0, nx, ny, g_offset, flags}
+// (flags: 1 = delta L within 1e-9 of an integer, 2 = values outside the
+// domain of Sec. 3.1, the curve then has no Gaussians) and the arc length L.
+// Returns the total number of Gaussians.
 int64_t or_plan(const or_curves* in, const or_scenes* sc, const or_params* pr, int32_t* plan, double* L) {
   const int N = in->n_curves;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int c = 0; c < N; ++c) {
     int32_t* row = plan + P_STRIDE * c;
     for (int k = 0; k < P_STRIDE; ++k) row[k] = 0;
+    if (!values_in_domain(in, c)) {
+      L[c] = 0.0;
+      row[P_FLAG] = 2;
+      continue;
+    }
     const Curve<double> cv = build_curve<double>(in, c, S_NONE, 0);
     const SceneGeom geo = scene_geom(sc, pr, in->scene[c]);
     const double len = arc_length(cv, geo.n_L);

@@ -12,11 +12,13 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nsplat.h")
 OK, EINVAL, ECAPACITY, EHIP = 0, 1, 2, 3
 CLOSED, FILLED = 1, 2
 MAX_DEGREE = 5
-ABI_VERSION = 2  # NSPLAT_ABI_VERSION of include/nsplat.h
+ABI_VERSION = 3  # NSPLAT_ABI_VERSION of include/nsplat.h
 CNT_GAUSS, CNT_PAIRS, CNT_STATUS, CNT_GAUSS_REQ, CNT_PAIRS_REQ, CNT_BOUND_REQ, CNT_BOUND = range(7)
 NUM_COUNTERS = 16
-STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA = 1, 2, 4, 8
-PLAN_STRIDE = 8
+STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA, STATUS_VALUE = 1, 2, 4, 8, 16
+PLAN_STRIDE = 9
+PLAN_FLAGS = 8
+PLAN_NEAR_INT, PLAN_INVALID = 1, 2
 
 vp = ctypes.c_void_p
 

@@ -432,8 +432,9 @@ __global__ __launch_bounds__(64) void k_fold(nsplat_curves cv, Work w, nsplat_gr
   const CurveView v = curve_view(cv, w.knots, c);
   const int C = cv.channels;
   const double* gc = w.gcurve + 4 * (int64_t)c;
-  if (lane == 0) gr.opacity[c] = (float)gc[0];
-  if (lane < C) gr.color[(int64_t)c * C + lane] = (float)gc[1 + lane];
+  // a NULL output leaves that gradient group out
+  if (lane == 0 && gr.opacity) gr.opacity[c] = (float)gc[0];
+  if (lane < C && gr.color) gr.color[(int64_t)c * C + lane] = (float)gc[1 + lane];
   const bool ok = curve_valid(v);
   const double* gcp = w.gcp + 4 * ((int64_t)v.k0 + (int64_t)c * CP_PAD);
   for (int k = lane; k < v.nk; k += 64) {
@@ -449,11 +450,14 @@ __global__ __launch_bounds__(64) void k_fold(nsplat_curves cv, Work w, nsplat_gr
       }
     }
     const int64_t kk = v.k0 + k;
-    gr.key_xy[2 * kk] = (float)acc[0];
-    gr.key_xy[2 * kk + 1] = (float)acc[1];
-    gr.key_w[kk] = (float)acc[2];
-    gr.key_s[kk] = (float)acc[3];
+    if (gr.key_xy) {
+      gr.key_xy[2 * kk] = (float)acc[0];
+      gr.key_xy[2 * kk + 1] = (float)acc[1];
+    }
+    if (gr.key_w) gr.key_w[kk] = (float)acc[2];
+    if (gr.key_s) gr.key_s[kk] = (float)acc[3];
   }
+  if (!gr.tau) return;
   float* gt = gr.tau + v.t0;
   if (!ok) {
     for (int t = lane; t < v.nt; t += 64) gt[t] = 0.0f;

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "nsplat_internal.h"
 
@@ -16,6 +18,9 @@ struct nsplat_ctx {
   int n_cu = 256;
   std::string err;
   nsp::Timer timer;
+  // tile side of the last nsplat_bin on each workspace (the tile lists,
+  // checkpoint offsets and adjoint items in it are laid out for that side)
+  std::vector<std::pair<const void*, int>> bin_tile;
 };
 
 namespace nsp {
@@ -230,6 +235,25 @@ int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   return NSPLAT_OK;
 }
 
+void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile) {
+  for (auto& e : ctx->bin_tile)
+    if (e.first == ws) {
+      e.second = tile;
+      return;
+    }
+  ctx->bin_tile.emplace_back(ws, tile);
+}
+
+// NSPLAT_EINVAL when the workspace's tile lists were built (by this context)
+// for another tile side than params.tile.
+int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile) {
+  for (const auto& e : ctx->bin_tile)
+    if (e.first == ws && e.second != tile)
+      return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with tile %d, "
+                  "but params.tile is %d", e.second, tile);
+  return NSPLAT_OK;
+}
+
 int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_params* pr,
             const nsplat_buffers* bf, void* stream, Launch* L) {
   if (!ctx) return NSPLAT_EINVAL;
@@ -316,6 +340,7 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   hipError_t h = launch_scene_setup(L, nullptr);
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
+  record_bin_tile(ctx, bf->ws, pr->tile);
   return NSPLAT_OK;
 }
 
@@ -326,6 +351,7 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!image || !T_final || !n_last) return fail(ctx, NSPLAT_EINVAL, "image / T_final / n_last is NULL");
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile))) return e;
   hipError_t h = launch_blend_fwd(L, image, T_final, n_last, persistent);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_forward");
   return NSPLAT_OK;
@@ -338,9 +364,7 @@ int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_s
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!dL || !T_final || !n_last || !gr) return fail(ctx, NSPLAT_EINVAL, "dL_dimage / T_final / n_last / grads is NULL");
-  if (cv->n_curves > 0 && (!gr->key_xy || !gr->key_w || !gr->key_s || !gr->color || !gr->opacity ||
-                           (cv->n_taus > 0 && !gr->tau)))
-    return fail(ctx, NSPLAT_EINVAL, "a gradient pointer is NULL");
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile))) return e;
   const bool use_reg = reg && (reg->bbox_weight != 0.0f || reg->deriv_weight != 0.0f);
   if (use_reg) {
     if (reg->deriv_weight != 0.0f && (reg->deriv_order < 1 || reg->deriv_order > 3))
@@ -509,6 +533,15 @@ int nsplat_autotune(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc == NSPLAT_EHIP && ctx->err.empty()) ctx->err = "autotune: HIP event error";
+  if (rc == NSPLAT_OK) {
+    // leave the buffers and outputs in the state of the chosen setting
+    nsplat_params p = *pr;
+    p.tile = *best_tile;
+    p.batch = *best_batch;
+    rc = nsplat_bin(ctx, cv, sc, &p, bf, stream);
+    if (rc == NSPLAT_OK) rc = nsplat_forward(ctx, cv, sc, &p, bf, image, T_final, n_last, persistent, stream);
+    if (rc == NSPLAT_OK) rc = nsplat_backward(ctx, cv, sc, &p, bf, dL, T_final, n_last, gr, persistent, stream);
+  }
   return rc;
 }
 

@@ -36,7 +36,7 @@ struct SceneTab {
   int32_t H, W, tiles_x, tiles_y, tile_off, pix_off, n_L, pad;
 };
 
-enum { P_COUNT = 0, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_BOFF, P_STRIDE };
+enum { P_COUNT = 0, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_BOFF, P_FLAGS, P_STRIDE };
 
 // Device pointers carved out of the caller's workspace.
 struct Work {

@@ -59,12 +59,47 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ inline int count_rule(double delta, double L, int floor_min) {
+// Count rule of Sec. 3.2 / 3.3: ceil(delta L), at least floor_min.  Sets
+// *near when delta L lies within 1e-9 of an integer at or above the floor
+// (another summation order of L could round the count to the other side).
+__device__ inline int count_rule(double delta, double L, int floor_min, int* near) {
   const double x = delta * L;
+  const double r = rint(x);
+  if (fabs(x - r) < 1e-9 && r >= (double)floor_min) *near = 1;
   const double M = ceil(x);
   if (!(M >= (double)floor_min)) return floor_min;  // also catches NaN
   if (M > 2.0e9) return 2000000000;
   return (int)M;
+}
+
+// Whether the values of curve c lie in the domain of Sec. 3.1 (w_i > 0,
+// tau_j >= 0 with at least one tau_j > 0, so that the parameter domain is not
+// empty; a stroke's widths > 0; everything finite), decided by the whole
+// block.  Every thread of the block must call it.
+__device__ inline bool curve_values_ok(const nsplat_curves& cv, const CurveView& v, int c) {
+  int bad = 0, pos = 0;
+  for (int k = threadIdx.x; k < v.nk; k += blockDim.x) {
+    const int64_t i = v.k0 + k;
+    const float x = cv.key_xy[2 * i], y = cv.key_xy[2 * i + 1], wt = cv.key_w[i];
+    if (!isfinite(x) || !isfinite(y) || !(wt > 0.0f) || !isfinite(wt)) bad = 1;
+    if (!v.filled()) {
+      const float sw = cv.key_s[i];
+      if (!(sw > 0.0f) || !isfinite(sw)) bad = 1;
+    }
+  }
+  for (int k = threadIdx.x; k < v.nt; k += blockDim.x) {
+    const float t = cv.tau[v.t0 + k];
+    if (!(t >= 0.0f) || !isfinite(t)) bad = 1;
+    if (t > 0.0f) pos = 1;
+  }
+  if (threadIdx.x == 0) {
+    if (!isfinite(cv.opacity[c])) bad = 1;
+    for (int ch = 0; ch < cv.channels; ++ch)
+      if (!isfinite(cv.color[(int64_t)c * cv.channels + ch])) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  pos = __syncthreads_or(pos);
+  return !bad && pos;
 }
 
 // THREADS lanes per curve: 1024 when there are few curves, so that the N_L
@@ -82,8 +117,22 @@ __global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat
     if (threadIdx.x == 0) {
       row[P_COUNT] = 0;
       row[P_NSAMP] = 0;
+      row[P_FLAGS] = NSPLAT_PLAN_INVALID;
       w.L[c] = 0.0;
       atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_DATA);
+    }
+    return;
+  }
+  if (!curve_values_ok(cv, v, c)) {
+    // no Gaussians, also under a frozen plan (the kernels downstream see a
+    // curve with no samples and leave its gradients at zero)
+    if (threadIdx.x == 0) {
+      row[P_COUNT] = 0;
+      row[P_NSAMP] = 0;
+      row[P_NX] = row[P_NY] = 0;
+      row[P_FLAGS] = NSPLAT_PLAN_INVALID;
+      w.L[c] = 0.0;
+      atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_VALUE);
     }
     return;
   }
@@ -141,16 +190,19 @@ __global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat
   const double L = block_sum<THREADS>(part, red);
   if (threadIdx.x == 0) {
     w.L[c] = L;
-    if (!frozen) {
-      if (!v.filled()) {
-        const int M = count_rule((double)pr.delta_c, L, v.closed() ? 3 : 2);
+    int near = 0;
+    if (!v.filled()) {
+      const int M = count_rule((double)pr.delta_c, L, v.closed() ? 3 : 2, &near);
+      if (!frozen) {
         row[P_NSAMP] = M;
         row[P_COUNT] = v.closed() ? M : M + 2 * pr.kappa;
         row[P_IX0] = row[P_IY0] = row[P_NX] = row[P_NY] = 0;
-      } else {
-        row[P_NSAMP] = count_rule((double)pr.delta_b, L, 3);
       }
+    } else {
+      const int nb = count_rule((double)pr.delta_b, L, 3, &near);
+      if (!frozen) row[P_NSAMP] = nb;
     }
+    row[P_FLAGS] = near ? NSPLAT_PLAN_NEAR_INT : 0;
   }
 }
 
@@ -796,11 +848,12 @@ hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const floa
   const int S = L.sc->n_scenes, C = L.cv->channels;
   int64_t npix = 0;
   for (int s = 0; s < S; ++s) npix += (int64_t)L.sc->hw_host[2 * s] * L.sc->hw_host[2 * s + 1];
-  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, L.stream, L.w.sacc, 0.0, (int64_t)(S + 1));
+  const Work& w = L.w;
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, L.stream, w.sacc, 0.0, (int64_t)(S + 1));
   if (npix <= 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_udf_weight, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, L.stream, *L.cv, L.w,
+  hipLaunchKernelGGL(k_udf_weight, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, L.stream, *L.cv, w,
                      L.bf->plan, (int64_t)L.bf->caps.boundary, S, C, sel, tau, dL);
-  hipLaunchKernelGGL(k_udf_grad, dim3(grid_for(npix, 256, 2048)), dim3(256), 0, L.stream, L.w, S, C, image, target,
+  hipLaunchKernelGGL(k_udf_grad, dim3(grid_for(npix, 256, 2048)), dim3(256), 0, L.stream, w, S, C, image, target,
                      dL, loss);
   return hipGetLastError();
 }

@@ -139,6 +139,10 @@ class Renderer:
         self.meta = Meta(batch, device)
         self.persistent = bool(persistent)
         self.h_dev = h_dev
+        # counts forward() calls: the adjoint reads the state the last forward
+        # left (Gaussians, tile lists, T, n_last, checkpoints), so an autograd
+        # node remembers the generation it was recorded at
+        self.generation = 0
         self.caps = dict(gauss=4096, pairs=16384, boundary=1024) if caps is None else dict(caps)
         self.n_tiles_alloc = 0
         self._alloc()
@@ -209,18 +213,21 @@ class Renderer:
     def forward(self, tensors, params=None):
         cv, pr = self._structs(tensors, params)
         c = self.ctx
+        self.generation += 1
         c.check(c.lib.nsplat_forward(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c), ctypes.byref(pr),
                                      ctypes.byref(self.bufs), _ptr(self.image), _ptr(self.T), _ptr(self.n_last),
                                      int(self.persistent), _stream()))
         return self.image
 
-    def backward(self, tensors, dL: torch.Tensor, params=None, reg: "Reg" = None, grads=None):
+    def backward(self, tensors, dL: torch.Tensor, params=None, reg: "Reg" = None, grads=None, want=None):
         """Parameter gradients of the image loss (upstream dL) plus, with `reg`,
         the geometric regularisers (Eq. 11-12).  `grads` may pass preallocated
-        output tensors (e.g. for graph capture)."""
+        output tensors (e.g. for graph capture); `want` (six booleans, default
+        all) selects the groups to compute; a group not wanted is returned as
+        None and the library leaves it out."""
         cv, pr = self._structs(tensors, params)
         if grads is None:
-            grads = [torch.empty_like(t) for t in tensors]
+            grads = [torch.empty_like(t) if w else None for t, w in zip(tensors, want or (True,) * 6)]
         gc = L.Grads(*[_ptr(g) for g in grads])
         c = self.ctx
         dL = dL.contiguous()
@@ -302,7 +309,11 @@ class Renderer:
 
 class NSplatFunction(torch.autograd.Function):
     """image = render(key_xy, key_w, key_s, tau, color, opacity); the backward
-    runs the library's adjoint."""
+    runs the library's adjoint.  The adjoint reads the Renderer's state from
+    the forward that recorded this node, so the backward raises if the same
+    Renderer has run another forward since.  Inputs that need no gradient
+    (e.g. weights or knot intervals held fixed, the ablations of Table 1) get
+    None, and the library does not write them."""
 
     @staticmethod
     def forward(ctx, key_xy, key_w, key_s, tau, color, opacity, renderer: Renderer, frozen: bool, sync: bool):
@@ -310,11 +321,19 @@ class NSplatFunction(torch.autograd.Function):
         img = renderer.run_forward(tensors, frozen=frozen, sync=sync)
         ctx.renderer = renderer
         ctx.tensors = tensors
+        ctx.generation = renderer.generation
         return img.clone()
 
     @staticmethod
     def backward(ctx, grad_img):
-        grads = ctx.renderer.backward(ctx.tensors, grad_img)
+        r = ctx.renderer
+        if r.generation != ctx.generation:
+            raise RuntimeError("nsplat: this Renderer has run another forward since the one this backward belongs "
+                               "to; its state (Gaussians, tile lists, per-pixel state) no longer matches")
+        want = tuple(bool(x) for x in ctx.needs_input_grad[:6])
+        if not any(want):
+            return (None,) * 9
+        grads = r.backward(ctx.tensors, grad_img, want=want)
         return (*grads, None, None, None)
 
 

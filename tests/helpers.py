@@ -11,6 +11,19 @@ GRAD_ATOL = 1e-6
 PARAM_NAMES = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
 
 
+def oracle_plan(gpu_plan):
+    """The oracle's [N][8] plan layout (its last column the flags) from the
+    library's plan rows."""
+    from paper_2606_31764_amd import _lib as L
+    g = np.asarray(gpu_plan, np.int32)
+    return np.concatenate([g[:, :7], g[:, L.PLAN_FLAGS:L.PLAN_FLAGS + 1]], 1).astype(np.int32)
+
+
+def plans_equal(gpu_plan, oracle_rows):
+    """Counts, windows, offsets and flags of the library's plan equal the oracle's."""
+    np.testing.assert_array_equal(oracle_plan(gpu_plan), np.asarray(oracle_rows, np.int32))
+
+
 def oracle_params(p):
     """The oracle's parameter dict from a render.Params (FP32-rounded like the GPU sees them)."""
     d = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import IMG_TOL, grad_close, grad_report, gpu_run, oracle_params
+from helpers import IMG_TOL, grad_close, grad_report, gpu_run, oracle_params, oracle_plan, plans_equal
 from paper_2606_31764_amd import synth
 from paper_2606_31764_amd.render import Params
 
@@ -37,7 +37,7 @@ def _full_parity(b, p, target_seed=5):
     target = oracle.render(tb, op)[0]
     out = gpu_run(b, p, target=target)
     ref_g = oracle.gaussians(b, op)
-    np.testing.assert_array_equal(out["plan"][:, :7], ref_g["plan"][:, :7])
+    plans_equal(out["plan"], ref_g["plan"])
     img_ref, _, _ = oracle.render(b, op)
     assert np.abs(out["image"] - img_ref).max() <= IMG_TOL
     _, gref, _, _ = oracle.loss_and_grad(b, target, op)
@@ -189,7 +189,7 @@ def test_frozen_plan_keeps_counts():
     r.run_forward(t2, frozen=True)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(r.plan_np()[:, :7], plan0[:, :7])
-    ref = oracle.gaussians(b2, oracle_params(p), frozen_plan=plan0)
+    ref = oracle.gaussians(b2, oracle_params(p), frozen_plan=oracle_plan(plan0))
     g = r.gaussians()
     assert np.abs(g["mu"] - ref["mu"]).max() < 1e-9
     assert np.abs(g["opacity"] - ref["opacity"]).max() < 2e-7
@@ -372,3 +372,100 @@ def test_transmittance_threshold_range():
     assert one["T"].min() < 0.5  # and the curves do cover pixels
     with pytest.raises(NSplatError, match="eps_T"):
         gpu_run(b, Params().replace(delta_c=2.0, eps_T=1.5), backward=False)
+
+
+# ---------------------------------------------------------------------------------
+# values outside the domain of Sec. 3.1: the curve is skipped, the status says so
+# ---------------------------------------------------------------------------------
+
+_GOOD_A = [[3, 20], [9, 25], [14, 18], [22, 24], [28, 20]]
+_GOOD_B = [[4, 6], [10, 3], [17, 9], [24, 4], [30, 8]]
+_BAD_XY = [[5, 12], [10, 16], [15, 10], [20, 14], [25, 11]]
+BAD_VALUES = {
+    "zero_weight": dict(w=[1, 0, 1, 1, 1]),
+    "negative_weight": dict(w=[1, 1, -0.5, 1, 1]),
+    "zero_width": dict(s=[2, 2, 0, 2, 2]),
+    "negative_interval": dict(tau=[1.0, -0.25]),
+    "empty_domain": dict(tau=[0.0, 0.0]),
+    "nan_key": dict(xy=[[5, 12], [10, float("nan")], [15, 10], [20, 14], [25, 11]]),
+    "inf_weight": dict(w=[1, 1, float("inf"), 1, 1]),
+    "nan_opacity": dict(o=float("nan")),
+    "inf_colour": dict(color=(0.1, float("inf"), 0.3)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD_VALUES))
+def test_invalid_values_skip_the_curve(case):
+    kw = dict(BAD_VALUES[case])
+    xy = kw.pop("xy", _BAD_XY)
+    kw.setdefault("w", [1, 1.5, 0.8, 1, 1.2])
+    kw.setdefault("s", [2, 2.5, 3, 2, 2])
+    kw.setdefault("tau", [1.0, 0.7])
+    good_a = _part(_GOOD_A, seed=1)
+    good_b = _part(_GOOD_B, seed=2, color=(0.7, 0.1, 0.2))
+    bad = _part(xy, **kw)
+    p = Params(delta_c=1.5, tile=16)
+    with_bad = _batch([good_a, bad, good_b], hw=(32, 36))
+    without = _batch([good_a, good_b], hw=(32, 36))
+    target = oracle.render(synth.perturbed(without, seed=3), oracle_params(p))[0]
+    out = gpu_run(with_bad, p, target=target)
+    ref = gpu_run(without, p, target=target)
+    from paper_2606_31764_amd import _lib as L
+    assert out["counters"][L.CNT_STATUS] == L.STATUS_VALUE
+    assert out["plan"][1, 0] == 0 and out["plan"][1, L.PLAN_FLAGS] & L.PLAN_INVALID
+    assert not out["plan"][0, L.PLAN_FLAGS] & L.PLAN_INVALID and not out["plan"][2, L.PLAN_FLAGS] & L.PLAN_INVALID
+    plans_equal(out["plan"], oracle.plan(with_bad, oracle_params(p))[0])
+    np.testing.assert_array_equal(out["image"], ref["image"])  # bit for bit
+    for n in ("key_xy", "key_w", "key_s", "tau", "color", "opacity"):
+        assert np.all(np.isfinite(out["grads"][n])), n
+    k0, k1 = with_bad.key_off[1], with_bad.key_off[2]
+    assert np.all(out["grads"]["key_xy"][k0:k1] == 0) and np.all(out["grads"]["key_w"][k0:k1] == 0)
+    assert np.all(out["grads"]["tau"][with_bad.tau_off[1]:with_bad.tau_off[2]] == 0)
+    assert out["grads"]["opacity"][1] == 0 and np.all(out["grads"]["color"][1] == 0)
+    # the other curves' gradients are those of the batch without the bad curve
+    keep = np.r_[0:k0, k1:len(with_bad.key_w)]
+    np.testing.assert_allclose(out["grads"]["key_xy"][keep], ref["grads"]["key_xy"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(out["grads"]["opacity"][[0, 2]], ref["grads"]["opacity"], rtol=1e-5, atol=1e-6)
+
+
+def test_invalid_values_under_a_frozen_plan():
+    """A curve whose weight becomes 0 between two calls is skipped also when
+    the second call keeps the first call's plan."""
+    import torch
+    from paper_2606_31764_amd import _lib as L
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = _batch([_part(_GOOD_A, seed=1), _part(_BAD_XY, seed=4), _part(_GOOD_B, seed=2)], hw=(32, 36))
+    r = Renderer(b, Params(delta_c=1.5))
+    t = param_tensors(b)
+    r.run_forward(t)
+    assert r.read_counters()[L.CNT_STATUS] == 0 and r.plan_np()[1, 0] > 0
+    t[1][b.key_off[1] + 2] = 0.0
+    r.run_forward(t, frozen=True)
+    torch.cuda.synchronize()
+    cnt = r.read_counters()
+    plan = r.plan_np()
+    assert cnt[L.CNT_STATUS] == L.STATUS_VALUE and plan[1, 0] == 0 and plan[1, L.PLAN_FLAGS] & L.PLAN_INVALID
+    assert cnt[L.CNT_GAUSS] == plan[0, 0] + plan[2, 0]
+    assert np.all(np.isfinite(r.image.cpu().numpy()))
+
+
+def test_forward_and_backward_refuse_another_tile_than_bin():
+    """Tile lists are laid out for the tile side nsplat_bin used; a forward or
+    backward with another params.tile is an argument error, not wrong output."""
+    import torch
+    from paper_2606_31764_amd import _lib as L
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config2(seed=2801, n_curves=4, size=64)
+    p = Params(delta_c=3.0, tile=16)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    r.run_forward(t)
+    with pytest.raises(L.NSplatError, match="tile 16"):
+        r.forward(t, params=p.replace(tile=32))
+    dL = torch.ones_like(r.image)
+    with pytest.raises(L.NSplatError, match="tile 16"):
+        r.backward(t, dL, params=p.replace(tile=8))
+    r.bin(t, params=p.replace(tile=32))
+    r.forward(t, params=p.replace(tile=32))  # consistent again
+    r.backward(t, dL, params=p.replace(tile=32))
+    torch.cuda.synchronize()

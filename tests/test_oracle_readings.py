@@ -151,3 +151,61 @@ def test_six_sigma_gradient_gap(name):
         scale = np.abs(g0[n]).max()
         gap = np.abs(g6[n] - g0[n]).max()
         assert gap <= 2e-5 * scale, (n, gap, scale)
+
+
+# ---------------------------------------------------------------------------------
+# value domain of Sec. 3.1 and the count flag of Sec. 3.2
+# ---------------------------------------------------------------------------------
+
+def _stroke(xy, w=None, s=None, tau=None, p=3):
+    nk = len(xy)
+    return dict(scene=0, degree=p, flags=0, key_xy=np.asarray(xy, float),
+                key_w=np.ones(nk) if w is None else np.asarray(w, float),
+                key_s=np.full(nk, 2.0) if s is None else np.asarray(s, float),
+                tau=np.ones(nk - p) if tau is None else np.asarray(tau, float), color=(0.1, 0.2, 0.3), opacity=0.9)
+
+
+BAD = {
+    "zero_weight": dict(w=[1, 0, 1, 1, 1]),
+    "negative_weight": dict(w=[1, 1, -0.5, 1, 1]),
+    "zero_width": dict(s=[2, 2, 0, 2, 2]),
+    "negative_interval": dict(tau=[1.0, -0.25]),
+    "empty_domain": dict(tau=[0.0, 0.0]),
+    "nan_key": dict(xy=[[5, 5], [10, float("nan")], [15, 8], [20, 5], [25, 9]]),
+    "inf_weight": dict(w=[1, 1, float("inf"), 1, 1]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD))
+def test_values_outside_the_domain_render_nothing(case):
+    """w_i > 0, tau_j >= 0 with a positive sum, widths > 0, finite inputs
+    (Sec. 3.1): a curve outside that domain gets no Gaussians and flag 2."""
+    kw = dict(BAD[case])
+    xy = kw.pop("xy", [[5, 5], [10, 12], [15, 8], [20, 5], [25, 9]])
+    good = _stroke([[3, 20], [9, 25], [14, 18], [22, 24], [28, 20]])
+    bad = _stroke(xy, **kw)
+    b = synth._assemble([good, bad, good], [[32, 32]], [[1.0, 1.0, 1.0]], 3)
+    pl, L, G = oracle.plan(b, dict(delta_c=1.0))
+    assert pl[1, oracle.P_COUNT] == 0 and pl[1, oracle.P_NSAMP] == 0
+    assert pl[1, oracle.P_FLAG] & oracle.FLAG_INVALID
+    assert not (pl[0, oracle.P_FLAG] & oracle.FLAG_INVALID) and pl[0, oracle.P_COUNT] > 0
+    assert G == pl[0, oracle.P_COUNT] + pl[2, oracle.P_COUNT]
+    img, _, _ = oracle.render(b, dict(delta_c=1.0))
+    ref, _, _ = oracle.render(synth._assemble([good, good], [[32, 32]], [[1.0, 1.0, 1.0]], 3), dict(delta_c=1.0))
+    np.testing.assert_array_equal(img, ref)
+
+
+def test_count_flag_marks_an_integral_delta_L():
+    """A straight degree-1 segment of length 10 has L = 10 exactly (C' is
+    constant, the midpoint rule exact up to rounding); delta_c = 1 puts delta L
+    on an integer and the plan flags it, delta_c = 1.05 does not."""
+    seg = dict(scene=0, degree=1, flags=0, key_xy=np.array([[3.0, 4.0], [13.0, 4.0]]), key_w=np.ones(2),
+               key_s=np.full(2, 2.0), tau=np.array([1.0]), color=(0.0, 0.0, 0.0), opacity=1.0)
+    b = synth._assemble([seg], [[16, 16]], [[1.0, 1.0, 1.0]], 3)
+    pl, L, _ = oracle.plan(b, dict(delta_c=1.0, kappa=0))
+    assert abs(L[0] - 10.0) < 1e-12
+    # ceil(delta L) is 10 or 11 depending on the last bit of the quadrature sum:
+    # exactly the ambiguity the flag reports
+    assert pl[0, oracle.P_FLAG] == oracle.FLAG_NEAR_INT and pl[0, oracle.P_NSAMP] in (10, 11)
+    pl, _, _ = oracle.plan(b, dict(delta_c=1.05, kappa=0))
+    assert pl[0, oracle.P_FLAG] == 0 and pl[0, oracle.P_NSAMP] == 11
