@@ -105,6 +105,11 @@ def load():
     """Loads the in-tree libnsplat.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch first: it loads the HIP runtime it ships, and the library's
+        # libamdhip64.so.7 then binds to that same copy.  Loaded the other way
+        # round, torch pulls in a second runtime beside the system one and the
+        # two do not see each other's devices.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libnsplat.so is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
         lib = ctypes.CDLL(LIB_PATH)
