@@ -323,6 +323,21 @@ int nsplat_udf_loss(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_s
                     const nsplat_params* params, const nsplat_buffers* bufs, const int32_t* sel, float tau,
                     const float* image, const float* target, float* dL_dimage, float* loss, void* stream);
 
+/* nsplat_udf_loss for callers that cannot allocate device memory or bring
+ * scratch of their own (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same arguments, results and errors,
+ * but the per-scene weight sums live in a static device array of the library
+ * (4096 doubles per device, held until the process ends) instead of the
+ * workspace, and the call allocates nothing.  At most 4095 scenes
+ * (NSPLAT_EINVAL above).  All calls on one device share that array, which
+ * keeps the last call's sums (each call clears what it uses first): calls that
+ * overlap on one device (different streams, or threads) race and give wrong
+ * results.  The workspace in bufs is still read for the render state of this
+ * step's nsplat_sample (boundary points, scene table). */
+int nsplat_udf_loss_noalloc(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                            const nsplat_params* params, const nsplat_buffers* bufs, const int32_t* sel, float tau,
+                            const float* image, const float* target, float* dL_dimage, float* loss, void* stream);
+
 /* Learnable parameters, writable (dev FP32; the arrays the curves point to). */
 typedef struct {
   int32_t n_curves, channels, n_keys, n_taus;

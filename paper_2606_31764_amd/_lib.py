@@ -85,6 +85,7 @@ _SIGS = {
     "nsplat_backward_reg": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
     "nsplat_adam_step": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "nsplat_udf_loss": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]),
+    "nsplat_udf_loss_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]),
     "nsplat_anneal_h": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, vp]),
     "nsplat_l2_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, vp]),

@@ -294,7 +294,18 @@ int nsplat_create(nsplat_ctx** out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
+  // the device address of nsplat_udf_loss_noalloc's static scratch, taken
+  // once per device with that device current
+  int prev = 0;
+  hipError_t h = hipGetDevice(&prev);
+  if (h == hipSuccess) h = hipSetDevice(device);
+  if (h == hipSuccess) {
+    h = udf_scratch_setup(device);
+    const hipError_t r = hipSetDevice(prev);
+    if (h == hipSuccess) h = r;
+  }
   *out = c;
+  if (h != hipSuccess) return hip_fail(c, h, "nsplat_create: device scratch");
   return NSPLAT_OK;
 }
 
@@ -396,6 +407,24 @@ int nsplat_udf_loss(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scene
   if (!(tau > 0.0f)) return fail(ctx, NSPLAT_EINVAL, "tau must be positive (got %g)", (double)tau);
   hipError_t h = launch_udf(L, sel, tau, image, target, dL, loss);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_udf_loss");
+  return NSPLAT_OK;
+}
+
+int nsplat_udf_loss_noalloc(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc,
+                            const nsplat_params* pr, const nsplat_buffers* bf, const int32_t* sel, float tau,
+                            const float* image, const float* target, float* dL, float* loss, void* stream) {
+  Launch L;
+  int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
+  if (e) return e;
+  if (!image || !target || !dL) return fail(ctx, NSPLAT_EINVAL, "image / target / dL_dimage is NULL");
+  if (!(tau > 0.0f)) return fail(ctx, NSPLAT_EINVAL, "tau must be positive (got %g)", (double)tau);
+  if (sc->n_scenes > UDF_SCRATCH_SLOTS - 1)
+    return fail(ctx, NSPLAT_EINVAL, "nsplat_udf_loss_noalloc takes at most %d scenes (got %d)",
+                UDF_SCRATCH_SLOTS - 1, sc->n_scenes);
+  double* sacc = udf_scratch(ctx->device);
+  if (!sacc) return fail(ctx, NSPLAT_EHIP, "nsplat_udf_loss_noalloc: device scratch was not set up");
+  hipError_t h = launch_udf(L, sel, tau, image, target, dL, loss, sacc);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_udf_loss_noalloc");
   return NSPLAT_OK;
 }
 

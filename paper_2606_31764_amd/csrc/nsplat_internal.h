@@ -351,6 +351,14 @@ struct Launch {
 
 // Scene table; also clears the NSPLAT_NUM_COUNTERS counters when given.
 hipError_t launch_scene_setup(const Launch& L, int32_t* clear_counters);
+// nsplat_udf_loss_noalloc's device scratch: UDF_SCRATCH_SLOTS doubles per
+// device (per-scene sums, so at most UDF_SCRATCH_SLOTS - 1 scenes), its
+// address taken once per device (with that device current) by
+// udf_scratch_setup and read back by udf_scratch (nullptr before the setup).
+constexpr int UDF_SCRATCH_SLOTS = 4096;
+constexpr int MAX_DEVICES = 64;
+hipError_t udf_scratch_setup(int device);
+double* udf_scratch(int device);
 hipError_t launch_sample(const Launch& L, int frozen);
 hipError_t launch_bin(const Launch& L);
 hipError_t launch_blend_fwd(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent);
@@ -359,7 +367,7 @@ hipError_t launch_blend_bwd(const Launch& L, const float* dL, const float* T_fin
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g);
 hipError_t launch_reg(const Launch& L, const nsplat_reg* reg);
 hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const float* image, const float* target,
-                      float* dL, float* loss);
+                      float* dL, float* loss, double* sacc = nullptr);
 hipError_t launch_adam(const nsplat_adam* cfg, const nsplat_values* prm, const nsplat_grads* g, float* m, float* v,
                        int32_t* step_dev, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

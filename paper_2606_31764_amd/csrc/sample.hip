@@ -12,6 +12,8 @@
 //   k_emit          one lane per Gaussian: span search and span-local
 //                   Cox-de Boor evaluation (Eq. 4-5), or the fill lattice
 //                   point with its SDF opacity (Eq. 6-7, S1-S3)
+#include <mutex>
+
 #include "nsplat_internal.h"
 
 namespace nsp {
@@ -844,11 +846,12 @@ __global__ __launch_bounds__(256) void k_udf_grad(Work w, int n_scenes, int C, c
 }  // namespace
 
 hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const float* image, const float* target,
-                      float* dL, float* loss) {
+                      float* dL, float* loss, double* sacc) {
   const int S = L.sc->n_scenes, C = L.cv->channels;
   int64_t npix = 0;
   for (int s = 0; s < S; ++s) npix += (int64_t)L.sc->hw_host[2 * s] * L.sc->hw_host[2 * s + 1];
-  const Work& w = L.w;
+  Work w = L.w;
+  if (sacc) w.sacc = sacc;  // per-scene weight sums somewhere else than the workspace
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, L.stream, w.sacc, 0.0, (int64_t)(S + 1));
   if (npix <= 0) return hipGetLastError();
   hipLaunchKernelGGL(k_udf_weight, dim3(grid_for(npix, 256, 8192)), dim3(256), 0, L.stream, *L.cv, w,
@@ -856,6 +859,36 @@ hipError_t launch_udf(const Launch& L, const int32_t* sel, float tau, const floa
   hipLaunchKernelGGL(k_udf_grad, dim3(grid_for(npix, 256, 2048)), dim3(256), 0, L.stream, w, S, C, image, target,
                      dL, loss);
   return hipGetLastError();
+}
+
+// Device scratch of nsplat_udf_loss_noalloc: the per-scene weight sums live
+// in this file-scope array instead of the caller's workspace, so that entry
+// point needs no memory of its own.  Each device holds its own copy for the
+// life of the process; host code must use the address udf_scratch_setup took
+// with hipGetSymbolAddress on that device, never the array's name (which on
+// the host only stands in for the symbol).
+static __device__ __align__(256) double scratch[UDF_SCRATCH_SLOTS];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t udf_scratch_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+double* udf_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (double*)g_scratch_ptr[device];
 }
 
 hipError_t launch_scene_setup(const Launch& L, int32_t* clear_counters) {

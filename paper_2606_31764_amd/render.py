@@ -244,15 +244,17 @@ class Renderer:
         return grads
 
     def udf_loss(self, tensors, image: torch.Tensor, target: torch.Tensor, tau: float, sel=None, loss=None,
-                 params=None, out=None):
+                 params=None, out=None, noalloc=False):
         """dL/dImage of the distance-weighted image loss (LIVE's unsigned-distance
         weights around the selected filled curves; sel: device int32 [n_curves] or
         None for every filled curve) for this step's boundaries; the loss value
-        is added to `loss` (device [1]) when given."""
+        is added to `loss` (device [1]) when given.  noalloc selects
+        nsplat_udf_loss_noalloc (scratch in the library's static device array)."""
         cv, pr = self._structs(tensors, params)
         dL = torch.empty_like(image) if out is None else out
         c = self.ctx
-        c.check(c.lib.nsplat_udf_loss(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c), ctypes.byref(pr),
+        fn = c.lib.nsplat_udf_loss_noalloc if noalloc else c.lib.nsplat_udf_loss
+        c.check(fn(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c), ctypes.byref(pr),
                                       ctypes.byref(self.bufs), _ptr(sel), float(tau), _ptr(image.contiguous()),
                                       _ptr(target.contiguous()), _ptr(dL), _ptr(loss), _stream()))
         return dL
