@@ -447,7 +447,15 @@ def bench_optim(args):
     caps = dict(gauss=2 * cnt[3] + 1024, pairs=2 * cnt[4] + 4096, boundary=2 * cnt[5] + 64)
     t = [x.clone() for x in t0]
     r = Renderer(b, p, caps=caps, ctx=ctx)
-    opt = Adam(t, lr=(1.5, 0.1, 0.2, 0.1, 0.01, 0.01), total_steps=150, ctx=ctx)
+    # Adam moves each parameter by about its learning rate per step, so the
+    # rates follow this workload's scales: the calligraphy rates of the
+    # supplement (intervals 0.1, widths 0.2) are for a few dozen normalised
+    # intervals, while these curves have 1997 intervals of ~5e-4 each, and
+    # would leave the value domain (tau < 0 is clamped, widths <= 0 are
+    # invalid) within a few steps
+    med_tau = float(np.median(b.tau))
+    lrs = (0.5, 0.01, 0.02, 0.02 * med_tau, 0.01, 0.01)
+    opt = Adam(t, lr=lrs, total_steps=150, ctx=ctx)
     dL = torch.empty_like(target)
     grads = [torch.empty_like(x) for x in t]
     losses = torch.zeros(3, device="cuda")
@@ -494,7 +502,11 @@ def bench_optim(args):
                         "loss (r = 3) + bounding-box loss, Adam", gaussians=int(cnt[0]), pairs=int(cnt[1]),
                status=int(cnt[2]), ms_per_step=ms, gaussians_per_s=cnt[0] / (ms * 1e-3),
                loss_l2_bbox_deriv=lv, phases_ms={k: v[0] for k, v in ph.items()})
+    res["learning_rates"] = list(lrs)
     log("optim step: %d Gaussians, %.3f ms/step (reg %.3f ms), status %d" % (cnt[0], ms, ph["reg"][0], cnt[2]))
+    # a step whose curves left the value domain renders nothing and times no work
+    if cnt[2] != 0 or cnt[0] == 0:
+        raise RuntimeError("optimisation step degenerated: status %d, %d Gaussians" % (cnt[2], cnt[0]))
     return res
 
 

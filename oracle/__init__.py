@@ -80,9 +80,10 @@ def lib():
             "or_plan": (i64, [vp, vp, vp, vp, vp]),
             "or_gaussians": (i64, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "or_bin": (i64, [i64, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, i64]),
-            "or_composite": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp]),
+            "or_composite": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp]),
             "or_param_grad_seeds": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
-            "or_param_grad_full": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "or_param_grad_seeds_scaled": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]),
+            "or_param_grad_full": (i32, [vp] * 18),
             "or_curve_knots": (i32, [i32, i32, i32, i32, vp, vp]),
             "or_curve_eval": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, i32, vp]),
             "or_basis_all": (i32, [i32, i32, vp, dbl, vp, vp]),
@@ -199,12 +200,14 @@ def _image_layout(batch):
     return C, n_img, n_t
 
 
-def composite(batch, g, params=None, pixels=None, upstream=None):
+def composite(batch, g, params=None, pixels=None, upstream=None, with_abs=False):
     """Eq. 8-9 by brute force.  pixels None: full images, returned flat
     (per scene [C][H][W] concatenated) with T_final flat ([H][W] per scene).
     pixels [n,3] (scene, y, x): values [n, C] and T [n].  With upstream (same
     layout as the image) also returns adj [G, 7]: the gradient of
-    sum(upstream * I) w.r.t. (mx, my, sigma, opacity, colour[0..2]) per Gaussian."""
+    sum(upstream * I) w.r.t. (mx, my, sigma, opacity, colour[0..2]) per Gaussian,
+    and with with_abs adjabs [G, 7]: the same sums taken over the absolute
+    values of every term (the scale of any evaluation's rounding error)."""
     B = _Batch(batch, params)
     C, n_img, n_t = _image_layout(batch)
     G = len(g["sigma"])
@@ -220,34 +223,50 @@ def composite(batch, g, params=None, pixels=None, upstream=None):
         img = np.zeros((npix, C)); T = np.zeros(npix)
     up = None if upstream is None else np.ascontiguousarray(upstream, np.float64)
     adj = np.zeros((G, 7)) if up is not None else None
+    adjabs = np.zeros((G, 7)) if (up is not None and with_abs) else None
     lib().or_composite(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)), _p(mu), _p(sg), _p(op), _p(cv),
-                       G, npix, _p(pix), _p(img), _p(T), _p(up), _p(adj))
+                       G, npix, _p(pix), _p(img), _p(T), _p(up), _p(adj), _p(adjabs))
     if up is None:
         return img, T
+    if with_abs:
+        return img, T, adj, adjabs
     return img, T, adj
 
 
-def param_grad(batch, g, adj, params=None):
-    """Gradient of the loss w.r.t. every curve parameter, given per-Gaussian adjoints."""
+def param_grad(batch, g, adj, params=None, adjabs=None):
+    """Gradient of the loss w.r.t. every curve parameter, given per-Gaussian
+    adjoints.  With adjabs (composite(..., with_abs=True)) also returns the
+    error scale of every component: sum_g adjabs_g . |d gaussian_g / d theta|."""
     B = _Batch(batch, params)
     k = B.keep
-    out = dict(key_xy=np.zeros_like(k["key_xy"]), key_w=np.zeros_like(k["key_w"]),
-               key_s=np.zeros_like(k["key_s"]), tau=np.zeros_like(k["tau"]),
-               color=np.zeros_like(k["color"]), opacity=np.zeros_like(k["opacity"]))
+    names = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+    out = {n: np.zeros_like(k[n]) for n in names}
+    scl = {n: np.zeros_like(k[n]) for n in names} if adjabs is not None else None
+    ab = None if adjabs is None else np.ascontiguousarray(adjabs, np.float64)
     lib().or_param_grad_full(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
-                             _p(np.ascontiguousarray(adj, np.float64)),
-                             *[_p(out[n]) for n in ("key_xy", "key_w", "key_s", "tau", "color", "opacity")])
-    return out
+                             _p(np.ascontiguousarray(adj, np.float64)), *[_p(out[n]) for n in names], _p(ab),
+                             *[(_p(scl[n]) if scl is not None else None) for n in names])
+    if adjabs is None:
+        return out
+    return out, scl
 
 
-def param_grad_seeds(batch, g, adj, seeds, params=None):
-    """Selected gradient components; seeds [n, 3] = (curve, kind, local index)."""
+def param_grad_seeds(batch, g, adj, seeds, params=None, adjabs=None):
+    """Selected gradient components; seeds [n, 3] = (curve, kind, local index).
+    With adjabs also returns their error scales (see param_grad)."""
     B = _Batch(batch, params)
     sd = np.ascontiguousarray(seeds, np.int32).reshape(-1, 3)
     out = np.zeros(len(sd))
-    lib().or_param_grad_seeds(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
-                              _p(np.ascontiguousarray(adj, np.float64)), len(sd), _p(sd), _p(out))
-    return out
+    if adjabs is None:
+        lib().or_param_grad_seeds(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
+                                  _p(np.ascontiguousarray(adj, np.float64)), len(sd), _p(sd), _p(out))
+        return out
+    scale = np.zeros(len(sd))
+    lib().or_param_grad_seeds_scaled(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)),
+                                     _p(np.ascontiguousarray(adj, np.float64)),
+                                     _p(np.ascontiguousarray(adjabs, np.float64)), len(sd), _p(sd), _p(out),
+                                     _p(scale))
+    return out, scale
 
 
 def render(batch, params=None, frozen_plan=None):
@@ -256,11 +275,15 @@ def render(batch, params=None, frozen_plan=None):
     return img, T, g
 
 
-def loss_and_grad(batch, target, params=None, frozen_plan=None):
-    """L = sum (I - I*)^2 and its gradient w.r.t. every curve parameter (FP64)."""
+def loss_and_grad(batch, target, params=None, frozen_plan=None, with_scale=False):
+    """L = sum (I - I*)^2 and its gradient w.r.t. every curve parameter (FP64).
+    with_scale: the gradient is a pair (values, error scales), see param_grad."""
     g = gaussians(batch, params, frozen_plan)
     img, T = composite(batch, g, params)
     up = 2.0 * (img - target)
+    if with_scale:
+        _, _, adj, adjabs = composite(batch, g, params, upstream=up, with_abs=True)
+        return float(np.sum((img - target) ** 2)), param_grad(batch, g, adj, params, adjabs), g, img
     _, _, adj = composite(batch, g, params, upstream=up)
     return float(np.sum((img - target) ** 2)), param_grad(batch, g, adj, params), g, img
 

@@ -479,7 +479,7 @@ struct Hit { int64_t g; double a, G, dx, dy, d2, T; };
 void composite_pixel(const or_curves* in, const or_params* pr, int C, const double* bg,
                      const double* mx, const double* my, const double* sg, const double* op,
                      const int32_t* gcurve, int64_t g0, int64_t g1, double px, double py,
-                     double* img, double* Tout, const double* up, double* adj) {
+                     double* img, double* Tout, const double* up, double* adj, double* adjabs) {
   std::vector<Hit> hits;
   double T = 1.0;
   double acc[3] = {0, 0, 0};
@@ -507,10 +507,14 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
   for (int h = (int)hits.size() - 1; h >= 0; --h) {
     const Hit& e = hits[h];
     const double* col = in->color + (size_t)C * gcurve[e.g];
-    double dLda = 0.0;
+    double dLda = 0.0, sabs = 0.0;
     for (int k = 0; k < C; ++k) {
       dLda += up[k] * (col[k] * e.T - R[k] / (1.0 - e.a));
       adj[7 * e.g + 4 + k] += up[k] * e.a * e.T;
+      // the magnitude of the terms dL/dalpha is formed from: the scale of
+      // its rounding error in any evaluation order
+      sabs += std::fabs(up[k]) * (std::fabs(col[k]) * e.T + std::fabs(R[k]) / (1.0 - e.a));
+      if (adjabs) adjabs[7 * e.g + 4 + k] += std::fabs(up[k]) * e.a * e.T;
     }
     for (int k = 0; k < C; ++k) R[k] += col[k] * e.a * e.T;
     if (op[e.g] * e.G < pr->alpha_max) {          // clamp inactive
@@ -520,6 +524,13 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
       adj[7 * e.g + 0] += dLdG * e.G * e.dx / (s * s);   // dG/dmx = G (x - mx) / s^2
       adj[7 * e.g + 1] += dLdG * e.G * e.dy / (s * s);
       adj[7 * e.g + 2] += dLdG * e.G * e.d2 / (s * s * s);
+      if (adjabs) {
+        const double sG = sabs * op[e.g] * e.G;
+        adjabs[7 * e.g + 3] += sabs * e.G;
+        adjabs[7 * e.g + 0] += sG * std::fabs(e.dx) / (s * s);
+        adjabs[7 * e.g + 1] += sG * std::fabs(e.dy) / (s * s);
+        adjabs[7 * e.g + 2] += sG * e.d2 / (s * s * s);
+      }
     }
   }
 }
@@ -762,7 +773,7 @@ int64_t or_bin(int64_t G, const double* mu, const double* sigma, const int32_t* 
 int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
                  const double* mu, const double* sigma, const double* opacity, const int32_t* gcurve,
                  int64_t G, int64_t npix, const int32_t* pix, double* img, double* Tfin,
-                 const double* up, double* adj) {
+                 const double* up, double* adj, double* adjabs) {
   const int C = in->channels;
   const std::vector<int64_t> sr = scene_ranges(in, plan, sc->n_scenes);
   std::vector<double> mx(G), my(G);
@@ -794,8 +805,9 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
     nthreads = omp_get_num_threads();
   }
 #endif
-  std::vector<std::vector<double>> adj_t;
+  std::vector<std::vector<double>> adj_t, abs_t;
   if (up) adj_t.assign(nthreads, std::vector<double>());
+  if (up && adjabs) abs_t.assign(nthreads, std::vector<double>());
 #pragma omp parallel
   {
     int tid = 0;
@@ -803,7 +815,9 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
     tid = omp_get_thread_num();
 #endif
     double* my_adj = nullptr;
+    double* my_abs = nullptr;
     if (up) { adj_t[tid].assign((size_t)7 * G, 0.0); my_adj = adj_t[tid].data(); }
+    if (up && adjabs) { abs_t[tid].assign((size_t)7 * G, 0.0); my_abs = abs_t[tid].data(); }
 #pragma omp for schedule(dynamic, 16)
     for (int64_t q = 0; q < npix; ++q) {
       const int s = pix[3 * q], y = pix[3 * q + 1], x = pix[3 * q + 2];
@@ -815,7 +829,7 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
           u[k] = full ? up[img_off[q] + (int64_t)k * H * W] : up[(int64_t)C * q + k];
       }
       composite_pixel(in, pr, C, sc->bg + (size_t)C * s, mx.data(), my.data(), sigma, opacity, gcurve,
-                      sr[2 * s], sr[2 * s + 1], x + 0.5, y + 0.5, v, &T, up ? u : nullptr, my_adj);
+                      sr[2 * s], sr[2 * s + 1], x + 0.5, y + 0.5, v, &T, up ? u : nullptr, my_adj, my_abs);
       for (int k = 0; k < C; ++k) {
         if (full) img[img_off[q] + (int64_t)k * H * W] = v[k];
         else img[(int64_t)C * q + k] = v[k];
@@ -825,9 +839,13 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
   }
   if (up) {
     for (int64_t i = 0; i < 7 * G; ++i) {
-      double s = 0.0;
+      double s = 0.0, a = 0.0;
       for (int t = 0; t < nthreads; ++t) s += adj_t[t][i];
       adj[i] = s;
+      if (adjabs) {
+        for (int t = 0; t < nthreads; ++t) a += abs_t[t][i];
+        adjabs[i] = a;
+      }
     }
   }
   return 0;
@@ -838,13 +856,21 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
 // derivative taken by forward-mode dual numbers over the frozen plan.
 // kind: 1 key x, 2 key y, 3 key weight, 4 key width, 5 tau, 6 opacity,
 // 7 + ch: colour channel ch.  index is local to the curve.
+// With adjabs (the per-Gaussian sums of absolute terms from or_composite),
+// *scale receives sum_g adjabs_g . |d(gaussian_g)/d(theta)|: the magnitude of
+// the terms the gradient sums, which bounds the rounding error of any
+// evaluation of it relative to FP32's unit roundoff.
 static double param_grad_one(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
-                             const double* adj, int c, int kind, int index) {
+                             const double* adj, const double* adjabs, int c, int kind, int index, double* scale) {
   const int32_t* row = plan + P_STRIDE * c;
   const int64_t g0 = row[P_GOFF];
   if (kind >= 7) {
-    double s = 0.0;
-    for (int j = 0; j < row[P_COUNT]; ++j) s += adj[7 * (g0 + j) + 4 + (kind - 7)];
+    double s = 0.0, sa = 0.0;
+    for (int j = 0; j < row[P_COUNT]; ++j) {
+      s += adj[7 * (g0 + j) + 4 + (kind - 7)];
+      if (adjabs) sa += adjabs[7 * (g0 + j) + 4 + (kind - 7)];
+    }
+    if (scale) *scale = sa;
     return s;
   }
   std::vector<char> need(row[P_COUNT]);
@@ -854,47 +880,77 @@ static double param_grad_one(const or_curves* in, const or_scenes* sc, const or_
   }
   std::vector<Gauss<Dual>> gs;
   curve_gaussians<Dual>(in, sc, pr, c, row, kind, index, gs, &need);
-  double s = 0.0;
+  double s = 0.0, sa = 0.0;
   for (size_t j = 0; j < gs.size(); ++j) {
     const double* a = adj + 7 * (g0 + j);
     s += a[0] * gs[j].mx.d + a[1] * gs[j].my.d + a[2] * gs[j].sigma.d + a[3] * gs[j].opacity.d;
+    if (adjabs) {
+      const double* b = adjabs + 7 * (g0 + j);
+      sa += b[0] * std::fabs(gs[j].mx.d) + b[1] * std::fabs(gs[j].my.d) + b[2] * std::fabs(gs[j].sigma.d) +
+            b[3] * std::fabs(gs[j].opacity.d);
+    }
   }
+  if (scale) *scale = sa;
   return s;
 }
 
-// Selected gradient components: seeds [n][3] = (curve, kind, index).
+// Selected gradient components: seeds [n][3] = (curve, kind, index); with
+// adjabs also their error scales (see param_grad_one) into scale [n].
 int or_param_grad_seeds(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
                         const double* adj, int64_t n, const int32_t* seeds, double* out) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t i = 0; i < n; ++i)
-    out[i] = param_grad_one(in, sc, pr, plan, adj, seeds[3 * i], seeds[3 * i + 1], seeds[3 * i + 2]);
+    out[i] = param_grad_one(in, sc, pr, plan, adj, nullptr, seeds[3 * i], seeds[3 * i + 1], seeds[3 * i + 2],
+                            nullptr);
+  return 0;
+}
+
+int or_param_grad_seeds_scaled(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
+                               const double* adj, const double* adjabs, int64_t n, const int32_t* seeds, double* out,
+                               double* scale) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = param_grad_one(in, sc, pr, plan, adj, adjabs, seeds[3 * i], seeds[3 * i + 1], seeds[3 * i + 2],
+                            scale + i);
   return 0;
 }
 
 // Every gradient component, written in the layout of the inputs.
 int or_param_grad_full(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
                        const double* adj, double* g_key_xy, double* g_key_w, double* g_key_s, double* g_tau,
-                       double* g_color, double* g_opacity) {
+                       double* g_color, double* g_opacity, const double* adjabs, double* s_key_xy, double* s_key_w,
+                       double* s_key_s, double* s_tau, double* s_color, double* s_opacity) {
   const int N = in->n_curves, C = in->channels;
   std::vector<int32_t> seeds;
-  std::vector<double*> dst;
+  std::vector<int64_t> off;   // offset of each seed's output in its group
+  std::vector<int> grp;       // group: 0 key_xy, 1 key_w, 2 key_s, 3 tau, 4 color, 5 opacity
+  auto add = [&](int c, int kind, int idx, int g, int64_t o) {
+    seeds.insert(seeds.end(), {c, kind, idx});
+    grp.push_back(g);
+    off.push_back(o);
+  };
   for (int c = 0; c < N; ++c) {
     const int k0 = in->key_off[c], nk = in->key_off[c + 1] - k0;
     const int t0 = in->tau_off[c], nt = in->tau_off[c + 1] - t0;
     for (int k = 0; k < nk; ++k) {
-      seeds.insert(seeds.end(), {c, S_KEY_X, k}); dst.push_back(g_key_xy + 2 * (k0 + k));
-      seeds.insert(seeds.end(), {c, S_KEY_Y, k}); dst.push_back(g_key_xy + 2 * (k0 + k) + 1);
-      seeds.insert(seeds.end(), {c, S_KEY_W, k}); dst.push_back(g_key_w + k0 + k);
-      seeds.insert(seeds.end(), {c, S_KEY_S, k}); dst.push_back(g_key_s + k0 + k);
+      add(c, S_KEY_X, k, 0, 2 * (k0 + k));
+      add(c, S_KEY_Y, k, 0, 2 * (k0 + k) + 1);
+      add(c, S_KEY_W, k, 1, k0 + k);
+      add(c, S_KEY_S, k, 2, k0 + k);
     }
-    for (int t = 0; t < nt; ++t) { seeds.insert(seeds.end(), {c, S_TAU, t}); dst.push_back(g_tau + t0 + t); }
-    seeds.insert(seeds.end(), {c, S_OPACITY, 0}); dst.push_back(g_opacity + c);
-    for (int ch = 0; ch < C; ++ch) { seeds.insert(seeds.end(), {c, 7 + ch, 0}); dst.push_back(g_color + C * c + ch); }
+    for (int t = 0; t < nt; ++t) add(c, S_TAU, t, 3, t0 + t);
+    add(c, S_OPACITY, 0, 5, c);
+    for (int ch = 0; ch < C; ++ch) add(c, 7 + ch, 0, 4, C * c + ch);
   }
-  const int64_t n = (int64_t)dst.size();
-  std::vector<double> out(n);
-  or_param_grad_seeds(in, sc, pr, plan, adj, n, seeds.data(), out.data());
-  for (int64_t i = 0; i < n; ++i) *dst[i] = out[i];
+  const int64_t n = (int64_t)grp.size();
+  std::vector<double> out(n), sc_out(n);
+  or_param_grad_seeds_scaled(in, sc, pr, plan, adj, adjabs, n, seeds.data(), out.data(), sc_out.data());
+  double* gdst[6] = {g_key_xy, g_key_w, g_key_s, g_tau, g_color, g_opacity};
+  double* sdst[6] = {s_key_xy, s_key_w, s_key_s, s_tau, s_color, s_opacity};
+  for (int64_t i = 0; i < n; ++i) {
+    gdst[grp[i]][off[i]] = out[i];
+    if (adjabs && sdst[grp[i]]) sdst[grp[i]][off[i]] = sc_out[i];
+  }
   return 0;
 }
 

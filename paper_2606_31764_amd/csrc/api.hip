@@ -34,8 +34,6 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   const int64_t gcap = caps->gauss, pcap = caps->pairs, bcap = caps->boundary;
   lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
   const int64_t tiles8 = nsplat_num_tiles(sc, 8);
-  int64_t n_pix = 0;
-  for (int s = 0; s < sc->n_scenes; ++s) n_pix += (int64_t)sc->hw_host[2 * s] * sc->hw_host[2 * s + 1];
   const int64_t scan_n = std::max<int64_t>({gcap, (int64_t)RADIX_MAX * lay.sort_blocks, tiles8 + 1, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
   const size_t sizes[N_WS] = {
@@ -64,7 +62,6 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(int32_t) * (size_t)(tiles8 + 1),              // ck_off
       sizeof(int32_t) * (size_t)(tiles8 + 1),              // item_off
       sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
-      sizeof(float) * 3 * (size_t)std::max<int64_t>(n_pix, 1),  // afin
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
       sizeof(double) * SEG_WORDS * (size_t)(bcap + (SDF_CHUNK - 1) * N + 1),  // segs
   };
@@ -105,9 +102,8 @@ Work carve(void* ws, const Layout& lay) {
   w.ck_off = (int32_t*)(b + lay.off[22]);
   w.item_off = (int32_t*)(b + lay.off[23]);
   w.ckbuf = (float*)(b + lay.off[24]);
-  w.afin = (float*)(b + lay.off[25]);
-  w.gcol = (float4*)(b + lay.off[26]);
-  w.segs = (double*)(b + lay.off[27]);
+  w.gcol = (float4*)(b + lay.off[25]);
+  w.segs = (double*)(b + lay.off[26]);
   return w;
 }
 

@@ -191,6 +191,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     // front to back: list positions end-1 down to start, at most `depth` per
     // step and never across a chunk boundary, where the state is stored
     const int ck0 = w.ck_off[tile];
+    int n_ck = 0;  // chunk boundaries passed (state stored)
     // loads run two steps ahead for the list indices and one step ahead for
     // the records, so a step waits for one round trip, issued a step earlier
     Entry e[E];
@@ -299,8 +300,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       nhi = n2hi;
       nlo = n2lo;
       if (hi > start && (end - hi) % CK == 0) {
-        // state in front of chunk (end - hi) / CK: T and the accumulated
-        // colour, with the current run closed at the boundary
+        // at the front of chunk k = (end - hi) / CK: T, and the colour the
+        // chunk just finished contributed (the current run closed at the
+        // boundary; the sum restarts for the next chunk)
         float* ckp = w.ckbuf + (int64_t)(ck0 + (end - hi) / CK - 1) * (4 * TILE * TILE);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
@@ -317,8 +319,12 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           const int slot = (quad * PPT + q) * 64 + lane;
           ckp[slot] = T[q];
 #pragma unroll
-          for (int c = 0; c < C; ++c) ckp[(1 + c) * TILE * TILE + slot] = acc[q][c];
+          for (int c = 0; c < C; ++c) {
+            ckp[(1 + c) * TILE * TILE + slot] = acc[q][c];
+            acc[q][c] = 0.0f;
+          }
         }
+        ++n_ck;
       }
       __builtin_amdgcn_wave_barrier();
       if (__ballot(!mine) == 0ull) break;  // every pixel of the quadrant has stopped
@@ -330,6 +336,25 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       if (C == 3) {
         acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
         acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+      }
+    }
+    // Suffix sums over the chunks, back to front: each boundary's slot
+    // receives the colour of everything behind it (the chunks after it; the
+    // background is added by the adjoint), a sum of the chunks' own
+    // contributions with no cancellation, and the total is the pixel's
+    // colour.  Each lane rereads only the slots it wrote itself.
+    const int64_t ck_first = (int64_t)ck0 * (4 * TILE * TILE);
+    for (int k = n_ck; k >= 1; --k) {
+      float* ckp = w.ckbuf + ck_first + (int64_t)(k - 1) * (4 * TILE * TILE);
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int slot = (quad * PPT + q) * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const float ch = ckp[(1 + c) * TILE * TILE + slot];
+          ckp[(1 + c) * TILE * TILE + slot] = acc[q][c];
+          acc[q][c] += ch;
+        }
       }
     }
 #pragma unroll
@@ -344,7 +369,6 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         for (int c = 0; c < C; ++c) {
           const int64_t o = (int64_t)st.pix_off * C + c * plane + (int64_t)y * st.W + x;
           image[o] = __builtin_fmaf(T[q], bg[s * C + c], acc[q][c]);
-          w.afin[o] = acc[q][c];
         }
         Tfin[pix] = T[q];
         nlast[pix] = stop[q];
@@ -399,20 +423,13 @@ __device__ inline int wave_min(int v) {
 
 // Flushes one wavefront's running per-curve sums into the FP64 per-curve
 // accumulators: the colour gradient sum_q dL/dI_c(q) sum(alpha T) of each
-// channel, and the opacity gradient of a stroke curve.  Over a run of entries
-// sum(alpha T) = T at the run's start - T now (alpha_j T_j = T_j - T_{j+1}),
-// so each pixel keeps only Tst, its T where the run began, reset here.
+// channel (aT: each pixel's sum of alpha T over the run, reset here), and the
+// opacity gradient of a stroke curve.
 template <int C, int PPT>
-__device__ inline void flush_curve(double* gcurve, int c, bool fill, const float (&gI)[PPT][3],
-                                   const float (&T)[PPT], float (&Tst)[PPT], float& accO) {
+__device__ inline void flush_curve(double* gcurve, int c, bool fill, const float (&gI)[PPT][3], float (&aT)[PPT],
+                                   float& accO) {
   float v[C + 1];
   v[0] = fill ? 0.0f : accO;
-  float aT[PPT];
-#pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    aT[q] = Tst[q] - T[q];
-    Tst[q] = T[q];
-  }
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) {
     float a = 0.0f;
@@ -420,6 +437,8 @@ __device__ inline void flush_curve(double* gcurve, int c, bool fill, const float
     for (int q = 0; q < PPT; ++q) a = __builtin_fmaf(gI[q][ch], aT[q], a);
     v[1 + ch] = a;
   }
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) aT[q] = 0.0f;
   accO = 0.0f;
   const float t = wave_totals_to_lanes<C + 1>(v);
   const int lane = __lane_id();
@@ -457,24 +476,29 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 }
 
 // Adjoint of the forward blend, one work item per (tile, quadrant, chunk).
-// Inside a chunk it walks front to back like the forward and starts from the
-// forward's state at the chunk boundary, so T follows the forward's own
-// products.  With K = sum_c dL/dI_c col_c and U the loss-weighted colour
-// accumulated in front (U += K alpha T), Eq. 8 gives
-//   dL/dalpha = T K - (R - U) / (1 - alpha),   R = sum_c dL/dI_c I_c,
-// R - U being the loss-weighted colour still to come behind the entry (the
-// back layers and the background).  Over a run of one curve's entries K is
-// fixed and R - U = Vc + K T after each entry, so dL/dalpha = -Vc / (1 - alpha)
-// with Vc set where the run begins.  Per Gaussian it accumulates dL/dmu and
-// dL/dsigma for stroke Gaussians and dL/do_j for fill Gaussians (whose own
-// opacity carries the SDF); colour gradients (and a stroke curve's opacity
-// gradient, its o_j all being o) belong to the curve, so each lane keeps
-// running per-curve sums that are flushed when the curve changes along the
-// list (and for strokes every FLUSH entries).  The entries of a step are cut
-// into runs of one curve with one ballot, and each run is composited by a loop
-// for its kind, with no per-entry curve test.  Occupancy: six wavefronts per
-// SIMD for one pixel per lane at depth 64, four for 32 x 32 tiles at depth 64
-// (128 VGPRs, unspilled); elsewhere the registers decide.
+// Inside its chunk an item walks back to front, starting from the state the
+// forward stored at the chunk's back end (T there, and the colour of
+// everything behind it), or from T_final for a pixel that stopped inside the
+// chunk.  With K = sum_c dL/dI_c col_c of an entry and B the loss-weighted
+// colour behind it, Eq. 8 gives
+//   dL/dalpha = T K - B / (1 - alpha),   T the transmittance in front of it.
+// Walking back to front, B grows by K alpha T = K (T - T') from each entry
+// (T' = T (1 - alpha), the transmittance behind it), and T is recovered as
+// T = T' / (1 - alpha).  Over a run of one curve's entries K is fixed, so
+// W = B - K T' does not change, and dL/dalpha = -W / (1 - alpha); W is
+// re-expressed where K changes.  B is built from the back, a sum of the terms
+// behind the entry, so its rounding stays relative to the colour actually
+// behind (a front-to-back form B = R - U loses it where T is small).  Per
+// Gaussian it accumulates dL/dmu and dL/dsigma for stroke Gaussians and
+// dL/do_j for fill Gaussians (whose own opacity carries the SDF); colour
+// gradients (and a stroke curve's opacity gradient, its o_j all being o)
+// belong to the curve, so each lane keeps running per-curve sums that are
+// flushed when the curve changes along the list (and for strokes every FLUSH
+// entries).  The entries of a step are cut into runs of one curve with one
+// ballot, and each run is composited by a loop for its kind, with no
+// per-entry curve test.  Occupancy: six wavefronts per SIMD for one pixel per
+// lane at depth 64, four for 32 x 32 tiles at depth 64 (128 VGPRs, unspilled);
+// elsewhere the registers decide.
 template <int C, int TILE, int E>
 __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 4 : 1)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
@@ -526,7 +550,10 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const int c_hi = end - kc * CK, c_lo = max(start, end - (kc + 1) * CK);  // the chunk's positions
     const int64_t plane = (int64_t)st.H * st.W;
-    float px[PPT], py[PPT], T[PPT], U[PPT], R[PPT], gI[PPT][3];
+    // the forward's state at the chunk's back end (the front of chunk kc + 1),
+    // stored when a chunk follows
+    const float* ckn = c_lo > start ? w.ckbuf + (int64_t)(w.ck_off[tile] + kc) * (4 * TILE * TILE) : nullptr;
+    float px[PPT], py[PPT], T[PPT], Wc[PPT], gI[PPT][3];
     int stop[PPT];
     int my_lo = end;
 #pragma unroll
@@ -536,8 +563,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       px[q] = (float)lx;
       py[q] = (float)ly;
       T[q] = 1.0f;
-      U[q] = 0.0f;
-      R[q] = 0.0f;
+      Wc[q] = 0.0f;
       stop[q] = end;  // invalid pixels never take part
 #pragma unroll
       for (int c = 0; c < 3; ++c) gI[q][c] = 0.0f;
@@ -545,58 +571,59 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         const int64_t pix = (int64_t)st.pix_off + (int64_t)(y0 + ly) * st.W + (x0 + lx);
         const float tf = Tfin[pix];
         stop[q] = nlast[pix];
+        // a pixel still live behind this chunk starts from the stored state,
+        // one that stopped inside it from T_final with only the background
+        // behind it (no chunk is stored after a pixel's stop is passed)
+        const int slot = (quad * PPT + q) * 64 + lane;
+        float behind[3] = {0.0f, 0.0f, 0.0f};
+        T[q] = tf;
+        if (stop[q] < c_lo) {  // then c_lo > start, so a chunk follows and ckn is set
+          T[q] = ckn[slot];
+#pragma unroll
+          for (int c = 0; c < C; ++c) behind[c] = ckn[(1 + c) * TILE * TILE + slot];
+        }
+        float B = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int64_t o = (int64_t)st.pix_off * C + c * plane + (int64_t)(y0 + ly) * st.W + (x0 + lx);
           gI[q][c] = dL[o];
-          R[q] = __builtin_fmaf(gI[q][c], __builtin_fmaf(tf, bg[s * C + c], w.afin[o]), R[q]);
+          B = __builtin_fmaf(gI[q][c], __builtin_fmaf(tf, bg[s * C + c], behind[c]), B);
         }
+        Wc[q] = B;  // W = B - K T' with no curve yet (K = 0)
         my_lo = min(my_lo, stop[q]);
       }
     }
     // positions below every pixel's stopping position take no part
     const int lo = max(wave_min(my_lo), c_lo);
     if (c_hi <= lo) continue;
-    if (kc > 0) {  // the forward's state in front of this chunk
-      const float* ckp = w.ckbuf + (int64_t)(w.ck_off[tile] + kc - 1) * (4 * TILE * TILE);
-#pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int slot = (quad * PPT + q) * 64 + lane;
-        T[q] = ckp[slot];
-#pragma unroll
-        for (int c = 0; c < C; ++c) U[q] = __builtin_fmaf(gI[q][c], ckp[(1 + c) * TILE * TILE + slot], U[q]);
-      }
-    }
     int cur = -1, since = 0;
     bool cur_fill = false;
-    // per pixel: K = sum_c dL/dI_c col_c of the current curve; V = R - U
-    // (the loss-weighted colour still to come), which over a run of one
-    // curve is Vc + K T (U grows by K alpha T = K (T - T')), so only Vc is
-    // kept, fixed where the run begins; and T where the run began (the
-    // curve's colour gradient is dL/dI_c times the run's sum of alpha T)
-    float Kc[PPT], Vc[PPT], Tst[PPT], accO = 0.0f;
+    // per pixel: K of the current curve, W (fixed over a run of one curve),
+    // and the run's sum of alpha T (the curve's colour gradient is dL/dI_c
+    // times it)
+    float Kc[PPT], aT[PPT], accO = 0.0f;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       Kc[q] = 0.0f;
-      Vc[q] = R[q] - U[q];
-      Tst[q] = T[q];
+      aT[q] = 0.0f;
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
-    // front to back over the chunk's positions c_hi - 1 down to lo
+    // back to front over the chunk's positions lo up to c_hi - 1, in steps
+    // of `depth` (each lane loads one entry per 64 of a step)
     Entry e[E];
-    int hi = c_hi, lo_s = max(lo, hi - depth);
+    int s_lo = lo, s_hi = min(c_hi, lo + depth);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
-      load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
+      load_entry(idx, gs, w.gcol, s_lo + k, k < s_hi - s_lo, &e[u]);
     }
-    while (hi > lo) {
+    while (s_lo < c_hi) {
       int cnt = 0;
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
-        const int mypos = hi - 1 - k;
-        const bool ok = k < hi - lo_s;
+        const int mypos = s_lo + k;
+        const bool ok = k < s_hi - s_lo;
         float4 geo;
         const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
         const uint64_t m = __ballot(keep);
@@ -610,17 +637,17 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         }
         cnt += __popcll(m);
       }
-      const int nhi = lo_s, nlo = max(lo, nhi - depth);
+      const int n_lo = s_hi, n_hi = min(c_hi, s_hi + depth);
 #pragma unroll
       for (int u = 0; u < E; ++u) {  // next step, in flight while this one is processed
         const int k = u * 64 + lane;
-        load_entry(idx, gs, w.gcol, nhi - 1 - k, k < nhi - nlo, &e[u]);
+        load_entry(idx, gs, w.gcol, n_lo + k, k < n_hi - n_lo, &e[u]);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // composited entries that begin a run (their curve differs from the
-      // entry before, the first one compared with the previous step's curve)
+      // entries that begin a run (their curve differs from the entry processed
+      // before them, the first one compared with the previous step's curve)
       uint64_t rs[E];
 #pragma unroll
       for (int g = 0; g < E; ++g) {
@@ -639,7 +666,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           if (m) jend = 64 * g + __builtin_ctzll(m);
         }
         if ((rs[j >> 6] >> (j & 63)) & 1ull) {  // a new curve: close the previous one
-          if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, T, Tst, accO);
+          if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, aT, accO);
           const int4 mt = wmeta[j];
           const float4 pc = wpc[j];
           const float col[3] = {pc.y, pc.z, pc.w};
@@ -648,8 +675,8 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
             float K = 0.0f;
 #pragma unroll
             for (int c = 0; c < C; ++c) K = __builtin_fmaf(gI[q][c], col[c], K);
-            // V now, re-expressed with the new curve's K
-            Vc[q] = __builtin_fmaf(-K, T[q], __builtin_fmaf(Kc[q], T[q], Vc[q]));
+            // B = W + K_old T' is unchanged; W re-expressed with the new K
+            Wc[q] = __builtin_fmaf(-K, T[q], __builtin_fmaf(Kc[q], T[q], Wc[q]));
             Kc[q] = K;
           }
           cur = __builtin_amdgcn_readfirstlane(mt.y);
@@ -677,11 +704,11 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               const float oG = op * G;
               const bool lt = oG < amax;
               const float alpha = in ? (lt ? oG : amax) : 0.0f;
-              const float onem = 1.0f - alpha;
-              // with R - U = Vc + K T (1 - alpha) after this entry,
-              // dL/dalpha = T K - (R - U) / (1 - alpha) = -Vc / (1 - alpha)
-              const float dLda = (in && lt) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
-              T[q] = T[q] * onem;
+              const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+              // dL/dalpha = (T' K - B) / (1 - alpha) = -W / (1 - alpha)
+              const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
+              T[q] = in ? T[q] * r : T[q];  // the transmittance in front of the entry
+              aT[q] = __builtin_fmaf(alpha, T[q], aT[q]);
               v3 = __builtin_fmaf(dLda, G, v3);  // dL/do_j
             }
           };
@@ -718,7 +745,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           // is flushed every FLUSH entries to keep that FP32 sum short
           for (; j < jend; ++j) {
             if (since >= FLUSH) {
-              flush_curve<C, PPT>(w.gcurve, cur, false, gI, T, Tst, accO);
+              flush_curve<C, PPT>(w.gcurve, cur, false, gI, aT, accO);
               since = 0;
             }
             ++since;
@@ -738,9 +765,10 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               const float oG = op * G;
               const bool lt = oG < amax;
               const float alpha = in ? (lt ? oG : amax) : 0.0f;
-              const float onem = 1.0f - alpha;
-              const float dLda = (in && lt) ? -Vc[q] * __builtin_amdgcn_rcpf(onem) : 0.0f;
-              T[q] = T[q] * onem;
+              const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+              const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
+              T[q] = in ? T[q] * r : T[q];
+              aT[q] = __builtin_fmaf(alpha, T[q], aT[q]);
               v[3] = __builtin_fmaf(dLda, G, v[3]);  // dL/do_j
               const float dG = dLda * op;
               const float dd2 = dG * G * gm.w * ln2;  // d exp2(a d2) / d d2 = G a ln 2
@@ -762,14 +790,14 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         }
       }
       __builtin_amdgcn_wave_barrier();
-      hi = nhi;
-      lo_s = nlo;
+      s_lo = n_lo;
+      s_hi = n_hi;
     }
     if (n_rows > 0) {
       flush_rows<RB>(park, ptgt, n_rows, ggrad);
       n_rows = 0;
     }
-    if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, T, Tst, accO);
+    if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, aT, accO);
   }
 }
 

@@ -20,7 +20,7 @@ constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 28;                // workspace entries
+constexpr int N_WS = 27;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -64,8 +64,8 @@ struct Work {
   double* sacc;        // [n_scenes + 1] per-scene sums (distance-weighted loss)
   int32_t* ck_off;     // [tiles at the smallest tile size + 1] first checkpoint of each tile (scan)
   int32_t* item_off;   // [tiles at the smallest tile size + 1] first adjoint item of each tile in blend order (scan)
-  float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries
-  float* afin;         // [pixels][3] accumulated colour at each pixel's end of compositing
+  float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries: T, and
+                       // the colour of everything behind the boundary (per channel)
   float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and 1 for fill Gaussians
   double* segs;        // [caps.boundary + (SDF_CHUNK - 1) * n_curves][SEG_WORDS] fill SDF segment records
 };

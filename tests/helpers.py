@@ -33,8 +33,10 @@ def oracle_params(p):
     return d
 
 
-def gpu_run(batch, params, target=None, persistent=False, backward=True, caps=None):
-    """sample -> bin -> forward (-> L2 backward against target) on the GPU."""
+def gpu_run(batch, params, target=None, persistent=False, backward=True, caps=None, upstream=None):
+    """sample -> bin -> forward (-> L2 backward against target) on the GPU.
+    upstream (image layout) replaces 2 (I - target) as the backward's dL/dImage,
+    e.g. the oracle's own, so that a gradient comparison sees the same input."""
     import torch
     from paper_2606_31764_amd.render import Renderer, param_tensors
     r = Renderer(batch, params, caps=caps, persistent=persistent)
@@ -44,14 +46,47 @@ def gpu_run(batch, params, target=None, persistent=False, backward=True, caps=No
                n_last=r.n_last.cpu().numpy(), plan=r.plan_np(), gauss=r.gaussians(), counters=r.read_counters())
     ranges, idx = r.tiles()
     out["ranges"], out["idx"] = ranges, idx
-    if backward and target is not None:
-        tgt = torch.as_tensor(np.asarray(target, np.float32), device="cuda")
-        dL = 2.0 * (img - tgt)
+    if backward and (target is not None or upstream is not None):
+        if upstream is not None:
+            dL = torch.as_tensor(np.asarray(upstream, np.float32), device="cuda")
+        else:
+            tgt = torch.as_tensor(np.asarray(target, np.float32), device="cuda")
+            dL = 2.0 * (img - tgt)
         grads = r.backward(t, dL)
         torch.cuda.synchronize()
         out["grads"] = {n: g.cpu().numpy().astype(np.float64) for n, g in zip(PARAM_NAMES, grads)}
         out["dL"] = dL.cpu().numpy().astype(np.float64)
     return out
+
+
+EPS32 = 2.0 ** -24   # FP32 unit roundoff
+K_ACC = 64           # roundoffs allowed on a component's error scale (see grad_check)
+
+
+def grad_check(g, ref, scale, rtol=GRAD_RTOL, atol=GRAD_ATOL, k=K_ACC):
+    """Per component: |g - ref| <= rtol |ref| + atol + k eps32 S, with S the
+    oracle's error scale of that component (the sum, over every pixel and
+    Gaussian, of the absolute values of the terms the gradient adds up; see
+    oracle.param_grad).  A component whose terms cancel has |ref| << S, and
+    no FP32 evaluation order can bring it below eps32 S; everything else is
+    held to the relative bound.  Returns (worst ratio, report)."""
+    worst, lines = 0.0, []
+    for n in PARAM_NAMES:
+        a = np.asarray(g[n], np.float64).ravel()
+        b = np.asarray(ref[n], np.float64).ravel()
+        sc = np.asarray(scale[n], np.float64).ravel()
+        if b.size == 0:
+            continue
+        d = np.abs(a - b)
+        bound = rtol * np.abs(b) + atol + k * EPS32 * sc
+        r = d / bound
+        i = int(np.argmax(r))
+        worst = max(worst, float(r[i]))
+        # roundoffs of the error scale the worst component needed beyond the relative bound
+        kneed = float(np.max(np.maximum(d - rtol * np.abs(b) - atol, 0.0) / np.maximum(EPS32 * sc, 1e-300)))
+        lines.append("%s: worst %.3g at %d (|d|=%.3g ref=%.3g S=%.3g), k needed %.3g" % (n, r[i], i, d[i], b[i],
+                                                                                      sc[i], kneed))
+    return worst, "; ".join(lines)
 
 
 def grad_close(g, ref, rtol=GRAD_RTOL, atol=GRAD_ATOL):

@@ -178,3 +178,54 @@ def test_autotune_returns_a_valid_config():
     img2 = r2.run_forward(t).clone()
     torch.cuda.synchronize()
     assert np.abs(img2.cpu().numpy() - img.cpu().numpy()).max() < 2e-6
+
+
+def test_full_c5_batched_matches_plain():
+    """The 64-scene batch at its full size (about 23M Gaussians), in the
+    benchmark's launch configuration (persistent, tile 32, depth 64): every
+    scene's image and tile lists bit-identical to its own plain per-scene run,
+    and its gradients equal up to FP32 atomic order."""
+    import torch
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b, kinds = synth.config5()
+    p = Params().replace(delta_c=3.0, h=1.0, tile=32, batch=64)
+    rb = Renderer(b, p, persistent=True)
+    tb = param_tensors(b)
+    n_img = 3 * sum(int(h) * int(w) for h, w in b.hw)
+    target = torch.as_tensor(np.random.default_rng(5901).uniform(0, 1, n_img).astype(np.float32), device="cuda")
+    img_b, grads_b = _step(rb, tb, target)
+    ranges_b, idx_b = rb.tiles()
+    img_b = img_b.cpu().numpy()
+    print("C5 batched G =", rb.read_counters()[0], "pairs =", len(idx_b), flush=True)
+    g_off = px_off = tile_off = p_off = 0
+    worst = 0.0
+    for s in range(b.n_scenes):
+        sc = b.select_scene(s)
+        r = Renderer(sc, p, persistent=False)
+        t = param_tensors(sc)
+        n = 3 * int(sc.hw[0][0]) * int(sc.hw[0][1])
+        img, grads = _step(r, t, target[px_off:px_off + n])
+        np.testing.assert_array_equal(img.cpu().numpy(), img_b[px_off:px_off + n])
+        ranges, idx = r.tiles()
+        nt, P = len(ranges), len(idx)
+        np.testing.assert_array_equal(idx_b[p_off:p_off + P], idx + g_off)
+        rs = ranges_b[tile_off:tile_off + nt].astype(np.int64)
+        ne = ranges[:, 1] > ranges[:, 0]
+        assert np.all((rs[:, 1] > rs[:, 0]) == ne)
+        np.testing.assert_array_equal(rs[ne] - p_off, ranges[ne])
+        c0 = int(np.searchsorted(b.scene, s))
+        ko, to = int(b.key_off[c0]), int(b.tau_off[c0])
+        sl = dict(key_xy=slice(ko, ko + len(sc.key_w)), key_w=slice(ko, ko + len(sc.key_w)),
+                  key_s=slice(ko, ko + len(sc.key_w)), tau=slice(to, to + len(sc.tau)),
+                  color=slice(c0, c0 + sc.n_curves), opacity=slice(c0, c0 + sc.n_curves))
+        gb = {nm: grads_b[i][sl[nm]].cpu().numpy().astype(np.float64) for i, nm in enumerate(PARAM_NAMES)}
+        gp = {nm: grads[i].cpu().numpy().astype(np.float64) for i, nm in enumerate(PARAM_NAMES)}
+        worst = max(worst, grad_close(gb, gp, rtol=1e-5, atol=1e-6))
+        g_off += int(r.read_counters()[0])
+        px_off += n
+        tile_off += nt
+        p_off += P
+        del r, t, img, grads
+    assert g_off == rb.read_counters()[0] and p_off == len(idx_b)
+    print("C5 per-scene gradient worst ratio", worst, flush=True)
+    assert worst <= 1.0

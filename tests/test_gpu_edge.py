@@ -469,3 +469,40 @@ def test_forward_and_backward_refuse_another_tile_than_bin():
     r.forward(t, params=p.replace(tile=32))  # consistent again
     r.backward(t, dL, params=p.replace(tile=32))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p_deg", [1, 4, 5])
+def test_fill_of_other_degrees(p_deg):
+    """Filled closed curves of degree 1 (a polygon), 4 and 5, against the oracle."""
+    rng = np.random.default_rng(40 + p_deg)
+    parts = []
+    for k in range(3):
+        nk = 9 + k
+        ang = 2 * np.pi * np.arange(nk) / nk + rng.uniform(-0.2, 0.2, nk)
+        rad = rng.uniform(9.0, 15.0, nk)
+        c = (14 + 12 * k, 16 + 6 * k)
+        xy = np.stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)], 1)
+        parts.append(_part(xy, p=p_deg, closed=True, filled=True, color=tuple(rng.uniform(0, 1, 3)),
+                           o=0.85, seed=50 + k))
+    b = _batch(parts, hw=(44, 52))
+    _full_parity(b, Params(h=1.0))
+
+
+def test_clockwise_fill():
+    """A fill whose boundary runs clockwise has winding -1 inside, so its SDF
+    sign is -1 everywhere (R11): the interior is not filled, only a band
+    around the boundary shows (opacity o sigmoid(-gamma d / h)).  GPU and
+    oracle agree, and pixels far inside keep the background."""
+    nk = 12
+    ang = -2 * np.pi * np.arange(nk) / nk          # decreasing angle: clockwise in y-down pixels
+    xy = np.stack([24 + 15 * np.cos(ang), 22 + 15 * np.sin(ang)], 1)
+    b = _batch([_part(xy, p=3, closed=True, filled=True, color=(0.9, 0.1, 0.1), o=0.9, seed=7)], hw=(44, 48))
+    out = _full_parity(b, Params(h=1.0))
+    img = out["image"].reshape(3, 44, 48)
+    # the centre (9 px or more from the boundary): background
+    assert np.all(np.abs(img[:, 18:27, 20:29] - 1.0) < 1e-4)
+    # the same path counter-clockwise fills the centre
+    xy_ccw = xy[::-1].copy()
+    b2 = _batch([_part(xy_ccw, p=3, closed=True, filled=True, color=(0.9, 0.1, 0.1), o=0.9, seed=7)], hw=(44, 48))
+    img2 = gpu_run(b2, Params(h=1.0), backward=False)["image"].reshape(3, 44, 48)
+    assert np.all(np.abs(img2[0, 18:27, 20:29] - (0.9 * 0.9 + 0.1 * 1.0)) < 2e-2)

@@ -146,3 +146,84 @@ def test_full_dense_gradient_invariances(runs, name):
         worst = max(worst, abs(tw.sum()) / (np.abs(tw).sum() + 1e-6), abs(tt.sum()) / (np.abs(tt).sum() + 1e-6))
     print(name, "worst relative Euler residual", worst, flush=True)
     assert worst < 1e-3
+
+
+def test_full_c3_every_pixel_and_dense_gradient(runs):
+    """Every pixel of the 512^2 fill image against the oracle, and the dense
+    gradient of an L2 loss against a seeded target, component by component
+    (the oracle's upstream gradient is fed to the GPU's backward, so both
+    differentiate the same function)."""
+    import torch
+    from helpers import grad_check
+    R = _run(runs, "c3")
+    b, r, t, p = R["b"], R["r"], R["t"], R["p"]
+    op = oracle_params(p)
+    rng = np.random.default_rng(3901)
+    target = rng.uniform(0.0, 1.0, R["img"].numel())
+    img_ref, T_ref = oracle.composite(b, R["ref"], op)
+    up = 2.0 * (img_ref - target)
+    _, _, adj, adjabs = oracle.composite(b, R["ref"], op, upstream=up, with_abs=True)
+    err = np.abs(R["img"].cpu().numpy() - img_ref).max()
+    print("c3 every-pixel max abs err", err, flush=True)
+    assert err <= IMG_TOL
+    assert np.abs(r.T.cpu().numpy() - T_ref).max() <= IMG_TOL
+    r.run_forward(t)  # the backward reads this forward's state
+    grads = r.backward(t, torch.as_tensor(up.astype(np.float32), device="cuda"))
+    torch.cuda.synchronize()
+    names = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+    gg = {n: x.cpu().numpy().astype(np.float64) for n, x in zip(names, grads)}
+    gref, scale = oracle.param_grad(b, R["ref"], adj, op, adjabs)
+    worst, rep = grad_check(gg, gref, scale)
+    print("c3 dense gradient", worst, rep, flush=True)
+    assert worst <= 1.0, rep
+
+
+def test_full_c4_band(runs):
+    """A 128-row band of the 1024^2 long-spline image against the oracle, and
+    gradient components of every curve that reaches the band for an upstream
+    gradient confined to it."""
+    import torch
+    from helpers import EPS32, K_ACC
+    R = _run(runs, "c4")
+    b, r, t, p = R["b"], R["r"], R["t"], R["p"]
+    op = oracle_params(p)
+    H, W = (int(v) for v in b.hw[0])
+    y0, y1 = 448, 576
+    yy, xx = np.mgrid[y0:y1, 0:W]
+    pix = np.stack([np.zeros(yy.size, int), yy.ravel(), xx.ravel()], 1)
+    rng = np.random.default_rng(4901)
+    up = rng.normal(0.0, 1.0, (len(pix), 1))
+    vals, T, adj, adjabs = oracle.composite(b, R["ref"], op, pixels=pix, upstream=up, with_abs=True)
+    img = R["img"].cpu().numpy().reshape(H, W)
+    err = np.abs(img[y0:y1].ravel() - vals[:, 0]).max()
+    print("c4 band max abs err", err, flush=True)
+    assert err <= IMG_TOL
+    dense = np.zeros((H, W), np.float32)
+    dense[y0:y1] = up[:, 0].reshape(y1 - y0, W)
+    r.run_forward(t)
+    grads = r.backward(t, torch.as_tensor(dense.reshape(-1), device="cuda"))
+    torch.cuda.synchronize()
+    names = ("key_xy", "key_w", "key_s", "tau", "color", "opacity")
+    gg = {n: x.cpu().numpy().astype(np.float64) for n, x in zip(names, grads)}
+    touched = np.unique(R["ref"]["curve"][np.any(adj != 0, axis=1)])
+    assert len(touched) > 0
+    seeds, where = [], []
+    for c in touched:
+        k0, k1 = b.key_off[c], b.key_off[c + 1]
+        t0, t1 = b.tau_off[c], b.tau_off[c + 1]
+        for k in rng.choice(k1 - k0, 12, replace=False):
+            seeds += [(c, 1, k), (c, 2, k), (c, 3, k), (c, 4, k)]
+            where += [("key_xy", 2 * (k0 + k)), ("key_xy", 2 * (k0 + k) + 1), ("key_w", k0 + k), ("key_s", k0 + k)]
+        for tt in rng.choice(t1 - t0, 8, replace=False):
+            seeds.append((c, 5, tt))
+            where.append(("tau", t0 + tt))
+        seeds.append((c, 6, 0))
+        where.append(("opacity", c))
+    ref, scale = oracle.param_grad_seeds(b, R["ref"], adj, np.array(seeds, np.int32), op, adjabs=adjabs)
+    got = np.array([gg[n].reshape(-1)[i] for n, i in where])
+    d = np.abs(got - ref)
+    bound = 1e-4 * np.abs(ref) + 1e-6 + K_ACC * EPS32 * scale
+    i = int(np.argmax(d / bound))
+    print("c4 band gradient: %d components, worst %.3g (%s: |d| %.3g ref %.3g S %.3g)"
+          % (len(ref), d[i] / bound[i], where[i][0], d[i], ref[i], scale[i]), flush=True)
+    assert np.all(d <= bound)

@@ -20,6 +20,8 @@ def _cases():
     return {
         "c1": (synth.config1(), Params().replace(delta_c=1.5)),
         "c2s": (synth.config2(seed=2100, n_curves=8, size=120), Params().replace(delta_c=3.0)),
+        # the calligraphy configuration at its full size: 32 strokes, 256^2
+        "c2_full": (synth.config2(), Params().replace(delta_c=3.0)),
         "c3s_h2": (synth.config3(seed=3100, n_paths=10, size=100), Params().replace(h=2.0)),
         "c3s_h1": (synth.config3(seed=3200, n_paths=6, size=72), Params().replace(h=1.0)),
         "c4s": (synth.config4(seed=4100, n_curves=2, n_cp=60, size=200), Params().replace(delta_c=10.0)),

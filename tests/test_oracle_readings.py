@@ -209,3 +209,20 @@ def test_count_flag_marks_an_integral_delta_L():
     assert pl[0, oracle.P_FLAG] == oracle.FLAG_NEAR_INT and pl[0, oracle.P_NSAMP] in (10, 11)
     pl, _, _ = oracle.plan(b, dict(delta_c=1.05, kappa=0))
     assert pl[0, oracle.P_FLAG] == 0 and pl[0, oracle.P_NSAMP] == 11
+
+
+def test_error_scale_bounds_the_gradient():
+    """The oracle's per-component error scale S is a sum of absolute values of
+    the terms the gradient adds, so |g| <= S for every component (equality
+    when no term cancels: the colour gradient of a curve whose upstream
+    gradient has one sign)."""
+    b = synth.config2(seed=2901, n_curves=5, size=48)
+    prm = dict(delta_c=3.0)
+    target = oracle.render(synth.perturbed(b, 3), prm)[0]
+    _, (g, S), _, img = oracle.loss_and_grad(b, target, prm, with_scale=True)
+    for n in g:
+        assert np.all(np.abs(g[n]) <= S[n] * (1 + 1e-12) + 1e-300), n
+        assert np.all(S[n][np.abs(g[n]) > 0] > 0)
+    # one sign of the upstream gradient: no cancellation in the colour sums
+    _, (g1, S1), _, _ = oracle.loss_and_grad(b, img - 0.1, prm, with_scale=True)
+    np.testing.assert_allclose(np.abs(g1["color"]), S1["color"], rtol=1e-12)
