@@ -89,6 +89,45 @@ def grad_check(g, ref, scale, rtol=GRAD_RTOL, atol=GRAD_ATOL, k=K_ACC):
     return worst, "; ".join(lines)
 
 
+def oracle_reference(batch, target, op):
+    """The oracle's image, its L2 upstream gradient 2 (I - target), and the
+    parameter gradient with its per-component error scale."""
+    _, (gref, scale), _, img_ref = oracle.loss_and_grad(batch, target, op, with_scale=True)
+    return img_ref, 2.0 * (img_ref - np.asarray(target, np.float64)), gref, scale
+
+
+def gpu_vs_oracle(batch, params, target, persistent=False):
+    """GPU forward, then its backward for the oracle's upstream gradient;
+    asserts the image (1e-5) and every gradient component (grad_check)."""
+    op = oracle_params(params)
+    img_ref, up, gref, scale = oracle_reference(batch, target, op)
+    out = gpu_run(batch, params, upstream=up, persistent=persistent)
+    err = np.abs(out["image"] - img_ref).max()
+    assert err <= IMG_TOL, err
+    worst, rep = grad_check(out["grads"], gref, scale)
+    assert worst <= 1.0, rep
+    return out, worst, rep
+
+
+def grad_check_fp64(g, ref, rtol=GRAD_RTOL, atol=GRAD_ATOL, floor=1e-9):
+    """Per component, for gradients the library accumulates in FP64 and rounds
+    to FP32 once (the regularisers): |g - ref| <= rtol |ref| + atol + floor *
+    max |ref of the group| (the floor covers FP64 cancellation, 1e-7 of which
+    would already be 1e9 FP64 roundoffs).  Returns (worst ratio, report)."""
+    worst, lines = 0.0, []
+    for n in PARAM_NAMES:
+        a = np.asarray(g[n], np.float64).ravel()
+        b = np.asarray(ref[n], np.float64).ravel()
+        if b.size == 0:
+            continue
+        d = np.abs(a - b)
+        r = d / (rtol * np.abs(b) + atol + floor * np.abs(b).max())
+        i = int(np.argmax(r))
+        worst = max(worst, float(r[i]))
+        lines.append("%s: worst %.3g at %d (|d|=%.3g ref=%.3g)" % (n, r[i], i, d[i], b[i]))
+    return worst, "; ".join(lines)
+
+
 def grad_close(g, ref, rtol=GRAD_RTOL, atol=GRAD_ATOL):
     """Per parameter group: max |g - ref| <= rtol * max |ref| + atol.  Returns the worst ratio."""
     worst = 0.0

@@ -92,12 +92,8 @@ def test_batched_against_oracle():
     p = Params().replace(delta_c=2.0, h=2.0)
     op = oracle_params(p)
     target = oracle.render(synth.perturbed(b, seed=4), op)[0]
-    from helpers import gpu_run
-    out = gpu_run(b, p, target=target, persistent=True)
-    img_ref, _, _ = oracle.render(b, op)
-    assert np.abs(out["image"] - img_ref).max() <= IMG_TOL
-    _, gref, _, _ = oracle.loss_and_grad(b, target, op)
-    assert grad_close(out["grads"], gref) <= 1.0
+    from helpers import gpu_vs_oracle
+    gpu_vs_oracle(b, p, target, persistent=True)
 
 
 def test_graph_replay_with_device_annealing():

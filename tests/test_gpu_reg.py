@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import PARAM_NAMES, grad_close, grad_report, oracle_params
+from helpers import PARAM_NAMES, grad_check_fp64, grad_close, oracle_params
 from paper_2606_31764_amd import synth
 from paper_2606_31764_amd.render import Params
 
@@ -42,7 +42,8 @@ def _oracle_reg(b, p, reg_kw, box=None):
 def _check(b, p, reg_kw, box=None, loss_rtol=2e-5):
     g, loss = _gpu_reg(b, p, reg_kw, box)
     v, gref = _oracle_reg(b, p, reg_kw, box)
-    assert grad_close(g, gref) <= 1.0, grad_report(g, gref)
+    worst, rep = grad_check_fp64(g, gref)
+    assert worst <= 1.0, rep
     assert abs(loss.sum() - v) <= loss_rtol * abs(v) + 1e-6, (loss, v)
     return g, gref
 
