@@ -78,23 +78,58 @@ __device__ inline void load_entry(const int32_t* __restrict__ idx, const Gauss* 
   load_rec(gs, gcol, e->g, e);
 }
 
+// Rectangle of tile-local pixel centres: x in [x0, x1], y in [y0, y1].
+struct Box {
+  float x0, y0, x1, y1;
+};
+
+// The pixel centres held by the lanes with a set bit in `live` (lane l owns
+// the BLK x BLK block at column l & 7, row l >> 3 of the quadrant): rows from
+// the lowest and highest set bits, columns from the eight row bytes folded
+// together.  Scalar work on a wavefront-uniform mask; `live` != 0.
+template <int TILE>
+__device__ inline Box live_box(int quad, uint64_t live) {
+  using Cfg = TileCfg<TILE>;
+  const int r0 = __builtin_ctzll(live) >> 3, r1 = (63 - __builtin_clzll(live)) >> 3;
+  uint64_t f = live | (live >> 32);
+  f |= f >> 16;
+  f |= f >> 8;
+  const uint32_t cols = (uint32_t)f & 0xffu;
+  const int c0 = __builtin_ctz(cols), c1 = 31 - __builtin_clz(cols);
+  const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
+  Box b;
+  b.x0 = (float)(qx + c0 * Cfg::BLK);
+  b.x1 = (float)(qx + c1 * Cfg::BLK + Cfg::BLK - 1);
+  b.y0 = (float)(qy + r0 * Cfg::BLK);
+  b.y1 = (float)(qy + r1 * Cfg::BLK + Cfg::BLK - 1);
+  return b;
+}
+
+// All pixel centres of the quadrant.
+template <int TILE>
+__device__ inline Box quad_box(int quad) {
+  using Cfg = TileCfg<TILE>;
+  Box b;
+  b.x0 = (float)((quad & 1) * Cfg::SUB);
+  b.y0 = (float)((quad >> 1) * Cfg::SUB);
+  b.x1 = b.x0 + (float)(Cfg::SUB - 1);
+  b.y1 = b.y0 + (float)(Cfg::SUB - 1);
+  return b;
+}
+
 // Tile-local centre (relative to the tile's first pixel centre), squared
 // support radius, exp2 coefficient -log2(e) / (2 sigma^2), and whether the
-// support disc reaches the rectangle of the quadrant's pixel centres, with
-// the radius enlarged by a relative 1e-4 so that the test is conservative
-// under FP32 rounding.
-template <int TILE>
-__device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, float ks, int quad, float4* geo) {
-  using Cfg = TileCfg<TILE>;
+// support disc reaches the rectangle `bx` of pixel centres (the quadrant's
+// pixels that can still take part), with the radius enlarged by a relative
+// 1e-4 so that the test is conservative under FP32 rounding.
+__device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, float ks, const Box& bx, float4* geo) {
   const double sg = (double)r.sigma;
   const float rr = ks * r.sigma;
   const float cx = (float)(r.mx - ox), cy = (float)(r.my - oy);
   *geo = make_float4(cx, cy, rr * rr, (float)(-0.5 * LOG2E / (sg * sg)));
   const float rc = rr * 1.0001f + 1e-4f;
-  const float qx0 = (float)((quad & 1) * Cfg::SUB), qy0 = (float)((quad >> 1) * Cfg::SUB);
-  const float qx1 = qx0 + (float)(Cfg::SUB - 1), qy1 = qy0 + (float)(Cfg::SUB - 1);
-  const float dx = fmaxf(fmaxf(qx0 - cx, cx - qx1), 0.0f);
-  const float dy = fmaxf(fmaxf(qy0 - cy, cy - qy1), 0.0f);
+  const float dx = fmaxf(fmaxf(bx.x0 - cx, cx - bx.x1), 0.0f);
+  const float dy = fmaxf(fmaxf(bx.y0 - cy, cy - bx.y1), 0.0f);
   return dx * dx + dy * dy <= rc * rc;
 }
 
@@ -188,6 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       stop[q] = start;
     }
     const double ox = (double)x0 + 0.5, oy = (double)y0 + 0.5;
+    const Box qbox = quad_box<TILE>(quad);
     // front to back: list positions end-1 down to start, at most `depth` per
     // step and never across a chunk boundary, where the state is stored
     const int ck0 = w.ck_off[tile];
@@ -212,7 +248,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         const int mypos = hi - 1 - k;
         const bool ok = k < hi - lo_s;
         float4 geo;
-        const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
+        const bool keep = ok && entry_geometry(e[u].r, ox, oy, ks, qbox, &geo);
         const uint64_t m = __ballot(keep);
         if (keep) {
           const int dst = cnt + __popcll(m & below);
@@ -619,13 +655,20 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
     }
     while (s_lo < c_hi) {
       int cnt = 0;
+      // pixels that take part somewhere in this step (their stop lies below
+      // its top); walking back to front the set only grows.  Entries that
+      // reach none of them are dropped.
+      bool lv = false;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) lv = lv || (stop[q] < s_hi);
+      const Box box = live_box<TILE>(quad, __ballot(lv));
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
         const int mypos = s_lo + k;
         const bool ok = k < s_hi - s_lo;
         float4 geo;
-        const bool keep = ok && entry_geometry<TILE>(e[u].r, ox, oy, ks, quad, &geo);
+        const bool keep = ok && entry_geometry(e[u].r, ox, oy, ks, box, &geo);
         const uint64_t m = __ballot(keep);
         if (keep) {
           const int dst = cnt + __popcll(m & below);
