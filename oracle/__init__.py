@@ -30,7 +30,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # termination threshold, fill padding, and the support radius (alpha = 0 beyond
 # cutoff * sigma; Eq. 9 itself has infinite support, cutoff <= 0 restores it).
 DEFAULTS = dict(delta_c=10.0, delta_b=0.5, rho=2.0, eta=1.5, gamma=5.0, nl_factor=3.0,
-                fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=6.0, kappa=4)
+                fill_pad=0.1, h=1.0, alpha_max=0.99, eps_T=1e-6, cutoff=6.0, delta_a=0.25, kappa=4)
+ANISO = 4  # curve flag: tangent-aligned (anisotropic) contour Gaussians
+NADJ = 9   # per-Gaussian adjoint slots: mx, my, sigma, opacity, colour (3), sp, theta
 
 P_COUNT, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_FLAG = range(8)
 FLAG_NEAR_INT, FLAG_INVALID = 1, 2
@@ -57,10 +59,12 @@ class _Scenes(ctypes.Structure):
     _fields_ = [("n_scenes", ctypes.c_int32), ("hw", ctypes.c_void_p), ("bg", ctypes.c_void_p)]
 
 
+_PARAM_NAMES = ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor", "fill_pad", "h", "alpha_max", "eps_T",
+                "cutoff", "delta_a")
+
+
 class _Params(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
-                                                "fill_pad", "h", "alpha_max", "eps_T", "cutoff")] + [
-        ("kappa", ctypes.c_int32)]
+    _fields_ = [(n, ctypes.c_double) for n in _PARAM_NAMES] + [("kappa", ctypes.c_int32)]
 
 
 class _Reg(ctypes.Structure):
@@ -78,9 +82,9 @@ def lib():
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         sig = {
             "or_plan": (i64, [vp, vp, vp, vp, vp]),
-            "or_gaussians": (i64, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "or_gaussians": (i64, [vp] * 11),
             "or_bin": (i64, [i64, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, i64]),
-            "or_composite": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp]),
+            "or_composite": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp]),
             "or_param_grad_seeds": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
             "or_param_grad_seeds_scaled": (i32, [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]),
             "or_param_grad_full": (i32, [vp] * 18),
@@ -135,9 +139,7 @@ class _Batch:
         pr = dict(DEFAULTS)
         pr.update({n: v for n, v in (params or {}).items() if n in DEFAULTS})
         self.pdict = pr
-        self.params = _Params(*[float(pr[n]) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
-                                                      "fill_pad", "h", "alpha_max", "eps_T", "cutoff")],
-                              int(pr["kappa"]))
+        self.params = _Params(*[float(pr[n]) for n in _PARAM_NAMES], int(pr["kappa"]))
 
     def refs(self):
         return ctypes.byref(self.curves), ctypes.byref(self.scenes), ctypes.byref(self.params)
@@ -155,7 +157,10 @@ def plan(batch, params=None):
 
 
 def gaussians(batch, params=None, frozen_plan=None):
-    """Gaussians in emission order: dict(mu [G,2], sigma, opacity, curve, local, plan, L)."""
+    """Gaussians in emission order: dict(mu [G,2], sigma, opacity, curve, local, plan, L,
+    sp, tdir [G,2]); sigma is the axis along the tangent of a tangent-aligned
+    Gaussian (curve flag ANISO), sp the axis across it and tdir its tangent
+    (isotropic Gaussians: sp = sigma, tdir = (1, 0))."""
     B = _Batch(batch, params)
     if frozen_plan is None:
         pl, L, G = plan(batch, params)
@@ -165,8 +170,9 @@ def gaussians(batch, params=None, frozen_plan=None):
         G = int(pl[:, P_COUNT].sum())
     mu = np.zeros((G, 2)); sg = np.zeros(G); op = np.zeros(G)
     cv = np.zeros(G, np.int32); lc = np.zeros(G, np.int32)
-    lib().or_gaussians(*B.refs(), _p(pl), _p(mu), _p(sg), _p(op), _p(cv), _p(lc))
-    return dict(mu=mu, sigma=sg, opacity=op, curve=cv, local=lc, plan=pl, L=L)
+    sp = np.zeros(G); td = np.zeros((G, 2))
+    lib().or_gaussians(*B.refs(), _p(pl), _p(mu), _p(sg), _p(op), _p(cv), _p(lc), _p(sp), _p(td))
+    return dict(mu=mu, sigma=sg, opacity=op, curve=cv, local=lc, plan=pl, L=L, sp=sp, tdir=td)
 
 
 def tile_key_count(hw, tile):
@@ -205,9 +211,10 @@ def composite(batch, g, params=None, pixels=None, upstream=None, with_abs=False)
     (per scene [C][H][W] concatenated) with T_final flat ([H][W] per scene).
     pixels [n,3] (scene, y, x): values [n, C] and T [n].  With upstream (same
     layout as the image) also returns adj [G, 7]: the gradient of
-    sum(upstream * I) w.r.t. (mx, my, sigma, opacity, colour[0..2]) per Gaussian,
-    and with with_abs adjabs [G, 7]: the same sums taken over the absolute
-    values of every term (the scale of any evaluation's rounding error)."""
+    sum(upstream * I) w.r.t. (mx, my, sigma, opacity, colour[0..2], sp, theta)
+    per Gaussian ([G, 9]), and with with_abs adjabs [G, 9]: the same sums taken
+    over the absolute values of every term (the scale of any evaluation's
+    rounding error)."""
     B = _Batch(batch, params)
     C, n_img, n_t = _image_layout(batch)
     G = len(g["sigma"])
@@ -222,10 +229,14 @@ def composite(batch, g, params=None, pixels=None, upstream=None, with_abs=False)
         npix = len(pix)
         img = np.zeros((npix, C)); T = np.zeros(npix)
     up = None if upstream is None else np.ascontiguousarray(upstream, np.float64)
-    adj = np.zeros((G, 7)) if up is not None else None
-    adjabs = np.zeros((G, 7)) if (up is not None and with_abs) else None
-    lib().or_composite(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)), _p(mu), _p(sg), _p(op), _p(cv),
-                       G, npix, _p(pix), _p(img), _p(T), _p(up), _p(adj), _p(adjabs))
+    adj = np.zeros((G, NADJ)) if up is not None else None
+    adjabs = np.zeros((G, NADJ)) if (up is not None and with_abs) else None
+    sp = g.get("sp")
+    td = g.get("tdir")
+    sp = None if sp is None else np.ascontiguousarray(sp, np.float64)
+    td = None if td is None else np.ascontiguousarray(td, np.float64)
+    lib().or_composite(*B.refs(), _p(np.ascontiguousarray(g["plan"], np.int32)), _p(mu), _p(sg), _p(op), _p(sp),
+                       _p(td), _p(cv), G, npix, _p(pix), _p(img), _p(T), _p(up), _p(adj), _p(adjabs))
     if up is None:
         return img, T
     if with_abs:

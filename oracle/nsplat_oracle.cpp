@@ -102,6 +102,7 @@ typedef struct {
   double alpha_max;  // per-pixel opacity clamp (1 = none)
   double eps_T;      // stop a pixel once T < eps_T (0 = never)
   double cutoff;     // support radius in sigmas (<= 0: none)
+  double delta_a;    // contour density of tangent-aligned (anisotropic) strokes
   int32_t kappa;     // extra copies of each open-curve endpoint
 } or_params;
 
@@ -119,7 +120,7 @@ typedef struct {
 
 namespace {
 
-enum { F_CLOSED = 1, F_FILLED = 2 };
+enum { F_CLOSED = 1, F_FILLED = 2, F_ANISO = 4 };
 enum { S_NONE = 0, S_KEY_X = 1, S_KEY_Y = 2, S_KEY_W = 3, S_KEY_S = 4, S_TAU = 5, S_OPACITY = 6 };
 enum { P_COUNT = 0, P_NSAMP = 1, P_IX0 = 2, P_IY0 = 3, P_NX = 4, P_NY = 5, P_GOFF = 6, P_FLAG = 7, P_STRIDE = 8 };
 
@@ -406,8 +407,12 @@ void fill_window(const std::vector<double>& bx, const std::vector<double>& by, d
 }
 
 // One Gaussian: centre, sigma, opacity.
+// One Gaussian: centre, sigma (the axis along the curve tangent for a
+// tangent-aligned stroke Gaussian, else the isotropic sigma), opacity, and
+// for a tangent-aligned one the axis across the curve and the tangent
+// direction (isotropic: sp = sigma, t = (1, 0)).
 template <class T>
-struct Gauss { T mx, my, sigma, opacity; };
+struct Gauss { T mx, my, sigma, opacity, sp, tx, ty; };
 
 // Gaussians of curve c for a given plan row, in emission order: open strokes
 // [kappa copies of sample 0, samples 0..M-1, kappa copies of sample M-1];
@@ -425,12 +430,33 @@ void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* 
   const T o = lift<T>(in->opacity[c], seed_kind == S_OPACITY);
   if (!cv.filled) {
     const int kap = cv.closed ? 0 : pr->kappa;
+    const bool aniso = (in->flags[c] & F_ANISO) != 0;
     std::vector<Gauss<T>> smp(ns);
     for (int j = 0; j < ns; ++j) {
       const T u = sample_u(cv, j, ns, cv.closed);
+      const int span = find_span(cv, val(u));
       T pt[3];
-      curve_point(cv, u, find_span(cv, val(u)), pt);
-      smp[j] = Gauss<T>{pt[0], pt[1], pt[2] / T(pr->rho), o};     // Eq. 5
+      curve_point(cv, u, span, pt);
+      const T sg = pt[2] / T(pr->rho);
+      smp[j] = Gauss<T>{pt[0], pt[1], sg, o, sg, T(1.0), T(0.0)};     // Eq. 5
+      if (aniso) {
+        // Tangent-aligned variant of Eq. 5 (the contour sampling of Bezier
+        // Splatting that the paper contrasts with, Sec. 3.2): the axis across
+        // the curve keeps s / rho, the axis along the tangent t = C' / |C'|
+        // (Eq. 2) covers the local sample spacing |C'| du with the same
+        // overlap ratio rho, and never falls below the axis across it.
+        std::vector<T> Dx, Dy;
+        curve_derivs(cv, u, span, 1, Dx, Dy);
+        const T len = sqrt(Dx[1] * Dx[1] + Dy[1] * Dy[1]);
+        const T a = cv.U[cv.p], b = cv.U[cv.m - cv.p];
+        const T du = (b - a) / T((double)(cv.closed ? ns : ns - 1));
+        if (val(len) > 0.0) {
+          smp[j].tx = Dx[1] / len;
+          smp[j].ty = Dy[1] / len;
+          const T along = len * du / T(pr->rho);
+          if (val(along) > val(sg)) smp[j].sigma = along;
+        }
+      }
     }
     for (int k = 0; k < kap; ++k) out.push_back(smp[0]);
     for (int j = 0; j < ns; ++j) out.push_back(smp[j]);
@@ -443,12 +469,12 @@ void curve_gaussians(const or_curves* in, const or_scenes* sc, const or_params* 
     for (int iy = 0; iy < plan_row[P_NY]; ++iy)
       for (int ix = 0; ix < plan_row[P_NX]; ++ix) {
         if (need && !(*need)[out.size()]) {
-          out.push_back(Gauss<T>{T(0.0), T(0.0), T(0.0), T(0.0)});
+          out.push_back(Gauss<T>{T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(1.0), T(0.0)});
           continue;
         }
         const double qx = (plan_row[P_IX0] + ix + 0.5) * h, qy = (plan_row[P_IY0] + iy + 0.5) * h;
         const T z = T(pr->gamma / h) * sdf(qx, qy, bx, by);
-        out.push_back(Gauss<T>{T(qx), T(qy), sig, o * sigmoid(z)});   // Eq. 7
+        out.push_back(Gauss<T>{T(qx), T(qy), sig, o * sigmoid(z), sig, T(1.0), T(0.0)});   // Eq. 7
       }
   }
   (void)sc;
@@ -474,12 +500,19 @@ std::vector<int64_t> scene_ranges(const or_curves* in, const int32_t* plan, int 
 // resolution of every quantity they would be added to.  If `up` is given the
 // adjoint of sum_c up_c I_c is added into adj[g][0..6] =
 // (d/dmx, d/dmy, d/dsigma, d/dopacity, d/dcolour[0..2]).
-struct Hit { int64_t g; double a, G, dx, dy, d2, T; };
+// One composited (pixel, Gaussian) pair: the Gaussian, its alpha and G, the
+// offset from its centre, and for a tangent-aligned Gaussian the offsets
+// along (dp) and across (dq) the tangent.
+// Per-Gaussian adjoint slots: mx, my, sigma, opacity, colour (3), sp, theta.
+constexpr int NADJ = 9;
+
+struct Hit { int64_t g; double a, G, dx, dy, d2, T, dp, dq; bool an; };
 
 void composite_pixel(const or_curves* in, const or_params* pr, int C, const double* bg,
                      const double* mx, const double* my, const double* sg, const double* op,
-                     const int32_t* gcurve, int64_t g0, int64_t g1, double px, double py,
-                     double* img, double* Tout, const double* up, double* adj, double* adjabs) {
+                     const double* sp, const double* tdir, const int32_t* gcurve, int64_t g0, int64_t g1,
+                     double px, double py, double* img, double* Tout, const double* up, double* adj,
+                     double* adjabs) {
   std::vector<Hit> hits;
   double T = 1.0;
   double acc[3] = {0, 0, 0};
@@ -487,13 +520,29 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
     const double dx = px - mx[g], dy = py - my[g];
     const double d2 = dx * dx + dy * dy;
     const double s2 = sg[g] * sg[g];
-    if (pr->cutoff > 0.0 && d2 > pr->cutoff * pr->cutoff * s2) continue;
-    if (d2 > 150.0 * s2) continue;  // exp(-75): below FP64 resolution
-    const double G = std::exp(-d2 / (2.0 * s2));
+    const bool an = sp && (in->flags[gcurve[g]] & F_ANISO);
+    double G, dp = 0.0, dq = 0.0;
+    if (!an) {
+      // Eq. 9
+      if (pr->cutoff > 0.0 && d2 > pr->cutoff * pr->cutoff * s2) continue;
+      if (d2 > 150.0 * s2) continue;  // exp(-75): below FP64 resolution
+      G = std::exp(-d2 / (2.0 * s2));
+    } else {
+      // Eq. 9 with the covariance R diag(sigma^2, sp^2) R^T, R the rotation
+      // to the tangent t: exp(-(dp^2 / sigma^2 + dq^2 / sp^2) / 2), dp and dq
+      // the offsets along t and along the normal n = (-t_y, t_x)
+      const double tx = tdir[2 * g], ty = tdir[2 * g + 1];
+      dp = dx * tx + dy * ty;
+      dq = dy * tx - dx * ty;
+      const double m2 = dp * dp / s2 + dq * dq / (sp[g] * sp[g]);
+      if (pr->cutoff > 0.0 && m2 > pr->cutoff * pr->cutoff) continue;
+      if (m2 > 150.0) continue;
+      G = std::exp(-0.5 * m2);
+    }
     const double a = std::min(pr->alpha_max, op[g] * G);
     const double* col = in->color + (size_t)C * gcurve[g];
     for (int k = 0; k < C; ++k) acc[k] += col[k] * a * T;
-    if (up) hits.push_back(Hit{g, a, G, dx, dy, d2, T});
+    if (up) hits.push_back(Hit{g, a, G, dx, dy, d2, T, dp, dq, an});
     T = T * (1.0 - a);
     if (T < pr->eps_T) break;
   }
@@ -510,26 +559,48 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
     double dLda = 0.0, sabs = 0.0;
     for (int k = 0; k < C; ++k) {
       dLda += up[k] * (col[k] * e.T - R[k] / (1.0 - e.a));
-      adj[7 * e.g + 4 + k] += up[k] * e.a * e.T;
+      adj[NADJ * e.g + 4 + k] += up[k] * e.a * e.T;
       // the magnitude of the terms dL/dalpha is formed from: the scale of
       // its rounding error in any evaluation order
       sabs += std::fabs(up[k]) * (std::fabs(col[k]) * e.T + std::fabs(R[k]) / (1.0 - e.a));
-      if (adjabs) adjabs[7 * e.g + 4 + k] += std::fabs(up[k]) * e.a * e.T;
+      if (adjabs) adjabs[NADJ * e.g + 4 + k] += std::fabs(up[k]) * e.a * e.T;
     }
     for (int k = 0; k < C; ++k) R[k] += col[k] * e.a * e.T;
     if (op[e.g] * e.G < pr->alpha_max) {          // clamp inactive
       const double s = sg[e.g];
       const double dLdG = dLda * op[e.g];
-      adj[7 * e.g + 3] += dLda * e.G;
-      adj[7 * e.g + 0] += dLdG * e.G * e.dx / (s * s);   // dG/dmx = G (x - mx) / s^2
-      adj[7 * e.g + 1] += dLdG * e.G * e.dy / (s * s);
-      adj[7 * e.g + 2] += dLdG * e.G * e.d2 / (s * s * s);
+      double* A = adj + NADJ * e.g;
+      A[3] += dLda * e.G;
+      // partials of G: w.r.t. (mx, my, sigma) and, tangent-aligned, sp and the
+      // tangent angle theta (t = (cos theta, sin theta))
+      double pg[5];
+      if (!e.an) {
+        pg[0] = e.dx / (s * s);           // dG/dmx = G (x - mx) / s^2
+        pg[1] = e.dy / (s * s);
+        pg[2] = e.d2 / (s * s * s);
+        pg[3] = pg[4] = 0.0;
+      } else {
+        const double q = sp[e.g], tx = tdir[2 * e.g], ty = tdir[2 * e.g + 1];
+        pg[0] = e.dp * tx / (s * s) - e.dq * ty / (q * q);
+        pg[1] = e.dp * ty / (s * s) + e.dq * tx / (q * q);
+        pg[2] = e.dp * e.dp / (s * s * s);
+        pg[3] = e.dq * e.dq / (q * q * q);
+        pg[4] = e.dp * e.dq * (1.0 / (q * q) - 1.0 / (s * s));
+      }
+      A[0] += dLdG * e.G * pg[0];
+      A[1] += dLdG * e.G * pg[1];
+      A[2] += dLdG * e.G * pg[2];
+      A[7] += dLdG * e.G * pg[3];
+      A[8] += dLdG * e.G * pg[4];
       if (adjabs) {
         const double sG = sabs * op[e.g] * e.G;
-        adjabs[7 * e.g + 3] += sabs * e.G;
-        adjabs[7 * e.g + 0] += sG * std::fabs(e.dx) / (s * s);
-        adjabs[7 * e.g + 1] += sG * std::fabs(e.dy) / (s * s);
-        adjabs[7 * e.g + 2] += sG * e.d2 / (s * s * s);
+        double* B = adjabs + NADJ * e.g;
+        B[3] += sabs * e.G;
+        B[0] += sG * std::fabs(pg[0]);
+        B[1] += sG * std::fabs(pg[1]);
+        B[2] += sG * pg[2];
+        B[7] += sG * pg[3];
+        B[8] += sG * std::fabs(pg[4]);
       }
     }
   }
@@ -659,7 +730,9 @@ int64_t or_plan(const or_curves* in, const or_scenes* sc, const or_params* pr, i
   for (int c = 0; c < N; ++c) {
     int32_t* row = plan + P_STRIDE * c;
     for (int k = 0; k < P_STRIDE; ++k) row[k] = 0;
-    if (!values_in_domain(in, c)) {
+    // values outside the domain of Sec. 3.1, or a tangent-aligned fill (the
+    // variant concerns contour samples only): no Gaussians, flag 2
+    if (!values_in_domain(in, c) || ((in->flags[c] & F_ANISO) && (in->flags[c] & F_FILLED))) {
       L[c] = 0.0;
       row[P_FLAG] = 2;
       continue;
@@ -670,7 +743,8 @@ int64_t or_plan(const or_curves* in, const or_scenes* sc, const or_params* pr, i
     L[c] = len;
     int flag = 0;
     if (!cv.filled) {
-      const int M = count_rule(pr->delta_c, len, cv.closed ? 3 : 2, &flag);
+      const double delta = (in->flags[c] & F_ANISO) ? pr->delta_a : pr->delta_c;
+      const int M = count_rule(delta, len, cv.closed ? 3 : 2, &flag);
       row[P_NSAMP] = M;
       row[P_COUNT] = cv.closed ? M : M + 2 * pr->kappa;
     } else {
@@ -696,7 +770,8 @@ int64_t or_plan(const or_curves* in, const or_scenes* sc, const or_params* pr, i
 // Gaussians for a plan (frozen or fresh): centres, sigma, opacity, owning
 // curve, index within the curve.
 int64_t or_gaussians(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
-                     double* mu, double* sigma, double* opacity, int32_t* curve, int32_t* local) {
+                     double* mu, double* sigma, double* opacity, int32_t* curve, int32_t* local, double* sp,
+                     double* tdir) {
   const int N = in->n_curves;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int c = 0; c < N; ++c) {
@@ -710,6 +785,11 @@ int64_t or_gaussians(const or_curves* in, const or_scenes* sc, const or_params* 
       opacity[g0 + j] = gs[j].opacity;
       curve[g0 + j] = c;
       local[g0 + j] = (int32_t)j;
+      if (sp) sp[g0 + j] = gs[j].sp;
+      if (tdir) {
+        tdir[2 * (g0 + j)] = gs[j].tx;
+        tdir[2 * (g0 + j) + 1] = gs[j].ty;
+      }
     }
   }
   int64_t total = 0;
@@ -768,12 +848,14 @@ int64_t or_bin(int64_t G, const double* mu, const double* sigma, const int32_t* 
 // Compositing (Eq. 8-9).  pix == NULL: every pixel of every scene; image
 // layout per scene [C][H][W] concatenated, T_final [H][W] concatenated.
 // Otherwise npix pixels given as (scene, y, x) triples, outputs [npix][C] and
-// [npix].  If up != NULL (same layout as img), adj [G][7] receives the
-// adjoint of sum(up * I) with respect to every Gaussian (it is zeroed first).
+// [npix].  If up != NULL (same layout as img), adj [G][9] receives the
+// adjoint of sum(up * I) with respect to every Gaussian (mx, my, sigma,
+// opacity, colour (3), sp, theta; it is zeroed first).  sp and tdir ([G],
+// [G][2]) describe tangent-aligned Gaussians (NULL: every Gaussian isotropic).
 int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, const int32_t* plan,
-                 const double* mu, const double* sigma, const double* opacity, const int32_t* gcurve,
-                 int64_t G, int64_t npix, const int32_t* pix, double* img, double* Tfin,
-                 const double* up, double* adj, double* adjabs) {
+                 const double* mu, const double* sigma, const double* opacity, const double* sp,
+                 const double* tdir, const int32_t* gcurve, int64_t G, int64_t npix, const int32_t* pix,
+                 double* img, double* Tfin, const double* up, double* adj, double* adjabs) {
   const int C = in->channels;
   const std::vector<int64_t> sr = scene_ranges(in, plan, sc->n_scenes);
   std::vector<double> mx(G), my(G);
@@ -816,8 +898,8 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
 #endif
     double* my_adj = nullptr;
     double* my_abs = nullptr;
-    if (up) { adj_t[tid].assign((size_t)7 * G, 0.0); my_adj = adj_t[tid].data(); }
-    if (up && adjabs) { abs_t[tid].assign((size_t)7 * G, 0.0); my_abs = abs_t[tid].data(); }
+    if (up) { adj_t[tid].assign((size_t)NADJ * G, 0.0); my_adj = adj_t[tid].data(); }
+    if (up && adjabs) { abs_t[tid].assign((size_t)NADJ * G, 0.0); my_abs = abs_t[tid].data(); }
 #pragma omp for schedule(dynamic, 16)
     for (int64_t q = 0; q < npix; ++q) {
       const int s = pix[3 * q], y = pix[3 * q + 1], x = pix[3 * q + 2];
@@ -828,7 +910,7 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
         for (int k = 0; k < C; ++k)
           u[k] = full ? up[img_off[q] + (int64_t)k * H * W] : up[(int64_t)C * q + k];
       }
-      composite_pixel(in, pr, C, sc->bg + (size_t)C * s, mx.data(), my.data(), sigma, opacity, gcurve,
+      composite_pixel(in, pr, C, sc->bg + (size_t)C * s, mx.data(), my.data(), sigma, opacity, sp, tdir, gcurve,
                       sr[2 * s], sr[2 * s + 1], x + 0.5, y + 0.5, v, &T, up ? u : nullptr, my_adj, my_abs);
       for (int k = 0; k < C; ++k) {
         if (full) img[img_off[q] + (int64_t)k * H * W] = v[k];
@@ -838,7 +920,7 @@ int or_composite(const or_curves* in, const or_scenes* sc, const or_params* pr, 
     }
   }
   if (up) {
-    for (int64_t i = 0; i < 7 * G; ++i) {
+    for (int64_t i = 0; i < NADJ * G; ++i) {
       double s = 0.0, a = 0.0;
       for (int t = 0; t < nthreads; ++t) s += adj_t[t][i];
       adj[i] = s;
@@ -867,27 +949,30 @@ static double param_grad_one(const or_curves* in, const or_scenes* sc, const or_
   if (kind >= 7) {
     double s = 0.0, sa = 0.0;
     for (int j = 0; j < row[P_COUNT]; ++j) {
-      s += adj[7 * (g0 + j) + 4 + (kind - 7)];
-      if (adjabs) sa += adjabs[7 * (g0 + j) + 4 + (kind - 7)];
+      s += adj[NADJ * (g0 + j) + 4 + (kind - 7)];
+      if (adjabs) sa += adjabs[NADJ * (g0 + j) + 4 + (kind - 7)];
     }
     if (scale) *scale = sa;
     return s;
   }
   std::vector<char> need(row[P_COUNT]);
   for (int j = 0; j < row[P_COUNT]; ++j) {
-    const double* a = adj + 7 * (g0 + j);
-    need[j] = (a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0 || a[3] != 0.0);
+    const double* a = adj + NADJ * (g0 + j);
+    need[j] = (a[0] != 0.0 || a[1] != 0.0 || a[2] != 0.0 || a[3] != 0.0 || a[7] != 0.0 || a[8] != 0.0);
   }
   std::vector<Gauss<Dual>> gs;
   curve_gaussians<Dual>(in, sc, pr, c, row, kind, index, gs, &need);
   double s = 0.0, sa = 0.0;
   for (size_t j = 0; j < gs.size(); ++j) {
-    const double* a = adj + 7 * (g0 + j);
-    s += a[0] * gs[j].mx.d + a[1] * gs[j].my.d + a[2] * gs[j].sigma.d + a[3] * gs[j].opacity.d;
+    const double* a = adj + NADJ * (g0 + j);
+    // d theta from the tangent's derivative: t = (cos theta, sin theta)
+    const double dth = gs[j].tx.v * gs[j].ty.d - gs[j].ty.v * gs[j].tx.d;
+    s += a[0] * gs[j].mx.d + a[1] * gs[j].my.d + a[2] * gs[j].sigma.d + a[3] * gs[j].opacity.d +
+         a[7] * gs[j].sp.d + a[8] * dth;
     if (adjabs) {
-      const double* b = adjabs + 7 * (g0 + j);
+      const double* b = adjabs + NADJ * (g0 + j);
       sa += b[0] * std::fabs(gs[j].mx.d) + b[1] * std::fabs(gs[j].my.d) + b[2] * std::fabs(gs[j].sigma.d) +
-            b[3] * std::fabs(gs[j].opacity.d);
+            b[3] * std::fabs(gs[j].opacity.d) + b[7] * std::fabs(gs[j].sp.d) + b[8] * std::fabs(dth);
     }
   }
   if (scale) *scale = sa;
