@@ -514,7 +514,7 @@ def cpu_baseline(b, p, target):
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     import oracle
     op = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
-                                                        "fill_pad", "h", "alpha_max", "eps_T")}
+                                                        "fill_pad", "h", "alpha_max", "eps_T", "delta_a")}
     op["kappa"] = int(p.kappa)
     op["cutoff"] = float(p.k_sigma)
     threads = oracle.num_threads()

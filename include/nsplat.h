@@ -57,12 +57,20 @@ extern "C" {
 
 #define NSPLAT_CLOSED 1     /* curve flag: closed (periodic knots, wrapped control polygon) */
 #define NSPLAT_FILLED 2     /* curve flag: filled interior (requires CLOSED) */
+/* curve flag: tangent-aligned (anisotropic) contour Gaussians instead of the
+ * isotropic ones of Eq. 5, the contour sampling of Bezier Splatting that
+ * Sec. 3.2 contrasts with (and the "BS Proto." of the supplementary
+ * comparison): sample j gets the axis s_j / rho across the curve and
+ * max(s_j / rho, |C'(u_j)| du / rho) along t_j = C'(u_j) / |C'(u_j)| (Eq. 2;
+ * du the samples' spacing in u), and the count M = ceil(delta_a L).  A stroke
+ * only: ANISO with FILLED is invalid data. */
+#define NSPLAT_ANISO 4
 #define NSPLAT_MAX_DEGREE 5
 
 /* Version of the structure layouts below; nsplat_abi_version() returns the
  * value the library was built with, so a binding can refuse a library whose
  * structures it would misread. */
-#define NSPLAT_ABI_VERSION 3
+#define NSPLAT_ABI_VERSION 4
 
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
@@ -132,7 +140,7 @@ typedef struct {
                               adjoint kernels with smaller register arrays */
   const int32_t* scene;    /* (dev) [n_curves] scene of each curve           */
   const int32_t* degree;   /* (dev) [n_curves] p                             */
-  const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED */
+  const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED | NSPLAT_ANISO */
   const int32_t* key_off;  /* (dev) [n_curves+1] into the key arrays         */
   const int32_t* tau_off;  /* (dev) [n_curves+1] into tau; open curves hold
                               n_k - p intervals, closed curves n_k           */
@@ -164,6 +172,7 @@ typedef struct {
   float k_sigma;    /* support radius in sigmas (6)                          */
   float alpha_max;  /* per-pixel opacity clamp (0.99)                        */
   float eps_T;      /* a pixel stops once its transmittance drops below, in [0, 1] (1e-6) */
+  float delta_a;    /* contour density of NSPLAT_ANISO strokes, samples per px (0.25) */
   int32_t kappa;    /* extra copies of each open-curve endpoint Gaussian (4) */
   int32_t tile;     /* tile side in px: 8, 16 or 32                          */
   int32_t batch;    /* Gaussians staged in LDS per block step: 32..256       */
@@ -181,7 +190,10 @@ typedef struct {
 typedef struct {
   int32_t* plan;      /* [n_curves][NSPLAT_PLAN_STRIDE]                      */
   void* gauss;        /* [caps.gauss] records of 32 bytes:
-                         {double mx, my; float sigma, opacity; int32 curve, local} */
+                         {double mx, my; float sigma, opacity; int32 curve, local};
+                         sigma is the axis along the tangent for an
+                         NSPLAT_ANISO curve's Gaussians, whose tangent and
+                         axis across the curve live in the workspace */
   int32_t* ranges;    /* [n_tiles][2] slice [begin, end) of idx per tile     */
   int32_t* idx;       /* [caps.pairs] Gaussian indices, ascending within a tile;
                          front-to-back order is the slice read from its end  */
@@ -399,6 +411,20 @@ int nsplat_timing_read(nsplat_ctx* ctx, double* ms, int64_t* count);
 
 /* Copies the counters to host memory and waits for them (synchronising). */
 int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bufs, int32_t* host_out, void* stream);
+
+/* Frame of the tangent-aligned (NSPLAT_ANISO) stroke Gaussians of this
+ * step's nsplat_sample (the contour variant of Eq. 5, Sec. 3.2): for the
+ * first n Gaussians, out[4 g .. 4 g + 3] = (t_x, t_y, sp, sigma / sp): the
+ * unit tangent C'(u) / |C'(u)| that the long axis (the record's sigma) lies
+ * on, or (1, 0) where C'(u) = 0, sp = s(u) / rho, the axis across it, and
+ * the axis ratio (exactly 1 where the two axes agree), each rounded once from
+ * FP64.  The
+ * entries of Gaussians of other kinds are unspecified.  out: dev FP32
+ * [4 n], caller-owned; 0 <= n <= caps.gauss.  An asynchronous device copy on
+ * `stream`.  NSPLAT_EINVAL for bad buffers, n outside that range or a NULL
+ * out with n > 0. */
+int nsplat_gauss_frame(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
+                       const nsplat_buffers* bufs, float* out, int64_t n, void* stream);
 
 /* Autotuner: times nsplat_bin + nsplat_forward + nsplat_backward on the given
  * state for every tile side in {8, 16, 32} and batch depth in

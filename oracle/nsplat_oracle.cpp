@@ -593,14 +593,23 @@ void composite_pixel(const or_curves* in, const or_params* pr, int C, const doub
       A[7] += dLdG * e.G * pg[3];
       A[8] += dLdG * e.G * pg[4];
       if (adjabs) {
+        // the magnitudes of the terms each partial is formed from (for the
+        // tangent-aligned form: its two axes' terms, and both inverse squares)
+        double ab[5] = {std::fabs(pg[0]), std::fabs(pg[1]), pg[2], pg[3], std::fabs(pg[4])};
+        if (e.an) {
+          const double q = sp[e.g], s = sg[e.g], tx = tdir[2 * e.g], ty = tdir[2 * e.g + 1];
+          ab[0] = std::fabs(e.dp * tx) / (s * s) + std::fabs(e.dq * ty) / (q * q);
+          ab[1] = std::fabs(e.dp * ty) / (s * s) + std::fabs(e.dq * tx) / (q * q);
+          ab[4] = std::fabs(e.dp * e.dq) * (1.0 / (q * q) + 1.0 / (s * s));
+        }
         const double sG = sabs * op[e.g] * e.G;
         double* B = adjabs + NADJ * e.g;
         B[3] += sabs * e.G;
-        B[0] += sG * std::fabs(pg[0]);
-        B[1] += sG * std::fabs(pg[1]);
-        B[2] += sG * pg[2];
-        B[7] += sG * pg[3];
-        B[8] += sG * std::fabs(pg[4]);
+        B[0] += sG * ab[0];
+        B[1] += sG * ab[1];
+        B[2] += sG * ab[2];
+        B[7] += sG * ab[3];
+        B[8] += sG * ab[4];
       }
     }
   }

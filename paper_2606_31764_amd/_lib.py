@@ -10,9 +10,9 @@ LIB_PATH = os.path.join(HERE, "libnsplat.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "nsplat.h")
 
 OK, EINVAL, ECAPACITY, EHIP = 0, 1, 2, 3
-CLOSED, FILLED = 1, 2
+CLOSED, FILLED, ANISO = 1, 2, 4
 MAX_DEGREE = 5
-ABI_VERSION = 3  # NSPLAT_ABI_VERSION of include/nsplat.h
+ABI_VERSION = 4  # NSPLAT_ABI_VERSION of include/nsplat.h
 CNT_GAUSS, CNT_PAIRS, CNT_STATUS, CNT_GAUSS_REQ, CNT_PAIRS_REQ, CNT_BOUND_REQ, CNT_BOUND = range(7)
 NUM_COUNTERS = 16
 STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA, STATUS_VALUE = 1, 2, 4, 8, 16
@@ -36,7 +36,7 @@ class Scenes(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor", "fill_pad",
-                                               "h", "k_sigma", "alpha_max", "eps_T")] + [
+                                               "h", "k_sigma", "alpha_max", "eps_T", "delta_a")] + [
         ("kappa", ctypes.c_int32), ("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("h_dev", vp)]
 
 
@@ -90,6 +90,7 @@ _SIGS = {
                                        ctypes.c_float, ctypes.c_float, vp]),
     "nsplat_l2_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, vp]),
     "nsplat_read_counters": (ctypes.c_int, [vp, vp, vp, vp]),
+    "nsplat_gauss_frame": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, vp]),
     "nsplat_autotune": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp]),
 }
 

@@ -6,6 +6,9 @@
 //                   triangle: control points, weights, widths, the 2p knots of
 //                   the span, and dL/du_j -> the domain ends u_p, u_{m-p}
 //                   (u_j is uniform in the domain).
+//   k_adj_aniso     one lane per tangent-aligned stroke Gaussian: the same,
+//                   plus dL/d(sp, theta) and the spacing term of sigma through
+//                   the first derivative C'(u_j) and the domain ends.
 //   k_adj_fill      one lane per fill Gaussian: dL/do_j -> curve opacity and,
 //                   through the sigmoid and the SDF (Eq. 7, S1-S3, sign
 //                   detached, nearest segment), the two end points of the
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_par
     if (g < G) {
       const Gauss r = gs[g];
       c = r.curve;
-      if (!(cv.flags[c] & NSPLAT_FILLED)) {
+      if (!(cv.flags[c] & (NSPLAT_FILLED | NSPLAT_ANISO))) {
         stroke = true;
         v = curve_view(cv, w.knots, c);
         const float* gg = w.ggrad + g * GG;
@@ -532,10 +535,12 @@ constexpr int MAXR = 3;  // highest derivative order of the derivative loss
 // derivative; and the rational Leibniz rule
 //   C^(k) = (A^(k) - sum_{i=1..k} binom(k, i) W^(i) C^(k-i)) / W, (A, W) = S.
 // Reverse: the same steps backwards, with the adjoint of the degree p - k
-// basis functions entering the Cox-de Boor triangle at its level p - k.
+// basis functions entering the Cox-de Boor triangle at its level p - k.  With
+// `up` set, the reverse pass starts from the given adjoint up[0..1] of
+// C^(r)(u) instead of that of the value (whose scale is then unused).
 template <int PD>
 __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView& v, double u, int span, int r,
-                                       double scale, PtAdj<PD>& out) {
+                                       double scale, PtAdj<PD>& out, const double* up = nullptr) {
   const double* U = v.U;
   const int p = v.p;
   const int R = r < p ? r : p;
@@ -627,8 +632,8 @@ __device__ inline double deriv_adjoint(const nsplat_curves& cv, const CurveView&
     dCx[k] = dCy[k] = 0.0;
     dS[k][0] = dS[k][1] = dS[k][2] = 0.0;
   }
-  dCx[r] = 2.0 * scale * Cx[r];
-  dCy[r] = 2.0 * scale * Cy[r];
+  dCx[r] = up ? up[0] : 2.0 * scale * Cx[r];
+  dCy[r] = up ? up[1] : 2.0 * scale * Cy[r];
 #pragma unroll
   for (int k = MAXR; k >= 0; --k) {
     if (k > r) continue;
@@ -975,6 +980,97 @@ __global__ __launch_bounds__(256, PD <= 3 ? 2 : 1) void k_reg_boundary(nsplat_cu
   block_loss(lb, ld, ra.loss);
 }
 
+// Tangent-aligned stroke Gaussians: centre mu = C(u_j), sp = s(u_j) / rho
+// across the curve, sigma = max(sp, |C'(u_j)| du / rho) along
+// t = C'(u_j) / |C'(u_j)| = (cos theta, sin theta), du the sample spacing.
+// dL/d(mu, sp) and, where sigma = sp, dL/dsigma go to the point adjoint;
+// dL/dtheta (d theta / d C' = n / |C'|, n = (-t_y, t_x)) and, where the
+// spacing term is the larger, dL/dsigma (d sigma / d C' = t du / rho) go to
+// the adjoint of the first derivative C'(u_j), whose reverse pass is that of
+// the derivative loss; dL/d du = dL/dsigma |C'| / rho goes to the domain
+// ends (du = (u_{m-p} - u_p) / (M - 1), or / M closed).
+template <int PD>
+__global__ __launch_bounds__(256) void k_adj_aniso(nsplat_curves cv, nsplat_params pr, Work w,
+                                                   const int32_t* plan, const int32_t* counters,
+                                                   const Gauss* __restrict__ gs) {
+  if (w.queue[Q_NANISO] == 0) return;  // no Gaussians of this kind
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const int lane = __lane_id();
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const double rho = (double)pr.rho;
+  for (int64_t base = wave0; base < G; base += stride) {
+    const int64_t g = base + lane;
+    int64_t kspan = -1 - lane, kcur = -1 - lane;
+    double cur[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    PtAdj<PD> pa;
+    int c = 0, span = 0;
+    CurveView v;
+    v.p = 0;
+    bool act = false;
+    if (g < G) {
+      const Gauss r = gs[g];
+      c = r.curve;
+      if ((cv.flags[c] & (NSPLAT_FILLED | NSPLAT_ANISO)) == NSPLAT_ANISO) {
+        act = true;
+        v = curve_view(cv, w.knots, c);
+        const float* gg = w.ggrad + g * GG;
+        const int32_t* row = plan + (int64_t)P_STRIDE * c;
+        const int M = row[P_NSAMP];
+        int j = v.closed() ? r.local : r.local - pr.kappa;
+        j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
+        double dt;
+        const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), &dt);
+        span = find_span(v.U, v.p, v.m, u);
+        double pt[3], d[3];
+        curve_point(cv, v, u, span, pt, d);
+        const double len = sqrt(d[0] * d[0] + d[1] * d[1]);
+        const double den = (double)(v.closed() ? M : M - 1);
+        const double du = (v.U[v.m - v.p] - v.U[v.p]) / den;
+        const double sp = pt[2] / rho;
+        const bool wide = len > 0.0 && len * du / rho > sp;  // the spacing term sets sigma
+        const double gsig = (double)gg[2], gsp = (double)gg[3], gth = (double)gg[4];
+        const double ab[3] = {(double)gg[0], (double)gg[1], (gsp + (wide ? 0.0 : gsig)) / rho};
+        point_adjoint(cv, v, u, span, ab, pa);
+        double ddu = 0.0;
+        if (len > 0.0) {
+          const double tx = d[0] / len, ty = d[1] / len;
+          double up[2] = {-ty * gth / len, tx * gth / len};
+          if (wide) {
+            up[0] += gsig * tx * du / rho;
+            up[1] += gsig * ty * du / rho;
+            ddu = gsig * len / rho;
+          }
+          PtAdj<PD> pd;
+          deriv_adjoint(cv, v, u, span, 1, 0.0, pd, up);
+#pragma unroll
+          for (int q = 0; q <= PD; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pa.cp[q][k] += pd.cp[q][k];
+#pragma unroll
+          for (int k = 0; k < 2 * PD; ++k) pa.knot[k] += pd.knot[k];
+          pa.ubar += pd.ubar;
+        }
+        cur[4] = pa.ubar * (1.0 - dt) - ddu / den;  // u_j = u_p + t_j (u_{m-p} - u_p)
+        cur[5] = pa.ubar * dt + ddu / den;
+        kspan = (int64_t)v.t0 + (int64_t)c * KNOT_PAD + span;
+        kcur = c;
+      }
+    }
+    if (!act) {
+#pragma unroll
+      for (int q = 0; q <= PD; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pa.cp[q][k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2 * PD; ++k) pa.knot[k] = 0.0;
+    }
+    const bool any = __ballot(act) != 0ull;
+    accumulate_points(w, kspan, c, v, span, pa, any);
+    if (any) accumulate_curve(w, kcur, c, v, cur);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_zero_grads(const Launch& L) {
@@ -1018,6 +1114,12 @@ void launch_adj_stroke_d(const Launch& L) {
 }
 
 template <int PD>
+void launch_adj_aniso_d(const Launch& L) {
+  hipLaunchKernelGGL(k_adj_aniso<PD>, dim3(grid_for(L.bf->caps.gauss, 256, 4096)), dim3(256), 0, L.stream, *L.cv,
+                     *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+}
+
+template <int PD>
 void launch_adj_boundary_d(const Launch& L) {
   hipLaunchKernelGGL(k_adj_boundary<PD>, dim3(grid_for(L.bf->caps.boundary, 256, 4096)), dim3(256), 0, L.stream,
                      *L.cv, L.w, L.bf->plan, L.bf->counters);
@@ -1040,8 +1142,13 @@ hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g) {
   {
     Phase ph(L, NSPLAT_T_ADJ_GAUSS);
-    if (low_degree(L)) launch_adj_stroke_d<3>(L);
-    else launch_adj_stroke_d<MAXP>(L);
+    if (low_degree(L)) {
+      launch_adj_stroke_d<3>(L);
+      launch_adj_aniso_d<3>(L);
+    } else {
+      launch_adj_stroke_d<MAXP>(L);
+      launch_adj_aniso_d<MAXP>(L);
+    }
     hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
                        *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
   }

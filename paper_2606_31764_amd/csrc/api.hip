@@ -64,6 +64,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
       sizeof(double) * SEG_WORDS * (size_t)(bcap + (SDF_CHUNK - 1) * N + 1),  // segs
+      sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gaux
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -104,6 +105,7 @@ Work carve(void* ws, const Layout& lay) {
   w.ckbuf = (float*)(b + lay.off[24]);
   w.gcol = (float4*)(b + lay.off[25]);
   w.segs = (double*)(b + lay.off[26]);
+  w.gaux = (float4*)(b + lay.off[27]);
   return w;
 }
 
@@ -203,8 +205,9 @@ int check_params(nsplat_ctx* ctx, const nsplat_params* pr) {
     return fail(ctx, NSPLAT_EINVAL, "tile must be 8, 16 or 32 (got %d)", pr->tile);
   if (pr->batch < 1 || pr->batch > MAX_BATCH)
     return fail(ctx, NSPLAT_EINVAL, "batch must be in [1, %d] (got %d)", MAX_BATCH, pr->batch);
-  if (!(pr->rho > 0.f) || !(pr->delta_c > 0.f) || !(pr->delta_b > 0.f) || !(pr->eta > 0.f) || !(pr->nl_factor > 0.f))
-    return fail(ctx, NSPLAT_EINVAL, "rho, delta_c, delta_b, eta and nl_factor must be > 0");
+  if (!(pr->rho > 0.f) || !(pr->delta_c > 0.f) || !(pr->delta_b > 0.f) || !(pr->eta > 0.f) ||
+      !(pr->nl_factor > 0.f) || !(pr->delta_a > 0.f))
+    return fail(ctx, NSPLAT_EINVAL, "rho, delta_c, delta_b, delta_a, eta and nl_factor must be > 0");
   if (!(pr->h > 0.f) && !pr->h_dev) return fail(ctx, NSPLAT_EINVAL, "h must be > 0");
   if (!(pr->alpha_max > 0.f && pr->alpha_max < 1.f))
     return fail(ctx, NSPLAT_EINVAL, "alpha_max must be in (0, 1) (got %g)", (double)pr->alpha_max);
@@ -507,6 +510,24 @@ int nsplat_read_counters(nsplat_ctx* ctx, const nsplat_buffers* bf, int32_t* hos
                                 hipMemcpyDeviceToHost, (hipStream_t)stream);
   if (h == hipSuccess) h = hipStreamSynchronize((hipStream_t)stream);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_read_counters");
+  return NSPLAT_OK;
+}
+
+int nsplat_gauss_frame(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_buffers* bf,
+                       float* out, int64_t n, void* stream) {
+  if (!ctx) return NSPLAT_EINVAL;
+  int e;
+  if ((e = check_curves(ctx, cv)) || (e = check_scenes(ctx, sc)) || (e = check_bufs(ctx, cv, sc, bf))) return e;
+  if (n < 0 || n > bf->caps.gauss)
+    return fail(ctx, NSPLAT_EINVAL, "n = %lld outside [0, caps.gauss = %lld]", (long long)n,
+                (long long)bf->caps.gauss);
+  if (n == 0) return NSPLAT_OK;
+  if (!out) return fail(ctx, NSPLAT_EINVAL, "out is NULL");
+  const Layout lay = workspace_layout(cv, sc, &bf->caps);
+  const Work w = carve(bf->ws, lay);
+  const hipError_t h = hipMemcpyAsync(out, w.gaux, sizeof(float4) * (size_t)n, hipMemcpyDeviceToDevice,
+                                      (hipStream_t)stream);
+  if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_gauss_frame");
   return NSPLAT_OK;
 }
 

@@ -55,7 +55,7 @@ __device__ inline int next_item(int it, int persistent, int32_t* queue) {
 struct Entry {
   Gauss r;
   float c0, c1, c2;
-  int g, fill;
+  int g, kind;  // kind: 0 isotropic stroke, 1 fill, 2 tangent-aligned stroke
 };
 
 // Record and colour of Gaussian g.
@@ -66,7 +66,7 @@ __device__ inline void load_rec(const Gauss* __restrict__ gs, const float4* __re
   e->c0 = cf.x;
   e->c1 = cf.y;
   e->c2 = cf.z;
-  e->fill = cf.w != 0.0f;
+  e->kind = (int)cf.w;
 }
 
 // The entry's record and its curve's colour / fill tag (both by Gaussian
@@ -133,6 +133,25 @@ __device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, floa
   return dx * dx + dy * dy <= rc * rc;
 }
 
+// A tangent-aligned Gaussian (axis sigma along t, sp across it, sigma >= sp)
+// is evaluated as exp2(-(a^2 + b^2)) with a = d . u and b = r (d x u), d the
+// offset from the centre: u = t sqrt(ck) / sigma, r = sigma / sp, and
+// ck = log2(e) / 2, so that a^2 + b^2 = ck (d_t^2 / sigma^2 + d_n^2 / sp^2).
+// The support is a^2 + b^2 <= ck k_sigma^2, inside the disc of radius
+// k_sigma sigma that binning and culling use.  Entries are staged like the
+// others (exp2 coefficient -ck / sigma^2); a wavefront converts the entries
+// of a run of such a curve when it reaches them, reading (t, sp, r) by
+// Gaussian index, so that the other kinds carry no extra loads.  Where the
+// two axes agree r is exactly 1 and the theta partial exactly 0.
+constexpr float ANI_CK = (float)(0.5 * LOG2E);
+constexpr float ANI_SQRT_CK = 0.8493218002880191f;  // sqrt(log2(e) / 2)
+__device__ inline void aniso_axes(const float4& aux, float coef, float* ux, float* uy, float* r) {
+  const float k = __builtin_sqrtf(-coef);  // sqrt(ck) / sigma
+  *ux = aux.x * k;
+  *uy = aux.y * k;
+  *r = aux.w;  // sigma / sp, rounded once from FP64 (exactly 1 where the axes agree)
+}
+
 __device__ inline uint64_t lanes_below() {
   const int lane = __lane_id();
   return lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -142,9 +161,10 @@ __device__ inline uint64_t lanes_below() {
 // A forward entry: what every composited pixel reads, in one 32-byte record
 // (one LDS address per entry), and the colour, read where a run begins.
 struct FwdRec {
-  float4 geo;          // tile-local centre, squared support radius, exp2 coefficient
-  float op;            // opacity
-  int pos, curve, pad;  // list position, curve
+  float4 geo;      // tile-local centre, squared support radius, exp2 coefficient
+                   // (tangent-aligned: centre, scaled axis u)
+  float op;           // opacity
+  int pos, curve, g;  // list position, curve, Gaussian
 };
 constexpr int FWD_ENTRY_BYTES = sizeof(FwdRec) + 16;
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
@@ -204,7 +224,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     // depend on the batch depth.
     float px[PPT], py[PPT], T[PPT], Tst[PPT], acc[PPT][3];
     int stop[PPT];
-    int run_curve = -1;
+    int run_curve = -1, run_kind = 0;
     float rc0 = 0.0f, rc1 = 0.0f, rc2 = 0.0f;  // the run's colour
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
 #pragma unroll
@@ -257,9 +277,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           rec.op = e[u].r.opacity;
           rec.pos = mypos;
           rec.curve = e[u].r.curve;
-          rec.pad = 0;
+          rec.g = e[u].g;
           wrec[dst] = rec;
-          wcol[dst] = make_float4(e[u].c0, e[u].c1, e[u].c2, 0.0f);
+          wcol[dst] = make_float4(e[u].c0, e[u].c1, e[u].c2, (float)e[u].kind);
         }
         cnt += __popcll(m);
       }
@@ -310,6 +330,40 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           rc1 = pc.y;
           rc2 = pc.z;
           run_curve = wrec[j].curve;
+          run_kind = __builtin_amdgcn_readfirstlane((int)pc.w);
+        }
+        if (run_kind == 2) {
+          // tangent-aligned strokes (elliptical Eq. 9): the segment's entries
+          // take their axis u and the ratio r (in place of the kind)
+          for (int i = j + lane; i < jend; i += 64) {
+            const float4 ax = w.gaux[wrec[i].g];
+            float ux, uy, rq;
+            aniso_axes(ax, wrec[i].geo.w, &ux, &uy, &rq);
+            wrec[i].geo.z = ux;
+            wrec[i].geo.w = uy;
+            wcol[i].w = rq;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const float lim = ANI_CK * ks * ks;
+          for (; j < jend; ++j) {
+            const float4 gm = wrec[j].geo;
+            const float op = wrec[j].op, rq = wcol[j].w;
+            const int pos = wrec[j].pos;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+              const float dx = px[q] - gm.x, dy = py[q] - gm.y;
+              const float a = __builtin_fmaf(dx, gm.z, dy * gm.w);
+              const float b = rq * __builtin_fmaf(dy, gm.z, -(dx * gm.w));
+              const float m = __builtin_fmaf(a, a, b * b);
+              const float G = __builtin_amdgcn_exp2f(-m);
+              const bool in = (m <= lim) && (T[q] >= eps);
+              const float Tn = T[q] * (1.0f - fminf(amax, op * G));
+              stop[q] = (in && Tn < eps) ? pos : stop[q];
+              T[q] = in ? Tn : T[q];
+            }
+          }
         }
 #pragma unroll 8
         for (; j < jend; ++j) {
@@ -633,7 +687,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
     const int lo = max(wave_min(my_lo), c_lo);
     if (c_hi <= lo) continue;
     int cur = -1, since = 0;
-    bool cur_fill = false;
+    bool cur_fill = false, cur_aniso = false;
     // per pixel: K of the current curve, W (fixed over a run of one curve),
     // and the run's sum of alpha T (the curve's colour gradient is dL/dI_c
     // times it)
@@ -673,10 +727,11 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         if (keep) {
           const int dst = cnt + __popcll(m & below);
           const double sg = (double)e[u].r.sigma;
+          // tangent-aligned entries: -1 (negative: the kind) in place of 1 / sigma^3
+          const float wbits = e[u].kind == 2 ? -1.0f : (float)(1.0 / (sg * sg * sg));
           wgeo[dst] = geo;
           wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
-          wmeta[dst] = make_int4(e[u].fill ? ~e[u].g : e[u].g, e[u].r.curve, mypos,
-                                 __float_as_int((float)(1.0 / (sg * sg * sg))));
+          wmeta[dst] = make_int4(e[u].kind == 1 ? ~e[u].g : e[u].g, e[u].r.curve, mypos, __float_as_int(wbits));
         }
         cnt += __popcll(m);
       }
@@ -724,9 +779,82 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           }
           cur = __builtin_amdgcn_readfirstlane(mt.y);
           cur_fill = __builtin_amdgcn_readfirstlane(mt.x) < 0;
+          cur_aniso = !cur_fill && __builtin_amdgcn_readfirstlane(mt.w) < 0;
           since = 0;
         }
-        if (cur_fill) {
+        if (cur_aniso) {
+          // tangent-aligned stroke Gaussians: dL/dmu (2), dL/dsigma, dL/dsp
+          // and dL/dtheta (t = (cos theta, sin theta)) parked in five rows.
+          // With h = dL/dG G / ck: dG/dmu = (a u - b r u^perp) 2 ln 2 G, and so
+          // on (the partials of exp(-(d_t^2 / sigma^2 + d_n^2 / sp^2) / 2)
+          // rewritten in a, b).
+          // the segment's entries take their axis u (in place of the support
+          // radius and coefficient) and -r (in place of the kind)
+          for (int i = j + lane; i < jend; i += 64) {
+            const float4 ax = w.gaux[wmeta[i].x];
+            float ux, uy, rq;
+            aniso_axes(ax, wgeo[i].w, &ux, &uy, &rq);
+            wgeo[i].z = ux;
+            wgeo[i].w = uy;
+            wmeta[i].w = __float_as_int(-rq);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const float lim = ANI_CK * ks * ks;
+          const float two_ln2 = 2.0f * ln2;
+          for (; j < jend; ++j) {
+            if (since >= FLUSH) {
+              flush_curve<C, PPT>(w.gcurve, cur, false, gI, aT, accO);
+              since = 0;
+            }
+            ++since;
+            const float4 gm = wgeo[j];
+            const float op = wop[4 * j];
+            const int4 mt = wmeta[j];
+            const float rq = -__int_as_float(mt.w);
+            const float isg = __builtin_sqrtf(__builtin_fmaf(gm.z, gm.z, gm.w * gm.w)) * (1.0f / ANI_SQRT_CK);
+            const float isp = isg * rq;           // 1 / sp
+            const float rr = rq - 1.0f / rq;      // sigma / sp - sp / sigma
+            const float rux = rq * gm.z, ruy = rq * gm.w;
+            float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            bool act = false;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+              const float dx = px[q] - gm.x, dy = py[q] - gm.y;
+              const float a = __builtin_fmaf(dx, gm.z, dy * gm.w);
+              const float b = rq * __builtin_fmaf(dy, gm.z, -(dx * gm.w));
+              const float m = __builtin_fmaf(a, a, b * b);
+              const bool in = (mt.z >= stop[q]) && (m <= lim);
+              act = act || in;
+              const float G = __builtin_amdgcn_exp2f(-m);
+              const float oG = op * G;
+              const bool lt = oG < amax;
+              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+              const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
+              T[q] = in ? T[q] * r : T[q];
+              aT[q] = __builtin_fmaf(alpha, T[q], aT[q]);
+              v[5] = __builtin_fmaf(dLda, G, v[5]);  // dL/do_j
+              const float h = dLda * op * G * two_ln2;
+              v[0] = __builtin_fmaf(h, __builtin_fmaf(a, gm.z, -(b * ruy)), v[0]);
+              v[1] = __builtin_fmaf(h, __builtin_fmaf(a, gm.w, b * rux), v[1]);
+              v[2] = __builtin_fmaf(h * a, a * isg, v[2]);
+              v[3] = __builtin_fmaf(h * b, b * isp, v[3]);
+              v[4] = __builtin_fmaf(h * a, b * rr, v[4]);
+            }
+            if (__ballot(act) == 0ull) continue;
+            if (n_rows + 5 > RB) {
+              flush_rows<RB>(park, ptgt, n_rows, ggrad);
+              n_rows = 0;
+            }
+            accO += v[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) park[(n_rows + i) * RB_ROW + lane] = v[i];
+            if (lane < 5) ptgt[n_rows + lane] = make_int2(mt.x, lane);
+            n_rows = __builtin_amdgcn_readfirstlane(n_rows + 5);
+          }
+        } else if (cur_fill) {
           // fill Gaussians: one value each (dL/do_j), parked in one row;
           // entries are evaluated two at a time (independent work of the
           // pair overlaps) and parked in order

@@ -20,7 +20,7 @@ constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 27;                // workspace entries
+constexpr int N_WS = 28;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -66,7 +66,8 @@ struct Work {
   int32_t* item_off;   // [tiles at the smallest tile size + 1] first adjoint item of each tile in blend order (scan)
   float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries: T, and
                        // the colour of everything behind the boundary (per channel)
-  float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and 1 for fill Gaussians
+  float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and its kind (Kind below)
+  float4* gaux;        // [caps.gauss] tangent-aligned Gaussians: tangent (x, y), axis across the curve
   double* segs;        // [caps.boundary + (SDF_CHUNK - 1) * n_curves][SEG_WORDS] fill SDF segment records
 };
 
@@ -96,12 +97,19 @@ constexpr int SEG_WORDS = 6;
 constexpr double SEG_FAR = 1e100;
 __host__ __device__ inline int64_t seg_base(int64_t boff, int c) { return boff + (int64_t)(SDF_CHUNK - 1) * c; }
 
-constexpr int GG = 4;  // floats per Gaussian in Work::ggrad
+// Floats per Gaussian in Work::ggrad: d/dmx, d/dmy, d/dsigma, then d/do_j for
+// a fill Gaussian or d/dsigma_across for a tangent-aligned one (a stroke
+// curve's opacity gradient is summed per curve), and d/dtheta of a
+// tangent-aligned one's tangent t = (cos theta, sin theta).
+constexpr int GG = 5;
+
+// Kind of a Gaussian, in the w component of Work::gcol.
+constexpr float KIND_STROKE = 0.0f, KIND_FILL = 1.0f, KIND_ANISO = 2.0f;
 
 // Work::queue slots with the number of fill and of stroke Gaussians the
 // sampling pass asked for (written with the Gaussian offsets), which lets the
 // per-kind adjoint kernels return at once when there are none.
-constexpr int Q_NFILL = 8, Q_NSTROKE = 9;
+constexpr int Q_NFILL = 8, Q_NSTROKE = 9, Q_NANISO = 10;
 
 struct Layout {
   size_t off[N_WS];
@@ -121,6 +129,7 @@ struct CurveView {
   const double* U;
   __device__ bool closed() const { return (flags & NSPLAT_CLOSED) != 0; }
   __device__ bool filled() const { return (flags & NSPLAT_FILLED) != 0; }
+  __device__ bool aniso() const { return (flags & NSPLAT_ANISO) != 0; }
   // Closed curves wrap the last ceil(p/2) key points in front (Sec. 3.1).
   __device__ int key_of_cp(int j) const {
     if (!closed()) return j;
@@ -151,6 +160,7 @@ __device__ inline bool curve_valid(const CurveView& v) {
   if (v.nk < v.p + 1) return false;
   if (v.nt != (v.closed() ? v.nk : v.nk - v.p)) return false;
   if (v.filled() && !v.closed()) return false;
+  if (v.filled() && v.aniso()) return false;  // tangent alignment concerns contour samples only
   return true;
 }
 

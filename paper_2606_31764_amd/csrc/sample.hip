@@ -194,7 +194,8 @@ __global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat
     w.L[c] = L;
     int near = 0;
     if (!v.filled()) {
-      const int M = count_rule((double)pr.delta_c, L, v.closed() ? 3 : 2, &near);
+      const double delta = (double)(v.aniso() ? pr.delta_a : pr.delta_c);
+      const int M = count_rule(delta, L, v.closed() ? 3 : 2, &near);
       if (!frozen) {
         row[P_NSAMP] = M;
         row[P_COUNT] = v.closed() ? M : M + 2 * pr.kappa;
@@ -212,15 +213,17 @@ __global__ __launch_bounds__(THREADS) void k_curve_prep(nsplat_curves cv, nsplat
 // which == 0: boundary points of filled curves -> P_BOFF, total to
 // counters[BOUND_REQ]; which == 1: Gaussians -> P_GOFF and goff[], total to
 // counters[GAUSS_REQ], capped total to counters[GAUSS], and the number of
-// fill and of stroke Gaussians to kinds[0], kinds[1].
+// fill Gaussians, of other (stroke) Gaussians and of tangent-aligned stroke
+// Gaussians to kinds[0], kinds[1], kinds[2].
 __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* plan, int32_t* goff,
                                                      int32_t* counters, int which, int64_t cap, int32_t* kinds) {
   __shared__ int64_t wsum[16];
   __shared__ int64_t fsum[16];
+  __shared__ int64_t asum[16];
   const int n = cv.n_curves;
   const int per = (n + 1023) / 1024;
   const int c0 = threadIdx.x * per;
-  int64_t s = 0, sf = 0;
+  int64_t s = 0, sf = 0, sa = 0;
   for (int i = 0; i < per; ++i) {
     const int c = c0 + i;
     if (c < n) {
@@ -230,13 +233,20 @@ __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* 
       } else {
         s += row[P_COUNT];
         if (cv.flags[c] & NSPLAT_FILLED) sf += row[P_COUNT];
+        else if (cv.flags[c] & NSPLAT_ANISO) sa += row[P_COUNT];
       }
     }
   }
   if (which == 1) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) sf += __shfl_xor(sf, off);
-    if (__lane_id() == 0) fsum[threadIdx.x >> 6] = sf;
+    for (int off = 32; off >= 1; off >>= 1) {
+      sf += __shfl_xor(sf, off);
+      sa += __shfl_xor(sa, off);
+    }
+    if (__lane_id() == 0) {
+      fsum[threadIdx.x >> 6] = sf;
+      asum[threadIdx.x >> 6] = sa;
+    }
   }
   // block exclusive scan of s
   int64_t incl = s;
@@ -276,10 +286,14 @@ __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* 
       if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_BOUND_CAP);
     } else {
       goff[n] = t32;
-      int64_t fills = 0;
-      for (int i = 0; i < 16; ++i) fills += fsum[i];
+      int64_t fills = 0, anis = 0;
+      for (int i = 0; i < 16; ++i) {
+        fills += fsum[i];
+        anis += asum[i];
+      }
       kinds[0] = fills > 0x7fffffff ? 0x7fffffff : (int32_t)fills;
       kinds[1] = tot - fills > 0x7fffffff ? 0x7fffffff : (int32_t)(tot - fills);
+      kinds[2] = anis > 0x7fffffff ? 0x7fffffff : (int32_t)anis;
       counters[NSPLAT_CNT_GAUSS_REQ] = t32;
       counters[NSPLAT_CNT_GAUSS] = (int32_t)(tot < cap ? tot : cap);
       if (tot > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_GAUSS_CAP);
@@ -620,12 +634,35 @@ __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params
       int j = v.closed() ? local : local - pr.kappa;
       j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
       const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), nullptr);
-      double pt[3];
-      curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, nullptr);
+      double pt[3], d[3];
+      const bool an = v.aniso();
+      curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, an ? d : nullptr);
       r.mx = pt[0];
       r.my = pt[1];
-      r.sigma = (float)(pt[2] / (double)pr.rho);  // Eq. 5
+      const double sg = pt[2] / (double)pr.rho;
+      r.sigma = (float)sg;  // Eq. 5
       r.opacity = (float)o;
+      if (an) {
+        // tangent-aligned: the axis across the curve keeps s / rho, the axis
+        // along t = C' / |C'| (Eq. 2) covers the spacing |C'| du of the
+        // samples with the same ratio rho, and never falls below the other
+        const double len = sqrt(d[0] * d[0] + d[1] * d[1]);
+        const double du = (v.U[v.m - v.p] - v.U[v.p]) / (double)(v.closed() ? M : M - 1);
+        float tx = 1.0f, ty = 0.0f;
+        double sig = sg;
+        if (len > 0.0) {
+          tx = (float)(d[0] / len);
+          ty = (float)(d[1] / len);
+          const double along = len * du / (double)pr.rho;
+          if (along > sg) sig = along;
+        }
+        r.sigma = (float)sig;
+        // the axis ratio sigma / sp is exactly 1 where the axes agree
+        w.gaux[g] = make_float4(tx, ty, (float)sg, (float)(sig / sg));
+      }
+      out[g] = r;
+      w.gcol[g] = curve_colour(cv, c, an ? KIND_ANISO : KIND_STROKE);
+      continue;
     } else {
       // Lanes take the window in bands of 8 rows, column by column inside a
       // band, so that a wavefront covers an 8 x 8 block of lattice points
@@ -694,12 +731,10 @@ __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params
       if (gp < G) {  // a capped (overflowing) emission may map past the capacity
         w.aux[gp] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
         out[gp] = r;
-        w.gcol[gp] = curve_colour(cv, c, 1.0f);
+        w.gcol[gp] = curve_colour(cv, c, KIND_FILL);
       }
       continue;
     }
-    out[g] = r;
-    w.gcol[g] = curve_colour(cv, c, 0.0f);
   }
 }
 

@@ -41,6 +41,7 @@ class Params:
     k_sigma: float = 6.0
     alpha_max: float = 0.99
     eps_T: float = 1e-6
+    delta_a: float = 0.25
     kappa: int = 4
     tile: int = 16
     batch: int = 64
@@ -50,8 +51,8 @@ class Params:
 
     def cstruct(self, h_dev: Optional[torch.Tensor] = None) -> L.Params:
         return L.Params(self.delta_c, self.delta_b, self.rho, self.eta, self.gamma, self.nl_factor, self.fill_pad,
-                        self.h, self.k_sigma, self.alpha_max, self.eps_T, int(self.kappa), int(self.tile),
-                        int(self.batch), _ptr(h_dev))
+                        self.h, self.k_sigma, self.alpha_max, self.eps_T, self.delta_a, int(self.kappa),
+                        int(self.tile), int(self.batch), _ptr(h_dev))
 
 
 class Context:
@@ -298,6 +299,19 @@ class Renderer:
         return dict(mu=raw[:, :2].copy(), sigma=u8[:, 16:20].copy().view(np.float32)[:, 0],
                     opacity=u8[:, 20:24].copy().view(np.float32)[:, 0], curve=u8[:, 24:28].copy().view(np.int32)[:, 0],
                     local=u8[:, 28:32].copy().view(np.int32)[:, 0])
+
+    def gauss_frame(self, tensors):
+        """Tangent and cross-axis width of the tangent-aligned stroke Gaussians
+        of the last sample: dict(tdir [G,2], sp [G], ratio [G]) as numpy (FP32);
+        rows of other kinds are unspecified."""
+        G = self.read_counters()[L.CNT_GAUSS]
+        out = torch.empty((max(G, 1), 4), dtype=torch.float32, device=self.gauss.device)
+        cv = self.meta.curves_c(*tensors)
+        c = self.ctx
+        c.check(c.lib.nsplat_gauss_frame(c.h, ctypes.byref(cv), ctypes.byref(self.meta.scenes_c),
+                                         ctypes.byref(self.bufs), _ptr(out), int(G), _stream()))
+        a = out[:G].cpu().numpy()
+        return dict(tdir=a[:, :2].copy(), sp=a[:, 2].copy(), ratio=a[:, 3].copy())
 
     def tiles(self, tile=None):
         tile = tile or self.params.tile

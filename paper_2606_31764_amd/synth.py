@@ -22,6 +22,7 @@ import numpy as np
 
 CLOSED = 1
 FILLED = 2
+ANISO = 4      # tangent-aligned contour Gaussians (strokes only)
 
 
 @dataclasses.dataclass
@@ -30,7 +31,7 @@ class CurveBatch:
     curves store n_k - p knot intervals, closed curves n_k (Sec. 3.1)."""
     scene: np.ndarray      # [N] int32
     degree: np.ndarray     # [N] int32
-    flags: np.ndarray      # [N] int32 (CLOSED | FILLED)
+    flags: np.ndarray      # [N] int32 (CLOSED | FILLED | ANISO)
     key_off: np.ndarray    # [N+1] int32
     tau_off: np.ndarray    # [N+1] int32
     key_xy: np.ndarray     # [K, 2] float32, pixels (y down)
@@ -119,7 +120,7 @@ def _taus(rng, n, normalise=True):
 # ---------------------------------------------------------------------------------
 
 def strokes(seed, n_curves=32, size=256, nk_range=(12, 40), step=8.0, width=(1.0, 8.0), degree=3,
-            weights=(0.3, 3.0), channels=3, margin=None, scene=0) -> List[dict]:
+            weights=(0.3, 3.0), channels=3, margin=None, scene=0, flags=0) -> List[dict]:
     rng = np.random.default_rng(seed)
     margin = size * 0.1 if margin is None else margin
     parts = []
@@ -130,7 +131,7 @@ def strokes(seed, n_curves=32, size=256, nk_range=(12, 40), step=8.0, width=(1.0
         walk = np.cumsum(rng.normal(0.0, step, (nk, 2)), axis=0)
         walk[0] = 0.0
         xy = np.clip(p0 + walk - walk[0], 1.0, size - 1.0)
-        parts.append(dict(scene=scene, degree=degree, flags=0, key_xy=xy,
+        parts.append(dict(scene=scene, degree=degree, flags=flags, key_xy=xy,
                           key_w=np.exp(rng.uniform(math.log(weights[0]), math.log(weights[1]), nk)),
                           key_s=rng.uniform(width[0], width[1], nk), tau=_taus(rng, nk - degree),
                           color=np.zeros(channels), opacity=1.0))

@@ -27,7 +27,7 @@ def plans_equal(gpu_plan, oracle_rows):
 def oracle_params(p):
     """The oracle's parameter dict from a render.Params (FP32-rounded like the GPU sees them)."""
     d = {k: float(np.float32(getattr(p, k))) for k in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor",
-                                                       "fill_pad", "h", "alpha_max", "eps_T")}
+                                                       "fill_pad", "h", "alpha_max", "eps_T", "delta_a")}
     d["kappa"] = int(p.kappa)
     d["cutoff"] = float(p.k_sigma)
     return d
