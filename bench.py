@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--optim-steps", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--only", choices=["batched", "optim"], default=None,
+    ap.add_argument("--no-aniso", action="store_true", help="skip the tangent-aligned contour measurement")
+    ap.add_argument("--only", choices=["batched", "optim", "aniso"], default=None,
                     help="run one secondary leg alone (for profiling); prints its result as JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -94,11 +95,13 @@ def timing_read(ctx):
     return {PHASES[i]: (ms[i], n[i]) for i in range(len(PHASES))}
 
 
-def blend_work(step, tile):
+def blend_work(step, tile, frame=None):
     """Algorithmic work of one forward blend launch, counted with torch on the
     GPU from the launch's own tile lists and stopping positions: evaluated
     (pixel, Gaussian) pairs, in-support pairs, and in-support pairs of fill
-    Gaussians."""
+    Gaussians.  With the tangent-aligned frame ([G, 4] device tensor of
+    (t, sp, ratio)), the support of a tangent-aligned Gaussian is its ellipse
+    (the fill count then counts those pairs instead)."""
     import torch
     r = step.r
     G = step.G
@@ -119,6 +122,9 @@ def blend_work(step, tile):
     stop = r.n_last.view(H, W).long()
     curve = u8[:, 24:28].contiguous().view(torch.int32).view(G).long()
     is_fill = ((r.meta.flags.long() & 2) != 0)[curve][gidx]
+    if frame is not None:
+        is_fill = ((r.meta.flags.long() & 4) != 0)[curve][gidx]
+        fr = frame[:G].double()[gidx]
     ev = 0
     hit = 0
     hit_fill = 0
@@ -133,7 +139,13 @@ def blend_work(step, tile):
             e = ok & (pos >= st)
             dx = xs.double() + 0.5 - mx[gidx]
             dy = ys.double() + 0.5 - my[gidx]
-            h = e & (dx * dx + dy * dy <= (ks * sigma[gidx]) ** 2)
+            if frame is None:
+                h = e & (dx * dx + dy * dy <= (ks * sigma[gidx]) ** 2)
+            else:
+                dp = dx * fr[:, 0] + dy * fr[:, 1]
+                dq = dy * fr[:, 0] - dx * fr[:, 1]
+                m2 = (dp / sigma[gidx]) ** 2 + (dq / fr[:, 2]) ** 2
+                h = e & torch.where(is_fill, m2 <= ks * ks, dx * dx + dy * dy <= (ks * sigma[gidx]) ** 2)
             ev += int(e.sum().item())
             hit += int(h.sum().item())
             hit_fill += int((h & is_fill).sum().item())
@@ -145,12 +157,19 @@ def blend_work(step, tile):
 # mul, fma) 5, exp2 argument and exp2 2, o G and the alpha_max clamp 2,
 # 1 - alpha and T (1 - alpha) 2, termination test 1 = 12 (the colour is added
 # once per run of one curve's entries, as col (T at the run's start - T), not
-# per pair).  Adjoint of a fill Gaussian (front to back inside a chunk): d^2 5,
-# exp2 2, o G and clamp 2, 1 - alpha 1, T (1 - alpha) 1, dL/dalpha =
-# -Vc rcp(1 - alpha) 2, dL/do_j FMA 2 = 15 (K, Vc and the colour gradient are
-# per curve run, not per pair); a stroke Gaussian adds dL/dmu and dL/dsigma
-# (14) and its opacity sum (1) = 30.
-FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 12, 15, 30
+# per pair).  Adjoint of a fill Gaussian (back to front inside a chunk): d^2 5,
+# exp2 2, o G and clamp 2, 1 - alpha 1, r = rcp(1 - alpha) 1, dL/dalpha =
+# -W r 1, T = T' r 1, the run's sum of alpha T (FMA) 2, dL/do_j (FMA) 2 = 17
+# (K, W and the colour gradient are per curve run, not per pair); a stroke
+# Gaussian adds dL/do_j o 1, the d^2 factor G a ln 2 3, dL/dmu 2 x 3 and
+# dL/dsigma 4 = 32.  Tangent-aligned strokes: forward 2 subs, a = d . u 3,
+# b = r (d x u) 4, a^2 + b^2 3, exp2 1, o G and clamp 2, 1 - alpha and
+# T (1 - alpha) 2, termination test 1 = 18; adjoint the same geometry 12,
+# exp2 1, clamp 2, 1 - alpha, rcp, dL/dalpha, T' r 4, sum alpha T 2,
+# dL/do_j 2, h = dL/dalpha o G 2 ln 2 3, dL/dmu 2 x 5, dL/dsigma, dL/dsp,
+# dL/dtheta 11 = 47.
+FWD_HIT_FLOPS, BWD_FILL_HIT_FLOPS, BWD_STROKE_HIT_FLOPS = 12, 17, 32
+FWD_ANISO_HIT_FLOPS, BWD_ANISO_HIT_FLOPS = 18, 47
 # The build disables packed FP32 instructions, so the FP32 vector peak is
 # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s, not the
 # packed 157.3.
@@ -284,6 +303,8 @@ def bench_main(args):
         out["batched"] = bench_batched(args)
     if not args.no_optim:
         out["optim_step"] = bench_optim(args)
+    if not args.no_aniso:
+        out["tangent_aligned"] = bench_aniso(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, p, target)
     return out
@@ -419,6 +440,68 @@ def bench_batched(args):
     res["hbm_phases_batched"]["radix_passes"] = passes
     res["pairs"] = int(bat.r.read_counters()[1])
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
+    return res
+
+
+def bench_aniso(args):
+    """Tangent-aligned contour Gaussians (the prototype variant of Eq. 5)
+    next to the paper's isotropic ones on the calligraphy workload (32 open
+    cubic strokes, 256x256, delta_c 3 / delta_a 0.25): fwd + L2 bwd per step,
+    and the blend kernels' algorithmic rates."""
+    import torch
+    from paper_2606_31764_amd import synth
+    from paper_2606_31764_amd.render import Context, Params, Renderer, param_tensors
+    p = Params().replace(**synth.CONFIG_PARAMS[2])
+    ctx = Context(0)
+    res = {}
+    K = args.steps
+    for name, flags in (("isotropic", 0), ("tangent_aligned", synth.ANISO)):
+        b = synth._assemble(synth.strokes(2000, flags=flags), [[256, 256]], [[1.0, 1.0, 1.0]], 3)
+        pert = synth.perturbed(b, seed=2999)
+        tr = Renderer(pert, p, ctx=ctx)
+        target = tr.run_forward(param_tensors(pert)).clone().cpu().numpy()
+        del tr
+        st = Step(b, p, target, ctx=ctx)
+        for _ in range(args.warmup):
+            st.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            st.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        timing_on(ctx, True)
+        for _ in range(min(K, 10)):
+            st.run()
+        torch.cuda.synchronize()
+        ph = timing_read(ctx)
+        timing_on(ctx, False)
+        phm = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()}
+        frame = None
+        if flags:
+            frame = torch.empty((max(st.G, 1), 4), dtype=torch.float32, device="cuda")
+            cv = st.r.meta.curves_c(*st.t)
+            ctx.check(ctx.lib.nsplat_gauss_frame(ctx.h, ctypes.byref(cv), ctypes.byref(st.r.meta.scenes_c),
+                                                 ctypes.byref(st.r.bufs), ctypes.c_void_p(frame.data_ptr()),
+                                                 int(st.G), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        ev, hit, hit_k = blend_work(st, p.tile, frame)
+        if flags:
+            f_fwd, f_bwd = FWD_ANISO_HIT_FLOPS * hit_k, BWD_ANISO_HIT_FLOPS * hit_k
+        else:
+            f_fwd, f_bwd = FWD_HIT_FLOPS * hit, BWD_STROKE_HIT_FLOPS * hit
+        ach_f = f_fwd / (phm["blend_fwd"] * 1e-3) / 1e12 if phm["blend_fwd"] else None
+        ach_b = f_bwd / (phm["blend_bwd"] * 1e-3) / 1e12 if phm["blend_bwd"] else None
+        res[name] = dict(gaussians=int(st.G), pairs=int(st.pairs), ms_per_step=ms,
+                         gaussians_per_s=st.G / (ms * 1e-3), in_support_pairs=hit, evaluated_pairs=ev,
+                         blend_fwd_tflops=ach_f, blend_bwd_tflops=ach_b,
+                         blend_fwd_frac=(ach_f / ALU_PEAK_TFLOPS) if ach_f else None,
+                         blend_bwd_frac=(ach_b / ALU_PEAK_TFLOPS) if ach_b else None, phases_ms=phm)
+        log("%s strokes: G %d, %.4f ms/step (fwd %.4f, bwd %.4f, adj %.4f ms)" % (
+            name, st.G, ms, phm["blend_fwd"], phm["blend_bwd"], phm["adj_gauss"]))
+        del st
+    res["workload"] = "32 open cubic strokes (12-40 key points, widths 1-8 px), 256x256 RGB, L2 vs perturbed target"
     return res
 
 
@@ -568,6 +651,8 @@ def main():
         out = bench_batched(args)
     elif args.only == "optim":
         out = bench_optim(args)
+    elif args.only == "aniso":
+        out = bench_aniso(args)
     else:
         out = bench_main(args)
     print(json.dumps(out), flush=True)

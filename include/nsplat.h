@@ -70,7 +70,7 @@ extern "C" {
 /* Version of the structure layouts below; nsplat_abi_version() returns the
  * value the library was built with, so a binding can refuse a library whose
  * structures it would misread. */
-#define NSPLAT_ABI_VERSION 4
+#define NSPLAT_ABI_VERSION 5
 
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
@@ -138,6 +138,11 @@ typedef struct {
                               NSPLAT_MAX_DEGREE.  A curve above it counts as
                               invalid data.  A bound of 3 or less selects
                               adjoint kernels with smaller register arrays */
+  int32_t any_flags;       /* (host) the union (bitwise or) of flags[c] over
+                              the batch, or a superset of it; a curve with a
+                              flag outside it counts as invalid data.
+                              Without NSPLAT_ANISO the blend kernels run
+                              their forms without the tangent-aligned kind */
   const int32_t* scene;    /* (dev) [n_curves] scene of each curve           */
   const int32_t* degree;   /* (dev) [n_curves] p                             */
   const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED | NSPLAT_ANISO */

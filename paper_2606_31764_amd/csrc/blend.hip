@@ -139,10 +139,10 @@ __device__ inline bool entry_geometry(const Gauss& r, double ox, double oy, floa
 // ck = log2(e) / 2, so that a^2 + b^2 = ck (d_t^2 / sigma^2 + d_n^2 / sp^2).
 // The support is a^2 + b^2 <= ck k_sigma^2, inside the disc of radius
 // k_sigma sigma that binning and culling use.  Entries are staged like the
-// others (exp2 coefficient -ck / sigma^2); a wavefront converts the entries
-// of a run of such a curve when it reaches them, reading (t, sp, r) by
-// Gaussian index, so that the other kinds carry no extra loads.  Where the
-// two axes agree r is exactly 1 and the theta partial exactly 0.
+// others (exp2 coefficient -ck / sigma^2); after staging a step that holds
+// such entries, the wavefront converts them, reading (t, sp, r) by Gaussian
+// index, so that the other kinds carry no extra loads.  Where the two axes
+// agree r is exactly 1 and the theta partial exactly 0.
 constexpr float ANI_CK = (float)(0.5 * LOG2E);
 constexpr float ANI_SQRT_CK = 0.8493218002880191f;  // sqrt(log2(e) / 2)
 __device__ inline void aniso_axes(const float4& aux, float coef, float* ux, float* uy, float* r) {
@@ -164,7 +164,8 @@ struct FwdRec {
   float4 geo;      // tile-local centre, squared support radius, exp2 coefficient
                    // (tangent-aligned: centre, scaled axis u)
   float op;           // opacity
-  int pos, curve, g;  // list position, curve, Gaussian
+  int pos, curve, g;  // list position, curve, Gaussian (tangent-aligned, once
+                      // converted: the bits of the axis ratio r)
 };
 constexpr int FWD_ENTRY_BYTES = sizeof(FwdRec) + 16;
 constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, position, 1/sigma^3)
@@ -191,7 +192,7 @@ __device__ inline int step_floor(int h, int start, int depth, int end) {
   return max(max(start, h - depth), end - (k + 1) * CK);
 }
 
-template <int C, int TILE, int E>
+template <int C, int TILE, int E, bool ANI>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
     }
     while (hi > start) {
       int cnt = 0;
+      bool step_aniso = false;
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
@@ -270,6 +272,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
         float4 geo;
         const bool keep = ok && entry_geometry(e[u].r, ox, oy, ks, qbox, &geo);
         const uint64_t m = __ballot(keep);
+        if (ANI) step_aniso = step_aniso || __ballot(keep && e[u].kind == 2) != 0ull;
         if (keep) {
           const int dst = cnt + __popcll(m & below);
           FwdRec rec;
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           rec.curve = e[u].r.curve;
           rec.g = e[u].g;
           wrec[dst] = rec;
-          wcol[dst] = make_float4(e[u].c0, e[u].c1, e[u].c2, (float)e[u].kind);
+          wcol[dst] = make_float4(e[u].c0, e[u].c1, e[u].c2, ANI ? (float)e[u].kind : 0.0f);
         }
         cnt += __popcll(m);
       }
@@ -296,6 +299,21 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ANI && step_aniso) {
+        // tangent-aligned entries of the step take their axis u and ratio r
+        for (int i = lane; i < cnt; i += 64) {
+          if (wcol[i].w != 2.0f) continue;
+          const float4 ax = w.gaux[wrec[i].g];
+          float ux, uy, rq;
+          aniso_axes(ax, wrec[i].geo.w, &ux, &uy, &rq);
+          wrec[i].geo.z = ux;
+          wrec[i].geo.w = uy;
+          wrec[i].g = __float_as_int(rq);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
       // composited entries that begin a run (their curve differs from the
       // entry before, the first one compared with the previous step's run)
       uint64_t rs[E];
@@ -330,26 +348,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
           rc1 = pc.y;
           rc2 = pc.z;
           run_curve = wrec[j].curve;
-          run_kind = __builtin_amdgcn_readfirstlane((int)pc.w);
+          if (ANI) run_kind = __builtin_amdgcn_readfirstlane((int)pc.w);
         }
-        if (run_kind == 2) {
-          // tangent-aligned strokes (elliptical Eq. 9): the segment's entries
-          // take their axis u and the ratio r (in place of the kind)
-          for (int i = j + lane; i < jend; i += 64) {
-            const float4 ax = w.gaux[wrec[i].g];
-            float ux, uy, rq;
-            aniso_axes(ax, wrec[i].geo.w, &ux, &uy, &rq);
-            wrec[i].geo.z = ux;
-            wrec[i].geo.w = uy;
-            wcol[i].w = rq;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ANI && run_kind == 2) {
+          // tangent-aligned strokes (elliptical Eq. 9)
           const float lim = ANI_CK * ks * ks;
           for (; j < jend; ++j) {
             const float4 gm = wrec[j].geo;
-            const float op = wrec[j].op, rq = wcol[j].w;
+            const float op = wrec[j].op, rq = __int_as_float(wrec[j].g);
             const int pos = wrec[j].pos;
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
@@ -589,7 +595,7 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // per-entry curve test.  Occupancy: six wavefronts per SIMD for one pixel per
 // lane at depth 64, four for 32 x 32 tiles at depth 64 (128 VGPRs, unspilled);
 // elsewhere the registers decide.
-template <int C, int TILE, int E>
+template <int C, int TILE, int E, bool ANI>
 __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 4 : 1)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
@@ -712,7 +718,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       // pixels that take part somewhere in this step (their stop lies below
       // its top); walking back to front the set only grows.  Entries that
       // reach none of them are dropped.
-      bool lv = false;
+      bool lv = false, step_aniso = false;
 #pragma unroll
       for (int q = 0; q < PPT; ++q) lv = lv || (stop[q] < s_hi);
       const Box box = live_box<TILE>(quad, __ballot(lv));
@@ -724,11 +730,12 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
         float4 geo;
         const bool keep = ok && entry_geometry(e[u].r, ox, oy, ks, box, &geo);
         const uint64_t m = __ballot(keep);
+        if (ANI) step_aniso = step_aniso || __ballot(keep && e[u].kind == 2) != 0ull;
         if (keep) {
           const int dst = cnt + __popcll(m & below);
           const double sg = (double)e[u].r.sigma;
           // tangent-aligned entries: -1 (negative: the kind) in place of 1 / sigma^3
-          const float wbits = e[u].kind == 2 ? -1.0f : (float)(1.0 / (sg * sg * sg));
+          const float wbits = (ANI && e[u].kind == 2) ? -1.0f : (float)(1.0 / (sg * sg * sg));
           wgeo[dst] = geo;
           wpc[dst] = make_float4(e[u].r.opacity, e[u].c0, e[u].c1, e[u].c2);
           wmeta[dst] = make_int4(e[u].kind == 1 ? ~e[u].g : e[u].g, e[u].r.curve, mypos, __float_as_int(wbits));
@@ -744,6 +751,23 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ANI && step_aniso) {
+        // tangent-aligned entries of the step take their axis u (in place of
+        // the support radius and coefficient) and -r (in place of the kind)
+        for (int i = lane; i < cnt; i += 64) {
+          const int4 mt = wmeta[i];
+          if (mt.x < 0 || mt.w >= 0) continue;
+          const float4 ax = w.gaux[mt.x];
+          float ux, uy, rq;
+          aniso_axes(ax, wgeo[i].w, &ux, &uy, &rq);
+          wgeo[i].z = ux;
+          wgeo[i].w = uy;
+          wmeta[i].w = __float_as_int(-rq);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
       // entries that begin a run (their curve differs from the entry processed
       // before them, the first one compared with the previous step's curve)
       uint64_t rs[E];
@@ -779,28 +803,15 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
           }
           cur = __builtin_amdgcn_readfirstlane(mt.y);
           cur_fill = __builtin_amdgcn_readfirstlane(mt.x) < 0;
-          cur_aniso = !cur_fill && __builtin_amdgcn_readfirstlane(mt.w) < 0;
+          cur_aniso = ANI && !cur_fill && __builtin_amdgcn_readfirstlane(mt.w) < 0;
           since = 0;
         }
-        if (cur_aniso) {
+        if (ANI && cur_aniso) {
           // tangent-aligned stroke Gaussians: dL/dmu (2), dL/dsigma, dL/dsp
           // and dL/dtheta (t = (cos theta, sin theta)) parked in five rows.
           // With h = dL/dG G / ck: dG/dmu = (a u - b r u^perp) 2 ln 2 G, and so
           // on (the partials of exp(-(d_t^2 / sigma^2 + d_n^2 / sp^2) / 2)
           // rewritten in a, b).
-          // the segment's entries take their axis u (in place of the support
-          // radius and coefficient) and -r (in place of the kind)
-          for (int i = j + lane; i < jend; i += 64) {
-            const float4 ax = w.gaux[wmeta[i].x];
-            float ux, uy, rq;
-            aniso_axes(ax, wgeo[i].w, &ux, &uy, &rq);
-            wgeo[i].z = ux;
-            wgeo[i].w = uy;
-            wmeta[i].w = __float_as_int(-rq);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           const float lim = ANI_CK * ks * ks;
           const float two_ln2 = 2.0f * ln2;
           for (; j < jend; ++j) {
@@ -830,7 +841,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               const float G = __builtin_amdgcn_exp2f(-m);
               const float oG = op * G;
               const bool lt = oG < amax;
-              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float alpha = in ? fminf(oG, amax) : 0.0f;  // = lt ? oG : amax
               const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
               const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
               T[q] = in ? T[q] * r : T[q];
@@ -874,7 +885,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               const float G = __builtin_amdgcn_exp2f(gm.w * d2);
               const float oG = op * G;
               const bool lt = oG < amax;
-              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float alpha = in ? fminf(oG, amax) : 0.0f;  // = lt ? oG : amax
               const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
               // dL/dalpha = (T' K - B) / (1 - alpha) = -W / (1 - alpha)
               const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
@@ -935,7 +946,7 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
               const float G = __builtin_amdgcn_exp2f(gm.w * d2);
               const float oG = op * G;
               const bool lt = oG < amax;
-              const float alpha = in ? (lt ? oG : amax) : 0.0f;
+              const float alpha = in ? fminf(oG, amax) : 0.0f;  // = lt ? oG : amax
               const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
               const float dLda = (in && lt) ? -Wc[q] * r : 0.0f;
               T[q] = in ? T[q] * r : T[q];
@@ -987,24 +998,24 @@ int resident_grid(K kernel, int n_blocks, int n_cu, size_t lds) {
 
 inline int depth_factor(int batch) { return batch <= 64 ? 1 : (batch <= 128 ? 2 : 4); }
 
-template <int C, int TILE, int E>
+template <int C, int TILE, int E, bool ANI>
 hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
   const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
   if (n_items <= 0) return hipSuccess;
   const size_t lds = (size_t)WPB * 64 * E * FWD_ENTRY_BYTES;
   int grid = (n_items + WPB - 1) / WPB;
   if (persistent) {
-    grid = resident_grid(k_blend_fwd<C, TILE, E>, grid, L.n_cu, lds);
+    grid = resident_grid(k_blend_fwd<C, TILE, E, ANI>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_FWD);
-  hipLaunchKernelGGL((k_blend_fwd<C, TILE, E>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
                      T_final, n_last, persistent);
   return hipGetLastError();
 }
 
-template <int C, int TILE, int E>
+template <int C, int TILE, int E, bool ANI>
 hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
   if (L.n_tiles <= 0) return hipSuccess;
   // the item count lives on the device; the grid covers its bound
@@ -1013,31 +1024,44 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {
-    grid = resident_grid(k_blend_bwd<C, TILE, E>, grid, L.n_cu, lds);
+    grid = resident_grid(k_blend_bwd<C, TILE, E, ANI>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_BWD);
-  hipLaunchKernelGGL((k_blend_bwd<C, TILE, E>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
                      dL, T_final, n_last, persistent);
   return hipGetLastError();
 }
 
+// The tangent-aligned kind is compiled in only for batches that declare it
+// (nsplat_curves.any_flags), so that the other batches run without its
+// branches and registers.
+inline bool any_aniso(const Launch& L) { return (L.cv->any_flags & NSPLAT_ANISO) != 0; }
+
 template <int C, int TILE>
 hipError_t fwd_d(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
+  const bool a = any_aniso(L);
   switch (depth_factor(L.pr->batch)) {
-    case 1: return fwd_t<C, TILE, 1>(L, image, T_final, n_last, persistent);
-    case 2: return fwd_t<C, TILE, 2>(L, image, T_final, n_last, persistent);
-    default: return fwd_t<C, TILE, 4>(L, image, T_final, n_last, persistent);
+    case 1: return a ? fwd_t<C, TILE, 1, true>(L, image, T_final, n_last, persistent)
+                     : fwd_t<C, TILE, 1, false>(L, image, T_final, n_last, persistent);
+    case 2: return a ? fwd_t<C, TILE, 2, true>(L, image, T_final, n_last, persistent)
+                     : fwd_t<C, TILE, 2, false>(L, image, T_final, n_last, persistent);
+    default: return a ? fwd_t<C, TILE, 4, true>(L, image, T_final, n_last, persistent)
+                      : fwd_t<C, TILE, 4, false>(L, image, T_final, n_last, persistent);
   }
 }
 
 template <int C, int TILE>
 hipError_t bwd_d(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
+  const bool a = any_aniso(L);
   switch (depth_factor(L.pr->batch)) {
-    case 1: return bwd_t<C, TILE, 1>(L, dL, T_final, n_last, persistent);
-    case 2: return bwd_t<C, TILE, 2>(L, dL, T_final, n_last, persistent);
-    default: return bwd_t<C, TILE, 4>(L, dL, T_final, n_last, persistent);
+    case 1: return a ? bwd_t<C, TILE, 1, true>(L, dL, T_final, n_last, persistent)
+                     : bwd_t<C, TILE, 1, false>(L, dL, T_final, n_last, persistent);
+    case 2: return a ? bwd_t<C, TILE, 2, true>(L, dL, T_final, n_last, persistent)
+                     : bwd_t<C, TILE, 2, false>(L, dL, T_final, n_last, persistent);
+    default: return a ? bwd_t<C, TILE, 4, true>(L, dL, T_final, n_last, persistent)
+                      : bwd_t<C, TILE, 4, false>(L, dL, T_final, n_last, persistent);
   }
 }
 

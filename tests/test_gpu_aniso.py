@@ -165,3 +165,29 @@ def test_batched_scenes_match_single():
         a = out["grads"][n].ravel()[sl]
         s = single["grads"][n].ravel()[sl]
         assert np.abs(a - s).max() <= 1e-4 * np.abs(s).max() + 1e-6, n
+
+
+def test_undeclared_flag_is_invalid_data():
+    """A batch whose declared flag union (nsplat_curves.any_flags) lacks the
+    tangent-aligned flag runs the blend forms without that kind; a curve that
+    carries the flag anyway is invalid data (no Gaussians, status bit, plan
+    flag) and the rest renders as without it."""
+    from paper_2606_31764_amd import _lib as L
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = mixed(seed=101)
+    p = Params().replace(delta_c=3.0, h=1.0)
+    r = Renderer(b, p)
+    assert r.meta.any_flags & A
+    r.meta.any_flags = int(np.bitwise_or.reduce(b.flags[(b.flags & A) == 0]))
+    t = param_tensors(b)
+    img = r.run_forward(t).cpu().numpy().astype(np.float64)
+    cnt = r.read_counters()
+    plan = r.plan_np()
+    an = (b.flags & A) != 0
+    assert cnt[L.CNT_STATUS] & 8                       # NSPLAT_STATUS_DATA
+    assert np.all(plan[an, 0] == 0) and np.all(plan[an, L.PLAN_FLAGS] & L.PLAN_INVALID)
+    assert np.all(plan[~an, 0] > 0)
+    keep = np.flatnonzero(~an)
+    sub = synth._gather(b, keep, lambda c: 0, b.hw, b.bg)
+    ref = oracle.render(sub, oracle_params(p))[0]
+    assert np.abs(img - ref).max() <= IMG_TOL
