@@ -440,7 +440,58 @@ def bench_batched(args):
     res["hbm_phases_batched"]["radix_passes"] = passes
     res["pairs"] = int(bat.r.read_counters()[1])
     log("batched: plain %.3f ms, batched %.3f ms, speedup %.2fx" % (plain_ms, bat_ms, plain_ms / bat_ms))
+    res["per_kind"] = batched_per_kind(args, b5, kinds, plain, tgt_all, p.replace(tile=tile, batch=depth), ctx)
     return res
+
+
+def batched_per_kind(args, b5, kinds, plain, tgt_all, p, ctx):
+    """Where the batched step's time goes by scene kind: the scenes of each
+    kind (strokes, fills, long splines) as a batch of their own at the tuned
+    setting, eager steps timed with events, their phases and sizes, and the
+    same scenes' plain per-scene steps."""
+    import torch
+    from paper_2606_31764_amd import synth
+    names = ("strokes", "fills", "long_splines")
+    out = {}
+    K = args.batched_steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for k, name in enumerate(names):
+        idx = [s for s in range(b5.n_scenes) if kinds[s] == k]
+        if not idx:
+            continue
+        sub = synth.concat([b5.select_scene(s) for s in idx])
+        tgt = torch.cat([tgt_all[s] for s in idx]).cpu().numpy()
+        st = Step(sub, p, tgt, persistent=True, ctx=ctx)
+        for _ in range(2):
+            st.run()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            st.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        timing_on(ctx, True)
+        for _ in range(2):
+            st.run()
+        torch.cuda.synchronize()
+        ph = timing_read(ctx)
+        timing_on(ctx, False)
+        steps = [plain[s] for s in idx]
+        e0.record()
+        for _ in range(K):
+            for s_ in steps:
+                s_.run()
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / K
+        out[name] = dict(scenes=len(idx), gaussians=int(st.G), pairs=int(st.pairs),
+                         pixels=int(sum(int(h) * int(w) for h, w in sub.hw)), batched_ms=ms, plain_ms=pms,
+                         phases_ms={kk: v[0] / 2 for kk, v in ph.items()})
+        log("  kind %-12s %2d scenes, G %8d, pairs %9d: batched %.3f ms (fwd %.3f, bwd %.3f), plain %.3f ms" % (
+            name, len(idx), st.G, st.pairs, ms, ph["blend_fwd"][0] / 2, ph["blend_bwd"][0] / 2, pms))
+        del st
+    return out
 
 
 def bench_aniso(args):
