@@ -22,15 +22,14 @@ struct Rect {
 };
 
 // Tile rectangle of one Gaussian: centre m = fl32(mu), r = k_sigma * sigma in
-// FP32, interval [(m - r) - 1, (m + r) + 1], tile = floor(x / tile), clamped.
+// FP32, interval [(m - r) - 1, (m + r) + 1], tile = floor(x / tile), clamped
+// (tile_axis, shared with the blend kernels' fill runs).
 __device__ inline bool tile_rect(const Gauss& gs, float k_sigma, float inv_tile, const SceneTab& st, Rect* rc) {
   const float mx = (float)gs.mx, my = (float)gs.my;
   const float r = k_sigma * gs.sigma;
-  const float xl = (mx - r) - 1.0f, xh = (mx + r) + 1.0f;
-  const float yl = (my - r) - 1.0f, yh = (my + r) + 1.0f;
-  if (!(xl == xl) || !(xh == xh) || !(yl == yl) || !(yh == yh)) return false;
-  const float fx0 = fmaxf(0.0f, floorf(xl * inv_tile)), fx1 = fminf((float)(st.tiles_x - 1), floorf(xh * inv_tile));
-  const float fy0 = fmaxf(0.0f, floorf(yl * inv_tile)), fy1 = fminf((float)(st.tiles_y - 1), floorf(yh * inv_tile));
+  float fx0, fx1, fy0, fy1;
+  if (!tile_axis(mx, r, inv_tile, st.tiles_x, &fx0, &fx1) || !tile_axis(my, r, inv_tile, st.tiles_y, &fy0, &fy1))
+    return false;
   if (fx0 > fx1 || fy0 > fy1) return false;
   rc->x0 = (int)fx0;
   rc->x1 = (int)fx1;

@@ -157,6 +157,92 @@ __device__ inline uint64_t lanes_below() {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// ---------------------------------------------------------------------------
+// Fill runs.  A fill curve's Gaussians sit on the lattice ((i + 1/2) h,
+// (j + 1/2) h) of its window and are emitted row by row (Sec. 3.3), all with
+// one sigma.  Binning's test (tile_axis) is separable and monotone along each
+// lattice axis, so the curve's points on a tile form a rectangle
+// [i0, i1] x [j0, j1] of the window, and since a tile's list is in Gaussian
+// order they occupy one run of consecutive positions, row by row.  At h = 1
+// the lattice is the pixel grid: a pixel's in-support Gaussians of the run are
+// its lattice neighbours at integer offsets (dx, dy) with dx^2 + dy^2 <=
+// (k_sigma sigma)^2, so each lane walks those offsets (in list order) and
+// gathers the opacities from LDS instead of visiting every entry of the run.
+// ---------------------------------------------------------------------------
+struct FillRun {
+  int c, ix0, iy0, nx, goff;  // curve, window origin, window columns, first Gaussian
+  int i0, i1, j0, j1, w;      // the run's rectangle (window-relative) and its width
+  int p_lo, p_hi;             // its list positions
+  int g_top;                  // the Gaussian at the run's entry point
+  float sigma;                // the curve's fill sigma
+};
+
+// Window-relative lattice indices [k0, k1] (below n) whose binning interval
+// covers tile t along one axis: each lane tests one candidate (the same
+// arithmetic as binning).  False when the interval does not fit the 64
+// candidates.
+__device__ inline bool fill_axis(int org, int n, double h, float r, float inv, int n_tiles, int t, int tile, int* k0,
+                                 int* k1) {
+  const int base = (int)floor(((double)t * tile - (double)r - 2.0) / h - 0.5) - org - 1;
+  const int k = base + (int)__lane_id();
+  bool ok = false;
+  if (k >= 0 && k < n) {
+    const float m = (float)(((double)(org + k) + 0.5) * h);
+    float f0, f1;
+    ok = tile_axis(m, r, inv, n_tiles, &f0, &f1) && f0 <= (float)t && (float)t <= f1;
+  }
+  const uint64_t b = __ballot(ok);
+  if (b == 0ull) return false;
+  const int lo = __builtin_ctzll(b), hi = 63 - __builtin_clzll(b);
+  if (__popcll(b) != hi - lo + 1) return false;           // not an interval
+  if ((lo == 0 && base + lo > 0) || (hi == 63 && base + hi < n - 1)) return false;  // may extend past the candidates
+  *k0 = base + lo;
+  *k1 = base + hi;
+  return true;
+}
+
+// The run of fill curve c that holds list position `at` (whose Gaussian has
+// window index `local`), if the list holds the whole rectangle there: its two
+// corners are checked in the list, so a run cut short (capacity overflow)
+// is left to the entry-by-entry path.  Wavefront-uniform.
+__device__ inline bool fill_run_at(const int32_t* __restrict__ plan, const int32_t* __restrict__ idx, int c, int g,
+                                   int local, float sigma, int at, int start, int end, double h, float ks, float inv,
+                                   const SceneTab& st, int lt, int tile, FillRun* fr) {
+  typedef const __attribute__((address_space(4))) int32_t* cip;
+  const cip row = (cip)(plan + (int64_t)P_STRIDE * c);
+  fr->c = c;
+  fr->ix0 = row[P_IX0];
+  fr->iy0 = row[P_IY0];
+  fr->nx = row[P_NX];
+  fr->goff = row[P_GOFF];
+  const int ny = row[P_NY];
+  fr->g_top = g;
+  fr->sigma = sigma;
+  if (fr->nx <= 0 || ny <= 0) return false;
+  const float r = ks * sigma;
+  const int tcol = lt % st.tiles_x, trow = lt / st.tiles_x;
+  if (!fill_axis(fr->ix0, fr->nx, h, r, inv, st.tiles_x, tcol, tile, &fr->i0, &fr->i1)) return false;
+  if (!fill_axis(fr->iy0, ny, h, r, inv, st.tiles_y, trow, tile, &fr->j0, &fr->j1)) return false;
+  const int jt = local / fr->nx, it = local - jt * fr->nx;
+  if (it < fr->i0 || it > fr->i1 || jt < fr->j0 || jt > fr->j1) return false;
+  fr->w = fr->i1 - fr->i0 + 1;
+  const int64_t n = (int64_t)fr->w * (fr->j1 - fr->j0 + 1);
+  fr->p_lo = at - ((jt - fr->j0) * fr->w + (it - fr->i0));
+  const int64_t p_hi = (int64_t)fr->p_lo + n - 1;
+  if (fr->p_lo < start || p_hi >= end) return false;
+  fr->p_hi = (int)p_hi;
+  const int g_lo = __builtin_amdgcn_readfirstlane(idx[fr->p_lo]);
+  const int g_hi = __builtin_amdgcn_readfirstlane(idx[fr->p_hi]);
+  return g_lo == fr->goff + fr->j0 * fr->nx + fr->i0 && g_hi == fr->goff + fr->j1 * fr->nx + fr->i1;
+}
+
+// Offsets (dx, dy) of a pixel's lattice neighbours inside the 6 sigma disc at
+// h = 1 (sigma = eta / rho, so k_sigma sigma = 4.5 with the paper's
+// constants): dx^2 + dy^2 <= R2, walked front to back (descending list
+// position: rows from the bottom, each from the right).
+constexpr int FR_R = 4;   // the largest |dx| the walk visits
+constexpr int FR_R2 = 20;  // dx^2 + dy^2 bound for k_sigma sigma = 4.5
+
 // LDS bytes per wavefront for a step of `depth` entries.
 // A forward entry: what every composited pixel reads, in one 32-byte record
 // (one LDS address per entry), and the colour, read where a run begins.
@@ -193,10 +279,11 @@ __device__ inline int step_floor(int h, int start, int depth, int end) {
 }
 
 template <int C, int TILE, int E, bool ANI>
-__global__ __launch_bounds__(BLOCK) void k_blend_fwd(
+__global__ __launch_bounds__(BLOCK, E == 1 ? (TILE == 32 ? 4 : 5) : 1) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
-    float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, int persistent) {
+    float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, const int32_t* __restrict__ plan,
+    int persistent) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   extern __shared__ __align__(16) char smem[];
@@ -207,6 +294,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
   FwdRec* wrec = (FwdRec*)mine_lds;
   float4* wcol = (float4*)(wrec + 64 * E);  // colour
   const uint64_t below = lanes_below();
+  // fill runs at h = 1 walk each pixel's lattice neighbours (see FillRun);
+  // the support radius must be the 4.5 the offsets are laid out for
+  const float hh = read_h(pr);
+  const bool fill_lattice = hh == 1.0f;
+  const float inv_tile = 1.0f / (float)TILE;
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
     if (item >= n_items) break;
@@ -261,7 +353,136 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(
       load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
       gnext[u] = k < nhi - nlo ? idx[nhi - 1 - k] : 0;
     }
+    // One fill run's positions fr.p_lo .. top at h = 1, front to back for each
+    // pixel: the colour run, the chunk boundaries and the per-pixel
+    // arithmetic are those of the entry-by-entry path, entry for entry.
+    auto fill_run_fwd = [&](const FillRun& fr, int top) {
+      constexpr int NB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
+      float* ol = (float*)mine_lds;            // [NB][NB] opacities (0: no Gaussian of the run waits there)
+      if (run_curve != fr.c) {                 // a run of this curve already open goes on
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const float a = Tst[q] - T[q];
+          acc[q][0] = __builtin_fmaf(rc0, a, acc[q][0]);
+          if (C == 3) {
+            acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
+            acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+          }
+          Tst[q] = T[q];
+        }
+        const float4 pc = w.gcol[fr.g_top];
+        rc0 = pc.x;
+        rc1 = pc.y;
+        rc2 = pc.z;
+        run_curve = fr.c;
+      }
+      const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
+      const int ib = x0 + qx - fr.ix0 - FR_R, jb = y0 + qy - fr.iy0 - FR_R;  // window index of cell (0, 0)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int sl = lane; sl < NB * NB; sl += 64) {
+        const int j = jb + sl / NB, i = ib + sl % NB;
+        float o = 0.0f;
+        if (i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1 &&
+            fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0) <= top)
+          o = gs[(int64_t)fr.goff + (int64_t)j * fr.nx + i].opacity;
+        ol[sl] = o;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double sgd = (double)fr.sigma;
+      const float coef = (float)(-0.5 * LOG2E / (sgd * sgd));  // as entry_geometry
+      int nb[PPT];
+      const int nb0 = end - (n_ck + 1) * CK;  // the next chunk boundary still to store
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) nb[q] = nb0;
+      // pixel q's LDS cell and the list position of its own lattice point:
+      // those of the lane's first pixel plus q's offset in the lane's block
+      int lx0, ly0;
+      pixel_of<TILE>(quad, lane, 0, &lx0, &ly0);
+      const int cell0 = (ly0 - qy + FR_R) * NB + (lx0 - qx + FR_R);
+      const int pb0 = fr.p_lo + (y0 + ly0 - fr.iy0 - fr.j0) * fr.w + (x0 + lx0 - fr.ix0 - fr.i0);
+      // the state of pixel q at chunk boundary nb[q] (all positions >= it done)
+      auto store_boundary = [&](int q) {
+        const float a = Tst[q] - T[q];
+        acc[q][0] = __builtin_fmaf(rc0, a, acc[q][0]);
+        if (C == 3) {
+          acc[q][1] = __builtin_fmaf(rc1, a, acc[q][1]);
+          acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
+        }
+        Tst[q] = T[q];
+        float* ckp = w.ckbuf + (int64_t)(ck0 + (end - nb[q]) / CK - 1) * (4 * TILE * TILE);
+        const int slot = (quad * PPT + q) * 64 + lane;
+        ckp[slot] = T[q];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+          ckp[(1 + ch) * TILE * TILE + slot] = acc[q][ch];
+          acc[q][ch] = 0.0f;
+        }
+        nb[q] -= CK;
+      };
+      // pixels are independent here: one pixel's whole walk at a time
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        for (int dy = FR_R; dy >= -FR_R; --dy) {
+          const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
+          const int roff = cell0 + (q / Cfg::BLK + dy) * NB + q % Cfg::BLK;
+          const int rpos = pb0 + (q / Cfg::BLK + dy) * fr.w + q % Cfg::BLK;
+#pragma unroll
+          for (int dx = FR_R; dx >= -FR_R; --dx) {
+            if (dx > dxm || dx < -dxm) continue;
+            const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
+            const float o = ol[roff + dx];
+            const int pos = rpos + dx;
+            if (o != 0.0f)
+              while (pos < nb[q]) store_boundary(q);
+            const float Tn = T[q] * (1.0f - fminf(amax, o * G));
+            const bool live = T[q] >= eps;
+            stop[q] = (live && Tn < eps) ? pos : stop[q];
+            T[q] = live ? Tn : T[q];
+          }
+        }
+      }
+      // boundaries at or above the run's bottom (none at or below start)
+      const int bl = max(fr.p_lo, start + 1);
+#pragma unroll
+      for (int q = 0; q < PPT; ++q)
+        while (nb[q] >= bl) store_boundary(q);
+      n_ck = (end - bl) / CK;
+    };
     while (hi > start) {
+      if (fill_lattice && __builtin_amdgcn_readfirstlane(e[0].kind) == 1) {
+        // the next entry (position hi - 1, lane 0's first) is a fill
+        // Gaussian: take its run's remaining positions pixel by pixel
+        FillRun fr;
+        const int c = __builtin_amdgcn_readfirstlane(e[0].r.curve);
+        const float sg = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e[0].r.sigma)));
+        const float rr = ks * sg;
+        if (rr * rr >= (float)FR_R2 && rr * rr < (float)(FR_R2 + 5) &&
+            fill_run_at(plan, idx, c, __builtin_amdgcn_readfirstlane(e[0].g),
+                        __builtin_amdgcn_readfirstlane(e[0].r.local), sg, hi - 1, start, end, 1.0, ks, inv_tile, st, lt,
+                        TILE, &fr)) {
+          fill_run_fwd(fr, hi - 1);
+          hi = fr.p_lo;
+          // the next step's loads, as at the start of the list
+          lo_s = step_floor(hi, start, depth, end);
+          nhi = lo_s;
+          nlo = step_floor(nhi, start, depth, end);
+#pragma unroll
+          for (int u = 0; u < E; ++u) {
+            const int k = u * 64 + lane;
+            load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
+            gnext[u] = k < nhi - nlo ? idx[nhi - 1 - k] : 0;
+          }
+          bool done = true;
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) done = done && !(T[q] >= eps);
+          if (__ballot(!done) == 0ull) break;  // every pixel of the quadrant has stopped
+          continue;
+        }
+      }
       int cnt = 0;
       bool step_aniso = false;
 #pragma unroll
@@ -1011,7 +1232,7 @@ hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last,
   Phase ph(L, NSPLAT_T_BLEND_FWD);
   hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
-                     T_final, n_last, persistent);
+                     T_final, n_last, L.bf->plan, persistent);
   return hipGetLastError();
 }
 

@@ -279,6 +279,18 @@ __device__ inline double sample_u(double a, double b, int j, int count, bool clo
 
 __device__ inline float read_h(const nsplat_params& pr) { return pr.h_dev ? *pr.h_dev : pr.h; }
 
+// One axis of a Gaussian's binning rectangle (Sec. 3.4): from m = fl32(mu)
+// and r = k_sigma sigma in FP32, the interval [(m - r) - 1, (m + r) + 1] in
+// tiles, floor(x / tile) clamped to [0, n - 1] (f0 > f1: no tile).  False for
+// a NaN bound.
+__device__ inline bool tile_axis(float m, float r, float inv_tile, int n, float* f0, float* f1) {
+  const float lo = (m - r) - 1.0f, hi = (m + r) + 1.0f;
+  if (!(lo == lo) || !(hi == hi)) return false;
+  *f0 = fmaxf(0.0f, floorf(lo * inv_tile));
+  *f1 = fminf((float)(n - 1), floorf(hi * inv_tile));
+  return true;
+}
+
 // Scene of a global tile index (binary search over the scene table).
 // The curve of Gaussian g: the last c with goff[c] <= g (goff ascending,
 // goff[0] = 0).
