@@ -242,6 +242,9 @@ __device__ inline bool fill_run_at(const int32_t* __restrict__ plan, const int32
 // position: rows from the bottom, each from the right).
 constexpr int FR_R = 4;   // the largest |dx| the walk visits
 constexpr int FR_R2 = 20;  // dx^2 + dy^2 bound for k_sigma sigma = 4.5
+// LDS row stride of the adjoint's lattice cells: 24 floats puts the four
+// lane rows of a half-wavefront in four different bank octets
+constexpr int FR_NS = 24;
 
 // LDS bytes per wavefront for a step of `depth` entries.
 // A forward entry: what every composited pixel reads, in one 32-byte record
@@ -264,8 +267,9 @@ constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, 
 // wavefront's LDS slice small enough for six wavefronts per SIMD; the others
 // (held to fewer wavefronts by their registers) park 16.
 constexpr int RB_ROW = 68;  // floats per parked row
-__host__ __device__ constexpr bool bwd_six_waves(int tile, int E) { return tile <= 16 && E == 1; }
+__host__ __device__ constexpr bool bwd_six_waves(int tile, int E) { return false; }
 __host__ __device__ constexpr int park_rows(int tile, int E) { return bwd_six_waves(tile, E) ? 12 : 16; }
+__host__ __device__ constexpr int bwd_waves(int tile, int E) { return E == 1 ? (tile <= 16 ? 5 : 4) : 1; }
 __host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E) {
   return ((size_t)64 * E * BWD_ENTRY_BYTES + (size_t)park_rows(tile, E) * (RB_ROW * 4 + 8) + 15) / 16 * 16;
 }
@@ -381,13 +385,16 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? (TILE == 32 ? 4 : 5) : 1) void k_bl
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int sl = lane; sl < NB * NB; sl += 64) {
+      // (unrolled, so that all the gathers are in flight before the first wait)
+#pragma unroll
+      for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
+        const int sl = it * 64 + lane;
         const int j = jb + sl / NB, i = ib + sl % NB;
         float o = 0.0f;
-        if (i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1 &&
+        if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1 &&
             fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0) <= top)
           o = gs[(int64_t)fr.goff + (int64_t)j * fr.nx + i].opacity;
-        ol[sl] = o;
+        if (sl < NB * NB) ol[sl] = o;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -426,6 +433,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? (TILE == 32 ? 4 : 5) : 1) void k_bl
       // pixels are independent here: one pixel's whole walk at a time
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
+#pragma unroll 1
         for (int dy = FR_R; dy >= -FR_R; --dy) {
           const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
           const int roff = cell0 + (q / Cfg::BLK + dy) * NB + q % Cfg::BLK;
@@ -817,11 +825,11 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // lane at depth 64, four for 32 x 32 tiles at depth 64 (128 VGPRs, unspilled);
 // elsewhere the registers decide.
 template <int C, int TILE, int E, bool ANI>
-__global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && E == 1 ? 4 : 1)) void k_blend_bwd(
+__global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
-    int persistent) {
+    const int32_t* __restrict__ plan, int persistent) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
@@ -829,6 +837,9 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
   const int depth = min(pr.batch, 64 * E);
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
+  // fill runs pixel by pixel (see FillRun), with one pixel per lane
+  const bool fill_lattice = PPT == 1 && read_h(pr) == 1.0f;
+  const float inv_tile = 1.0f / (float)TILE;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   constexpr int RB = park_rows(TILE, E);
   char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(TILE, E);
@@ -934,7 +945,142 @@ __global__ __launch_bounds__(BLOCK, bwd_six_waves(TILE, E) ? 6 : (TILE == 32 && 
       const int k = u * 64 + lane;
       load_entry(idx, gs, w.gcol, s_lo + k, k < s_hi - s_lo, &e[u]);
     }
+    // One fill run's positions p0 .. p1 at h = 1, back to front for each
+    // pixel over its in-disc lattice neighbours (the reverse of the forward's
+    // walk), with the per-pixel arithmetic of the entry-by-entry path; each
+    // Gaussian's dL/do_j is summed over the lanes in LDS and added with one
+    // atomic.
+    auto fill_run_bwd = [&](const FillRun& fr, int p0, int p1) {
+      // (one pixel per lane: lane (l & 7, l >> 3) of the quadrant's 8 x 8
+      // block; fill_lattice is false otherwise)
+      constexpr int NB = Cfg::SUB + 2 * FR_R;  // 16 cells per axis
+      constexpr int NS = FR_NS;                // LDS row stride (conflict-free rows)
+      float* ol = (float*)mine_lds;  // [NB][NS] opacities (NaN: no Gaussian at p0 .. p1 there)
+      float* gl = park;              // [NB][NS] dL/do_j
+      if (n_rows > 0) {
+        flush_rows<RB>(park, ptgt, n_rows, ggrad);
+        n_rows = 0;
+      }
+      if (cur != fr.c) {  // a new curve: close the previous one, W for the new K
+        if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, aT, accO);
+        const float4 pc = w.gcol[fr.g_top];
+        const float col[3] = {pc.x, pc.y, pc.z};
+        float K = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) K = __builtin_fmaf(gI[0][ch], col[ch], K);
+        Wc[0] = __builtin_fmaf(-K, T[0], __builtin_fmaf(Kc[0], T[0], Wc[0]));
+        Kc[0] = K;
+        cur = fr.c;
+        cur_fill = true;
+        cur_aniso = false;
+        since = 0;
+      }
+      const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
+      const int ib = x0 + qx - fr.ix0 - FR_R, jb = y0 + qy - fr.iy0 - FR_R;  // window index of cell (0, 0)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // (unrolled, so that all the gathers are in flight before the first wait)
+#pragma unroll
+      for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
+        const int sl = it * 64 + lane;
+        const int j = jb + sl / NB, i = ib + sl % NB;
+        float o = __builtin_nanf("");
+        if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1) {
+          const int pos = fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0);
+          if (pos >= p0 && pos <= p1) o = gs[(int64_t)fr.goff + (int64_t)j * fr.nx + i].opacity;
+        }
+        if (sl < NB * NB) {
+          ol[(sl / NB) * NS + sl % NB] = o;
+          gl[(sl / NB) * NS + sl % NB] = 0.0f;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double sgd = (double)fr.sigma;
+      const float coef = (float)(-0.5 * LOG2E / (sgd * sgd));  // as entry_geometry
+      const int lx = lane & 7, ly = lane >> 3;
+      const bool col0 = lx == 0, col7 = lx == 7;
+      const int pb0 = fr.p_lo + (y0 + qy + ly - fr.iy0 - fr.j0) * fr.w + (x0 + qx + lx - fr.ix0 - fr.i0);
+#pragma unroll 1
+      for (int dy = -FR_R; dy <= FR_R; ++dy) {
+        const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
+        const int roff = (ly + dy + FR_R) * NS + lx + FR_R;         // this pixel's cell in row dy
+        const int rpos = pb0 + dy * fr.w;
+        float v[2 * FR_R + 1];
+#pragma unroll
+        for (int dx = -FR_R; dx <= FR_R; ++dx) {
+          v[dx + FR_R] = 0.0f;
+          if (dx > dxm || dx < -dxm) continue;
+          const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
+          const float o = ol[roff + dx];
+          const bool in = (o == o) && (rpos + dx >= stop[0]);
+          const float oG = o * G;
+          const float alpha = in ? fminf(oG, amax) : 0.0f;
+          const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+          const float dLda = (in && oG < amax) ? -Wc[0] * r : 0.0f;
+          T[0] = in ? T[0] * r : T[0];
+          aT[0] = __builtin_fmaf(alpha, T[0], aT[0]);
+          v[dx + FR_R] = dLda * G;  // dL/do_j of the cell at dx (0 unless in)
+        }
+        // the row's cells get their sums over the pixels of each lane row
+        // by two sliding sums along the row (DPP shifts by one lane, 8-lane
+        // groups kept apart): P ends with cell lx - 4, Q with cell lx + 4
+        float P = v[2 * FR_R], Q = v[0];
+#pragma unroll
+        for (int k = 1; k <= 2 * FR_R; ++k) {
+          const float ps = col7 ? 0.0f : P, qs = col0 ? 0.0f : Q;
+          P = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(ps), 0x111, 0xf, 0xf, true)) +
+              v[2 * FR_R - k];  // row_shr:1
+          Q = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(qs), 0x101, 0xf, 0xf, true)) +
+              v[k];  // row_shl:1
+        }
+        const int crow = (ly + dy + FR_R) * NS;  // cell row of this lane row
+        gl[crow + lx] += P;                      // cell column lx - 4
+        gl[crow + lx + 2 * FR_R] += Q;           // cell column lx + 4
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
+        const int sl = it * 64 + lane;
+        if (sl >= NB * NB) continue;
+        const float o = ol[(sl / NB) * NS + sl % NB], val = gl[(sl / NB) * NS + sl % NB];
+        if (o == o && val != 0.0f) {
+          const int j = jb + sl / NB, i = ib + sl % NB;
+          unsafeAtomicAdd(ggrad + ((int64_t)fr.goff + (int64_t)j * fr.nx + i) * GG + 3, val);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     while (s_lo < c_hi) {
+      if (fill_lattice && __builtin_amdgcn_readfirstlane(e[0].kind) == 1) {
+        // the next entry (position s_lo, lane 0's first) is a fill Gaussian:
+        // take its run's positions in this chunk pixel by pixel
+        FillRun fr;
+        const int c = __builtin_amdgcn_readfirstlane(e[0].r.curve);
+        const float sg = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e[0].r.sigma)));
+        const float rr = ks * sg;
+        if (rr * rr >= (float)FR_R2 && rr * rr < (float)(FR_R2 + 5) &&
+            fill_run_at(plan, idx, c, __builtin_amdgcn_readfirstlane(e[0].g),
+                        __builtin_amdgcn_readfirstlane(e[0].r.local), sg, s_lo, start, end, 1.0, ks, inv_tile, st, lt,
+                        TILE, &fr)) {
+          const int p1 = min(fr.p_hi, c_hi - 1);
+          fill_run_bwd(fr, s_lo, p1);
+          s_lo = p1 + 1;
+          s_hi = min(c_hi, s_lo + depth);
+#pragma unroll
+          for (int u = 0; u < E; ++u) {
+            const int k = u * 64 + lane;
+            load_entry(idx, gs, w.gcol, s_lo + k, k < s_hi - s_lo, &e[u]);
+          }
+          continue;
+        }
+      }
       int cnt = 0;
       // pixels that take part somewhere in this step (their stop lies below
       // its top); walking back to front the set only grows.  Entries that
@@ -1251,7 +1397,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   Phase ph(L, NSPLAT_T_BLEND_BWD);
   hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
-                     dL, T_final, n_last, persistent);
+                     dL, T_final, n_last, L.bf->plan, persistent);
   return hipGetLastError();
 }
 
