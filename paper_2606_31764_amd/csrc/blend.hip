@@ -32,6 +32,9 @@ struct TileCfg {
   static constexpr int PPT = BLK * BLK;
 };
 constexpr int WPB = 4;                  // wavefronts per block
+// Kernel forms (template KIND): with the tangent-aligned kind, with the
+// fill-run walk (see FillRun).
+constexpr int KIND_ANI = 1, KIND_FILL = 2;
 constexpr int BLOCK = 64 * WPB;
 
 template <int TILE>
@@ -267,11 +270,17 @@ constexpr int BWD_ENTRY_BYTES = 48;   // geometry, opacity + colour, (g, curve, 
 // wavefront's LDS slice small enough for six wavefronts per SIMD; the others
 // (held to fewer wavefronts by their registers) park 16.
 constexpr int RB_ROW = 68;  // floats per parked row
-__host__ __device__ constexpr bool bwd_six_waves(int tile, int E) { return false; }
-__host__ __device__ constexpr int park_rows(int tile, int E) { return bwd_six_waves(tile, E) ? 12 : 16; }
-__host__ __device__ constexpr int bwd_waves(int tile, int E) { return E == 1 ? (tile <= 16 ? 5 : 4) : 1; }
-__host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E) {
-  return ((size_t)64 * E * BWD_ENTRY_BYTES + (size_t)park_rows(tile, E) * (RB_ROW * 4 + 8) + 15) / 16 * 16;
+__host__ __device__ constexpr bool bwd_six_waves(int tile, int E, int kind) {
+  return tile <= 16 && E == 1 && !(kind & KIND_FILL);
+}
+__host__ __device__ constexpr int park_rows(int tile, int E, int kind) { return bwd_six_waves(tile, E, kind) ? 12 : 16; }
+// wavefronts per SIMD the adjoint is built for: six without the fill-run
+// walk at one pixel per lane and depth 64, five with it
+__host__ __device__ constexpr int bwd_waves(int tile, int E, int kind) {
+  return bwd_six_waves(tile, E, kind) ? 6 : (E == 1 ? (tile <= 16 ? 5 : 4) : 1);
+}
+__host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E, int kind) {
+  return ((size_t)64 * E * BWD_ENTRY_BYTES + (size_t)park_rows(tile, E, kind) * (RB_ROW * 4 + 8) + 15) / 16 * 16;
 }
 
 // Lower end of the step that starts at list position h (walking down from
@@ -282,8 +291,8 @@ __device__ inline int step_floor(int h, int start, int depth, int end) {
   return max(max(start, h - depth), end - (k + 1) * CK);
 }
 
-template <int C, int TILE, int E, bool ANI>
-__global__ __launch_bounds__(BLOCK, E == 1 ? (TILE == 32 ? 4 : 5) : 1) void k_blend_fwd(
+template <int C, int TILE, int E, int KIND>
+__global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, const int32_t* __restrict__ plan,
@@ -298,10 +307,10 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? (TILE == 32 ? 4 : 5) : 1) void k_bl
   FwdRec* wrec = (FwdRec*)mine_lds;
   float4* wcol = (float4*)(wrec + 64 * E);  // colour
   const uint64_t below = lanes_below();
+  constexpr bool ANI = (KIND & KIND_ANI) != 0;
   // fill runs at h = 1 walk each pixel's lattice neighbours (see FillRun);
   // the support radius must be the 4.5 the offsets are laid out for
-  const float hh = read_h(pr);
-  const bool fill_lattice = hh == 1.0f;
+  const bool fill_lattice = (KIND & KIND_FILL) != 0 && read_h(pr) == 1.0f;
   const float inv_tile = 1.0f / (float)TILE;
   for (int it = 0;; ++it) {
     const int item = next_item(it, persistent, w.queue);
@@ -824,8 +833,8 @@ __device__ inline void flush_rows(const float* park, const int2* tgt, int n, flo
 // per-entry curve test.  Occupancy: six wavefronts per SIMD for one pixel per
 // lane at depth 64, four for 32 x 32 tiles at depth 64 (128 VGPRs, unspilled);
 // elsewhere the registers decide.
-template <int C, int TILE, int E, bool ANI>
-__global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E)) void k_blend_bwd(
+template <int C, int TILE, int E, int KIND>
+__global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
@@ -837,12 +846,13 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E)) void k_blend_bwd(
   const int depth = min(pr.batch, 64 * E);
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
+  constexpr bool ANI = (KIND & KIND_ANI) != 0;
   // fill runs pixel by pixel (see FillRun), with one pixel per lane
-  const bool fill_lattice = PPT == 1 && read_h(pr) == 1.0f;
+  const bool fill_lattice = (KIND & KIND_FILL) != 0 && PPT == 1 && read_h(pr) == 1.0f;
   const float inv_tile = 1.0f / (float)TILE;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  constexpr int RB = park_rows(TILE, E);
-  char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(TILE, E);
+  constexpr int RB = park_rows(TILE, E, KIND);
+  char* mine_lds = smem + (size_t)wv * bwd_wave_bytes(TILE, E, KIND);
   float4* wgeo = (float4*)mine_lds;
   float4* wpc = wgeo + 64 * E;
   int4* wmeta = (int4*)(wpc + 64 * E);  // (g, or ~g for fills), curve, list position, 1/sigma^3 bits
@@ -1365,70 +1375,84 @@ int resident_grid(K kernel, int n_blocks, int n_cu, size_t lds) {
 
 inline int depth_factor(int batch) { return batch <= 64 ? 1 : (batch <= 128 ? 2 : 4); }
 
-template <int C, int TILE, int E, bool ANI>
+template <int C, int TILE, int E, int KIND>
 hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
   const int n_items = (int)L.n_tiles * TileCfg<TILE>::QUADS;
   if (n_items <= 0) return hipSuccess;
   const size_t lds = (size_t)WPB * 64 * E * FWD_ENTRY_BYTES;
   int grid = (n_items + WPB - 1) / WPB;
   if (persistent) {
-    grid = resident_grid(k_blend_fwd<C, TILE, E, ANI>, grid, L.n_cu, lds);
+    grid = resident_grid(k_blend_fwd<C, TILE, E, KIND>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_FWD);
-  hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
                      T_final, n_last, L.bf->plan, persistent);
   return hipGetLastError();
 }
 
-template <int C, int TILE, int E, bool ANI>
+template <int C, int TILE, int E, int KIND>
 hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
   if (L.n_tiles <= 0) return hipSuccess;
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
   const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * (L.bf->caps.pairs / CK + L.n_tiles);
-  const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E);
+  const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E, KIND);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {
-    grid = resident_grid(k_blend_bwd<C, TILE, E, ANI>, grid, L.n_cu, lds);
+    grid = resident_grid(k_blend_bwd<C, TILE, E, KIND>, grid, L.n_cu, lds);
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, L.stream, L.w.queue);
   }
   Phase ph(L, NSPLAT_T_BLEND_BWD);
-  hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, ANI>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
+  hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
                      dL, T_final, n_last, L.bf->plan, persistent);
   return hipGetLastError();
 }
 
-// The tangent-aligned kind is compiled in only for batches that declare it
-// (nsplat_curves.any_flags), so that the other batches run without its
-// branches and registers.
-inline bool any_aniso(const Launch& L) { return (L.cv->any_flags & NSPLAT_ANISO) != 0; }
+// The tangent-aligned kind and the fill-run walk are compiled in only for
+// batches that declare such curves (nsplat_curves.any_flags), so that the
+// other batches run without their branches and registers.
+inline int kinds_of(const Launch& L) {
+  return ((L.cv->any_flags & NSPLAT_ANISO) ? KIND_ANI : 0) | ((L.cv->any_flags & NSPLAT_FILLED) ? KIND_FILL : 0);
+}
+
+template <int C, int TILE, int E>
+hipError_t fwd_k(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
+  switch (kinds_of(L)) {
+    case 0: return fwd_t<C, TILE, E, 0>(L, image, T_final, n_last, persistent);
+    case KIND_ANI: return fwd_t<C, TILE, E, KIND_ANI>(L, image, T_final, n_last, persistent);
+    case KIND_FILL: return fwd_t<C, TILE, E, KIND_FILL>(L, image, T_final, n_last, persistent);
+    default: return fwd_t<C, TILE, E, KIND_ANI | KIND_FILL>(L, image, T_final, n_last, persistent);
+  }
+}
 
 template <int C, int TILE>
 hipError_t fwd_d(const Launch& L, float* image, float* T_final, int32_t* n_last, int persistent) {
-  const bool a = any_aniso(L);
   switch (depth_factor(L.pr->batch)) {
-    case 1: return a ? fwd_t<C, TILE, 1, true>(L, image, T_final, n_last, persistent)
-                     : fwd_t<C, TILE, 1, false>(L, image, T_final, n_last, persistent);
-    case 2: return a ? fwd_t<C, TILE, 2, true>(L, image, T_final, n_last, persistent)
-                     : fwd_t<C, TILE, 2, false>(L, image, T_final, n_last, persistent);
-    default: return a ? fwd_t<C, TILE, 4, true>(L, image, T_final, n_last, persistent)
-                      : fwd_t<C, TILE, 4, false>(L, image, T_final, n_last, persistent);
+    case 1: return fwd_k<C, TILE, 1>(L, image, T_final, n_last, persistent);
+    case 2: return fwd_k<C, TILE, 2>(L, image, T_final, n_last, persistent);
+    default: return fwd_k<C, TILE, 4>(L, image, T_final, n_last, persistent);
+  }
+}
+
+template <int C, int TILE, int E>
+hipError_t bwd_k(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
+  switch (kinds_of(L)) {
+    case 0: return bwd_t<C, TILE, E, 0>(L, dL, T_final, n_last, persistent);
+    case KIND_ANI: return bwd_t<C, TILE, E, KIND_ANI>(L, dL, T_final, n_last, persistent);
+    case KIND_FILL: return bwd_t<C, TILE, E, KIND_FILL>(L, dL, T_final, n_last, persistent);
+    default: return bwd_t<C, TILE, E, KIND_ANI | KIND_FILL>(L, dL, T_final, n_last, persistent);
   }
 }
 
 template <int C, int TILE>
 hipError_t bwd_d(const Launch& L, const float* dL, const float* T_final, const int32_t* n_last, int persistent) {
-  const bool a = any_aniso(L);
   switch (depth_factor(L.pr->batch)) {
-    case 1: return a ? bwd_t<C, TILE, 1, true>(L, dL, T_final, n_last, persistent)
-                     : bwd_t<C, TILE, 1, false>(L, dL, T_final, n_last, persistent);
-    case 2: return a ? bwd_t<C, TILE, 2, true>(L, dL, T_final, n_last, persistent)
-                     : bwd_t<C, TILE, 2, false>(L, dL, T_final, n_last, persistent);
-    default: return a ? bwd_t<C, TILE, 4, true>(L, dL, T_final, n_last, persistent)
-                      : bwd_t<C, TILE, 4, false>(L, dL, T_final, n_last, persistent);
+    case 1: return bwd_k<C, TILE, 1>(L, dL, T_final, n_last, persistent);
+    case 2: return bwd_k<C, TILE, 2>(L, dL, T_final, n_last, persistent);
+    default: return bwd_k<C, TILE, 4>(L, dL, T_final, n_last, persistent);
   }
 }
 
