@@ -205,12 +205,12 @@ __device__ inline bool fill_axis(int org, int n, double h, float r, float inv, i
 }
 
 // The run of fill curve c that holds list position `at` (whose Gaussian has
-// window index `local`), if the list holds the whole rectangle there: its two
-// corners are checked in the list, so a run cut short (capacity overflow)
-// is left to the entry-by-entry path.  Wavefront-uniform.
-__device__ inline bool fill_run_at(const int32_t* __restrict__ plan, const int32_t* __restrict__ idx, int c, int g,
-                                   int local, float sigma, int at, int start, int end, double h, float ks, float inv,
-                                   const SceneTab& st, int lt, int tile, FillRun* fr) {
+// window index `local`): its rectangle and list positions, if they fit the
+// list.  Wavefront-uniform.  Whether the list holds the whole rectangle there
+// is for fill_corners_ok to say.
+__device__ inline bool fill_run_at(const int32_t* __restrict__ plan, int c, int g, int local, float sigma, int at,
+                                   int start, int end, double h, float ks, float inv, const SceneTab& st, int lt,
+                                   int tile, FillRun* fr) {
   typedef const __attribute__((address_space(4))) int32_t* cip;
   const cip row = (cip)(plan + (int64_t)P_STRIDE * c);
   fr->c = c;
@@ -234,9 +234,36 @@ __device__ inline bool fill_run_at(const int32_t* __restrict__ plan, const int32
   const int64_t p_hi = (int64_t)fr->p_lo + n - 1;
   if (fr->p_lo < start || p_hi >= end) return false;
   fr->p_hi = (int)p_hi;
-  const int g_lo = __builtin_amdgcn_readfirstlane(idx[fr->p_lo]);
-  const int g_hi = __builtin_amdgcn_readfirstlane(idx[fr->p_hi]);
-  return g_lo == fr->goff + fr->j0 * fr->nx + fr->i0 && g_hi == fr->goff + fr->j1 * fr->nx + fr->i1;
+  return true;
+}
+
+// The run's two corner entries are those of the rectangle: otherwise (a run
+// cut short by a capacity overflow) it is left to the entry-by-entry path.
+__device__ inline bool fill_corners_ok(const int32_t* __restrict__ idx, const FillRun& fr) {
+  const int g_lo = __builtin_amdgcn_readfirstlane(idx[fr.p_lo]);
+  const int g_hi = __builtin_amdgcn_readfirstlane(idx[fr.p_hi]);
+  return g_lo == fr.goff + fr.j0 * fr.nx + fr.i0 && g_hi == fr.goff + fr.j1 * fr.nx + fr.i1;
+}
+
+// Opacities of the quadrant's lattice neighbourhood (NB x NB cells, window
+// index (ib, jb) at cell 0; lane l gathers cells it * 64 + l): those of the
+// run's Gaussians at list positions p0 .. p1, `none` elsewhere.  Reads below
+// the record capacity only, so that a rectangle still to be checked is safe.
+template <int NB, int NIT>
+__device__ inline void fill_gather(const Gauss* __restrict__ gs, int64_t gcap, const FillRun& fr, int ib, int jb,
+                                   int p0, int p1, float none, float (&og)[NIT]) {
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int sl = it * 64 + (int)__lane_id();
+    const int j = jb + sl / NB, i = ib + sl % NB;
+    float o = none;
+    if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1) {
+      const int pos = fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0);
+      const int64_t g = (int64_t)fr.goff + (int64_t)j * fr.nx + i;
+      if (pos >= p0 && pos <= p1 && g < gcap) o = gs[g].opacity;
+    }
+    og[it] = o;
+  }
 }
 
 // Offsets (dx, dy) of a pixel's lattice neighbours inside the 6 sigma disc at
@@ -296,7 +323,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, const int32_t* __restrict__ plan,
-    int persistent) {
+    int64_t gcap, int persistent) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   extern __shared__ __align__(16) char smem[];
@@ -369,8 +396,10 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     // One fill run's positions fr.p_lo .. top at h = 1, front to back for each
     // pixel: the colour run, the chunk boundaries and the per-pixel
     // arithmetic are those of the entry-by-entry path, entry for entry.
-    auto fill_run_fwd = [&](const FillRun& fr, int top) {
-      constexpr int NB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
+    constexpr int FNB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
+    constexpr int FNIT = (FNB * FNB + 63) / 64;
+    auto fill_run_fwd = [&](const FillRun& fr, int top, const float (&og)[FNIT]) {
+      constexpr int NB = FNB;
       float* ol = (float*)mine_lds;            // [NB][NB] opacities (0: no Gaussian of the run waits there)
       if (run_curve != fr.c) {                 // a run of this curve already open goes on
 #pragma unroll
@@ -390,21 +419,12 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
         run_curve = fr.c;
       }
       const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
-      const int ib = x0 + qx - fr.ix0 - FR_R, jb = y0 + qy - fr.iy0 - FR_R;  // window index of cell (0, 0)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // (unrolled, so that all the gathers are in flight before the first wait)
 #pragma unroll
-      for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
-        const int sl = it * 64 + lane;
-        const int j = jb + sl / NB, i = ib + sl % NB;
-        float o = 0.0f;
-        if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1 &&
-            fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0) <= top)
-          o = gs[(int64_t)fr.goff + (int64_t)j * fr.nx + i].opacity;
-        if (sl < NB * NB) ol[sl] = o;
-      }
+      for (int it = 0; it < FNIT; ++it)
+        if (it * 64 + lane < NB * NB) ol[it * 64 + lane] = og[it];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -447,18 +467,30 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
           const int roff = cell0 + (q / Cfg::BLK + dy) * NB + q % Cfg::BLK;
           const int rpos = pb0 + (q / Cfg::BLK + dy) * fr.w + q % Cfg::BLK;
+          // the row's opacities first, one LDS wait per row
+          float orow[2 * FR_R + 1];
 #pragma unroll
-          for (int dx = FR_R; dx >= -FR_R; --dx) {
-            if (dx > dxm || dx < -dxm) continue;
+          for (int dx = -FR_R; dx <= FR_R; ++dx) orow[dx + FR_R] = ol[roff + dx];
+          auto cell = [&](int dx, bool check) {
             const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
-            const float o = ol[roff + dx];
+            const float o = orow[dx + FR_R];
             const int pos = rpos + dx;
-            if (o != 0.0f)
+            if (check && o != 0.0f)
               while (pos < nb[q]) store_boundary(q);
             const float Tn = T[q] * (1.0f - fminf(amax, o * G));
             const bool live = T[q] >= eps;
             stop[q] = (live && Tn < eps) ? pos : stop[q];
             T[q] = live ? Tn : T[q];
+          };
+          // a chunk boundary falls in the row of some lane only now and then
+          if (__ballot(rpos - dxm < nb[q]) == 0ull) {
+#pragma unroll
+            for (int dx = FR_R; dx >= -FR_R; --dx)
+              if (dx <= dxm && dx >= -dxm) cell(dx, false);
+          } else {
+#pragma unroll
+            for (int dx = FR_R; dx >= -FR_R; --dx)
+              if (dx <= dxm && dx >= -dxm) cell(dx, true);
           }
         }
       }
@@ -477,13 +509,21 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
         const int c = __builtin_amdgcn_readfirstlane(e[0].r.curve);
         const float sg = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e[0].r.sigma)));
         const float rr = ks * sg;
+        float og[FNIT];
+        bool take = false;
         if (rr * rr >= (float)FR_R2 && rr * rr < (float)(FR_R2 + 5) &&
-            fill_run_at(plan, idx, c, __builtin_amdgcn_readfirstlane(e[0].g),
-                        __builtin_amdgcn_readfirstlane(e[0].r.local), sg, hi - 1, start, end, 1.0, ks, inv_tile, st, lt,
-                        TILE, &fr)) {
-          fill_run_fwd(fr, hi - 1);
+            fill_run_at(plan, c, __builtin_amdgcn_readfirstlane(e[0].g), __builtin_amdgcn_readfirstlane(e[0].r.local),
+                        sg, hi - 1, start, end, 1.0, ks, inv_tile, st, lt, TILE, &fr)) {
+          // the opacities and the corner check in flight together
+          const int ib = x0 + (quad & 1) * Cfg::SUB - fr.ix0 - FR_R, jb = y0 + (quad >> 1) * Cfg::SUB - fr.iy0 - FR_R;
+          fill_gather<FNB, FNIT>(gs, gcap, fr, ib, jb, fr.p_lo, hi - 1, 0.0f, og);
+          take = fill_corners_ok(idx, fr);
+        }
+        if (take) {
+          const int top = hi - 1;
           hi = fr.p_lo;
-          // the next step's loads, as at the start of the list
+          // the next step's loads (as at the start of the list), in flight
+          // during the walk
           lo_s = step_floor(hi, start, depth, end);
           nhi = lo_s;
           nlo = step_floor(nhi, start, depth, end);
@@ -493,6 +533,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
             load_entry(idx, gs, w.gcol, hi - 1 - k, k < hi - lo_s, &e[u]);
             gnext[u] = k < nhi - nlo ? idx[nhi - 1 - k] : 0;
           }
+          fill_run_fwd(fr, top, og);
           bool done = true;
 #pragma unroll
           for (int q = 0; q < PPT; ++q) done = done && !(T[q] >= eps);
@@ -838,7 +879,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
-    const int32_t* __restrict__ plan, int persistent) {
+    const int32_t* __restrict__ plan, int64_t gcap, int persistent) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
@@ -960,10 +1001,12 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     // walk), with the per-pixel arithmetic of the entry-by-entry path; each
     // Gaussian's dL/do_j is summed over the lanes in LDS and added with one
     // atomic.
-    auto fill_run_bwd = [&](const FillRun& fr, int p0, int p1) {
+    constexpr int BNB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
+    constexpr int BNIT = (BNB * BNB + 63) / 64;
+    auto fill_run_bwd = [&](const FillRun& fr, const float (&og)[BNIT]) {
       // (one pixel per lane: lane (l & 7, l >> 3) of the quadrant's 8 x 8
       // block; fill_lattice is false otherwise)
-      constexpr int NB = Cfg::SUB + 2 * FR_R;  // 16 cells per axis
+      constexpr int NB = BNB;                  // 16 cells per axis
       constexpr int NS = FR_NS;                // LDS row stride (conflict-free rows)
       float* ol = (float*)mine_lds;  // [NB][NS] opacities (NaN: no Gaussian at p0 .. p1 there)
       float* gl = park;              // [NB][NS] dL/do_j
@@ -990,18 +1033,11 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // (unrolled, so that all the gathers are in flight before the first wait)
 #pragma unroll
-      for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
+      for (int it = 0; it < BNIT; ++it) {
         const int sl = it * 64 + lane;
-        const int j = jb + sl / NB, i = ib + sl % NB;
-        float o = __builtin_nanf("");
-        if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1) {
-          const int pos = fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0);
-          if (pos >= p0 && pos <= p1) o = gs[(int64_t)fr.goff + (int64_t)j * fr.nx + i].opacity;
-        }
         if (sl < NB * NB) {
-          ol[(sl / NB) * NS + sl % NB] = o;
+          ol[(sl / NB) * NS + sl % NB] = og[it];
           gl[(sl / NB) * NS + sl % NB] = 0.0f;
         }
       }
@@ -1018,13 +1054,17 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
         const int roff = (ly + dy + FR_R) * NS + lx + FR_R;         // this pixel's cell in row dy
         const int rpos = pb0 + dy * fr.w;
+        // the row's opacities first, one LDS wait per row; each becomes
+        // the cell's dL/do_j in place
         float v[2 * FR_R + 1];
 #pragma unroll
+        for (int dx = -FR_R; dx <= FR_R; ++dx) v[dx + FR_R] = ol[roff + dx];
+#pragma unroll
         for (int dx = -FR_R; dx <= FR_R; ++dx) {
+          const float o = v[dx + FR_R];
           v[dx + FR_R] = 0.0f;
           if (dx > dxm || dx < -dxm) continue;
           const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
-          const float o = ol[roff + dx];
           const bool in = (o == o) && (rpos + dx >= stop[0]);
           const float oG = o * G;
           const float alpha = in ? fminf(oG, amax) : 0.0f;
@@ -1075,12 +1115,20 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         const int c = __builtin_amdgcn_readfirstlane(e[0].r.curve);
         const float sg = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e[0].r.sigma)));
         const float rr = ks * sg;
+        float og[BNIT];
+        bool take = false;
+        int p1 = 0;
         if (rr * rr >= (float)FR_R2 && rr * rr < (float)(FR_R2 + 5) &&
-            fill_run_at(plan, idx, c, __builtin_amdgcn_readfirstlane(e[0].g),
-                        __builtin_amdgcn_readfirstlane(e[0].r.local), sg, s_lo, start, end, 1.0, ks, inv_tile, st, lt,
-                        TILE, &fr)) {
-          const int p1 = min(fr.p_hi, c_hi - 1);
-          fill_run_bwd(fr, s_lo, p1);
+            fill_run_at(plan, c, __builtin_amdgcn_readfirstlane(e[0].g), __builtin_amdgcn_readfirstlane(e[0].r.local),
+                        sg, s_lo, start, end, 1.0, ks, inv_tile, st, lt, TILE, &fr)) {
+          // the opacities and the corner check in flight together
+          p1 = min(fr.p_hi, c_hi - 1);
+          const int ib = x0 + (quad & 1) * Cfg::SUB - fr.ix0 - FR_R, jb = y0 + (quad >> 1) * Cfg::SUB - fr.iy0 - FR_R;
+          fill_gather<BNB, BNIT>(gs, gcap, fr, ib, jb, s_lo, p1, __builtin_nanf(""), og);
+          take = fill_corners_ok(idx, fr);
+        }
+        if (take) {
+          // the next step's loads in flight during the walk
           s_lo = p1 + 1;
           s_hi = min(c_hi, s_lo + depth);
 #pragma unroll
@@ -1088,6 +1136,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
             const int k = u * 64 + lane;
             load_entry(idx, gs, w.gcol, s_lo + k, k < s_hi - s_lo, &e[u]);
           }
+          fill_run_bwd(fr, og);
           continue;
         }
       }
@@ -1388,7 +1437,7 @@ hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last,
   Phase ph(L, NSPLAT_T_BLEND_FWD);
   hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
-                     T_final, n_last, L.bf->plan, persistent);
+                     T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent);
   return hipGetLastError();
 }
 
@@ -1407,7 +1456,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   Phase ph(L, NSPLAT_T_BLEND_BWD);
   hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
-                     dL, T_final, n_last, L.bf->plan, persistent);
+                     dL, T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent);
   return hipGetLastError();
 }
 
