@@ -467,6 +467,15 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
           const int roff = cell0 + (q / Cfg::BLK + dy) * NB + q % Cfg::BLK;
           const int rpos = pb0 + (q / Cfg::BLK + dy) * fr.w + q % Cfg::BLK;
+          {
+            // a row with no Gaussian still to composite for any live pixel
+            // changes nothing (chunk boundaries it crosses are stored with
+            // the unchanged state at the end)
+            const int jr = y0 + ly0 + q / Cfg::BLK + dy - fr.iy0, ir = x0 + lx0 + q % Cfg::BLK - fr.ix0;
+            const bool any = T[q] >= eps && jr >= fr.j0 && jr <= fr.j1 && ir + dxm >= fr.i0 && ir - dxm <= fr.i1 &&
+                             rpos - dxm <= top;
+            if (__ballot(any) == 0ull) continue;
+          }
           // the row's opacities first, one LDS wait per row
           float orow[2 * FR_R + 1];
 #pragma unroll
@@ -1003,7 +1012,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     // atomic.
     constexpr int BNB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
     constexpr int BNIT = (BNB * BNB + 63) / 64;
-    auto fill_run_bwd = [&](const FillRun& fr, const float (&og)[BNIT]) {
+    auto fill_run_bwd = [&](const FillRun& fr, int p0, int p1, const float (&og)[BNIT]) {
       // (one pixel per lane: lane (l & 7, l >> 3) of the quadrant's 8 x 8
       // block; fill_lattice is false otherwise)
       constexpr int NB = BNB;                  // 16 cells per axis
@@ -1054,6 +1063,14 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         const int dxm = dy * dy <= 4 ? 4 : (dy * dy == 9 ? 3 : 2);  // dx^2 + dy^2 <= FR_R2
         const int roff = (ly + dy + FR_R) * NS + lx + FR_R;         // this pixel's cell in row dy
         const int rpos = pb0 + dy * fr.w;
+        {
+          // a row with no Gaussian of p0 .. p1 at or in front of any pixel's
+          // stop adds nothing
+          const int jr = y0 + qy + ly + dy - fr.iy0, ir = x0 + qx + lx - fr.ix0;
+          const bool any = jr >= fr.j0 && jr <= fr.j1 && ir + dxm >= fr.i0 && ir - dxm <= fr.i1 &&
+                           rpos + dxm >= max(p0, stop[0]) && rpos - dxm <= p1;
+          if (__ballot(any) == 0ull) continue;
+        }
         // the row's opacities first, one LDS wait per row; each becomes
         // the cell's dL/do_j in place
         float v[2 * FR_R + 1];
@@ -1117,6 +1134,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         const float rr = ks * sg;
         float og[BNIT];
         bool take = false;
+        const int p0 = s_lo;
         int p1 = 0;
         if (rr * rr >= (float)FR_R2 && rr * rr < (float)(FR_R2 + 5) &&
             fill_run_at(plan, c, __builtin_amdgcn_readfirstlane(e[0].g), __builtin_amdgcn_readfirstlane(e[0].r.local),
@@ -1136,7 +1154,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
             const int k = u * 64 + lane;
             load_entry(idx, gs, w.gcol, s_lo + k, k < s_hi - s_lo, &e[u]);
           }
-          fill_run_bwd(fr, og);
+          fill_run_bwd(fr, p0, p1, og);
           continue;
         }
       }
