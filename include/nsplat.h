@@ -70,7 +70,7 @@ extern "C" {
 /* Version of the structure layouts below; nsplat_abi_version() returns the
  * value the library was built with, so a binding can refuse a library whose
  * structures it would misread. */
-#define NSPLAT_ABI_VERSION 5
+#define NSPLAT_ABI_VERSION 6
 
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
@@ -181,6 +181,13 @@ typedef struct {
   int32_t kappa;    /* extra copies of each open-curve endpoint Gaussian (4) */
   int32_t tile;     /* tile side in px: 8, 16 or 32                          */
   int32_t batch;    /* Gaussians staged in LDS per block step: 32..256       */
+  int32_t chunk;    /* list positions per chunk of the adjoint's split of each
+                       tile list (the forward stores every pixel's state at
+                       chunk boundaries; the adjoint runs one work item per
+                       tile quadrant and chunk): a power of two in
+                       [512, 8192], or 0 for 4096 when the launch has at
+                       least 16 tile quadrants per compute unit and 512
+                       otherwise.  It only changes FP32 rounding.            */
   const float* h_dev; /* (dev, optional) if non-NULL the grid step is read
                          from here, so a captured graph can anneal it        */
 } nsplat_params;

@@ -12,7 +12,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nsplat.h")
 OK, EINVAL, ECAPACITY, EHIP = 0, 1, 2, 3
 CLOSED, FILLED, ANISO = 1, 2, 4
 MAX_DEGREE = 5
-ABI_VERSION = 5  # NSPLAT_ABI_VERSION of include/nsplat.h
+ABI_VERSION = 6  # NSPLAT_ABI_VERSION of include/nsplat.h
 CNT_GAUSS, CNT_PAIRS, CNT_STATUS, CNT_GAUSS_REQ, CNT_PAIRS_REQ, CNT_BOUND_REQ, CNT_BOUND = range(7)
 NUM_COUNTERS = 16
 STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA, STATUS_VALUE = 1, 2, 4, 8, 16
@@ -38,7 +38,8 @@ class Scenes(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in ("delta_c", "delta_b", "rho", "eta", "gamma", "nl_factor", "fill_pad",
                                                "h", "k_sigma", "alpha_max", "eps_T", "delta_a")] + [
-        ("kappa", ctypes.c_int32), ("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("h_dev", vp)]
+        ("kappa", ctypes.c_int32), ("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("chunk", ctypes.c_int32),
+        ("h_dev", vp)]
 
 
 class Caps(ctypes.Structure):

@@ -18,9 +18,14 @@ struct nsplat_ctx {
   int n_cu = 256;
   std::string err;
   nsp::Timer timer;
-  // tile side of the last nsplat_bin on each workspace (the tile lists,
-  // checkpoint offsets and adjoint items in it are laid out for that side)
-  std::vector<std::pair<const void*, int>> bin_tile;
+  // tile side and chunk length of the last nsplat_bin on each workspace (the
+  // tile lists, checkpoint offsets and adjoint items in it are laid out for
+  // them)
+  struct BinState {
+    const void* ws;
+    int tile, ck_lg;
+  };
+  std::vector<BinState> bin_tile;
 };
 
 namespace nsp {
@@ -61,7 +66,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(double) * (size_t)(S + 1),                    // sacc
       sizeof(int32_t) * (size_t)(tiles8 + 1),              // ck_off
       sizeof(int32_t) * (size_t)(tiles8 + 1),              // item_off
-      sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK + 1),  // ckbuf
+      sizeof(float) * 4 * 32 * 32 * (size_t)(pcap / CK_MIN + 1),  // ckbuf
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
       sizeof(double) * SEG_WORDS * (size_t)(bcap + (SDF_CHUNK - 1) * N + 1),  // segs
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gaux
@@ -216,7 +221,23 @@ int check_params(nsplat_ctx* ctx, const nsplat_params* pr) {
     return fail(ctx, NSPLAT_EINVAL, "eps_T must be in [0, 1] (got %g)", (double)pr->eps_T);
   if (pr->kappa < 0) return fail(ctx, NSPLAT_EINVAL, "kappa must be >= 0");
   if (!(pr->fill_pad >= 0.f)) return fail(ctx, NSPLAT_EINVAL, "fill_pad must be >= 0");
+  if (pr->chunk != 0 && (pr->chunk < CK_MIN || pr->chunk > CK_MAX || (pr->chunk & (pr->chunk - 1)) != 0))
+    return fail(ctx, NSPLAT_EINVAL, "chunk must be 0 or a power of two in [%d, %d] (got %d)", CK_MIN, CK_MAX,
+                pr->chunk);
   return NSPLAT_OK;
+}
+
+// log2 of the chunk length of a launch: params.chunk, or when it is 0, 4096
+// for a launch whose tile quadrants (the forward's work items) number at
+// least 16 per compute unit, so that the unsplit lists already fill the GPU
+// and fewer chunks save the per-chunk state and per-item set-up, and 512
+// otherwise, so that the adjoint splits long lists across wavefronts.
+int chunk_log2(const nsplat_params* pr, int64_t n_tiles, int n_cu) {
+  int ck = pr->chunk;
+  if (ck == 0) ck = n_tiles * (pr->tile == 8 ? 1 : 4) >= 16LL * n_cu ? 4096 : CK_MIN;
+  int lg = 0;
+  while ((1 << lg) < ck) ++lg;
+  return lg;
 }
 
 int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, const nsplat_buffers* bf) {
@@ -234,22 +255,28 @@ int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   return NSPLAT_OK;
 }
 
-void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile) {
+void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int ck_lg) {
   for (auto& e : ctx->bin_tile)
-    if (e.first == ws) {
-      e.second = tile;
+    if (e.ws == ws) {
+      e.tile = tile;
+      e.ck_lg = ck_lg;
       return;
     }
-  ctx->bin_tile.emplace_back(ws, tile);
+  ctx->bin_tile.push_back({ws, tile, ck_lg});
 }
 
 // NSPLAT_EINVAL when the workspace's tile lists were built (by this context)
-// for another tile side than params.tile.
-int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile) {
-  for (const auto& e : ctx->bin_tile)
-    if (e.first == ws && e.second != tile)
+// for another tile side or chunk length than this launch's.
+int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int ck_lg) {
+  for (const auto& e : ctx->bin_tile) {
+    if (e.ws != ws) continue;
+    if (e.tile != tile)
       return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with tile %d, "
-                  "but params.tile is %d", e.second, tile);
+                  "but params.tile is %d", e.tile, tile);
+    if (e.ck_lg != ck_lg)
+      return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with chunk %d, "
+                  "but this launch's chunk is %d", 1 << e.ck_lg, 1 << ck_lg);
+  }
   return NSPLAT_OK;
 }
 
@@ -269,6 +296,7 @@ int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, c
   L->stream = (hipStream_t)stream;
   L->n_tiles = nsplat_num_tiles(sc, pr->tile);
   L->n_cu = ctx->n_cu;
+  L->ck_lg = chunk_log2(pr, L->n_tiles, ctx->n_cu);
   L->tm = ctx->timer.on ? &ctx->timer : nullptr;
   return NSPLAT_OK;
 }
@@ -350,7 +378,7 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   hipError_t h = launch_scene_setup(L, nullptr);
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
-  record_bin_tile(ctx, bf->ws, pr->tile);
+  record_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg);
   return NSPLAT_OK;
 }
 
@@ -361,7 +389,7 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!image || !T_final || !n_last) return fail(ctx, NSPLAT_EINVAL, "image / T_final / n_last is NULL");
-  if ((e = check_bin_tile(ctx, bf->ws, pr->tile))) return e;
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg))) return e;
   hipError_t h = launch_blend_fwd(L, image, T_final, n_last, persistent);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_forward");
   return NSPLAT_OK;
@@ -374,7 +402,7 @@ int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_s
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!dL || !T_final || !n_last || !gr) return fail(ctx, NSPLAT_EINVAL, "dL_dimage / T_final / n_last / grads is NULL");
-  if ((e = check_bin_tile(ctx, bf->ws, pr->tile))) return e;
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg))) return e;
   const bool use_reg = reg && (reg->bbox_weight != 0.0f || reg->deriv_weight != 0.0f);
   if (use_reg) {
     if (reg->deriv_weight != 0.0f && (reg->deriv_order < 1 || reg->deriv_order > 3))

@@ -5,8 +5,8 @@
 // TileCfg below.  Centres become exact tile-local FP32 coordinates when an
 // entry is loaded (FP64 centre minus the tile origin, rounded once).  The
 // forward stops a pixel once T < eps_T and a wavefront once all its pixels
-// have stopped, and stores each pixel's state at every chunk boundary (CK
-// list positions) it passes.  The adjoint runs one wavefront per (tile,
+// have stopped, and stores each pixel's state at every chunk boundary (a
+// chunk is 2^ck_lg list positions, chosen per launch) it passes.  The adjoint runs one wavefront per (tile,
 // quadrant, chunk), front to back from that stored state, parks each
 // Gaussian's per-lane gradient values in LDS and sums sixteen of them at a
 // time, with one atomic per value and wavefront.
@@ -304,7 +304,7 @@ __host__ __device__ constexpr int park_rows(int tile, int E, int kind) { return 
 // wavefronts per SIMD the adjoint is built for: six without the fill-run
 // walk at one pixel per lane and depth 64, five with it
 __host__ __device__ constexpr int bwd_waves(int tile, int E, int kind) {
-  return bwd_six_waves(tile, E, kind) ? 6 : (E == 1 ? (tile <= 16 ? 5 : 4) : 1);
+  return bwd_six_waves(tile, E, kind) ? 6 : (E == 1 ? 4 : 1);
 }
 __host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E, int kind) {
   return ((size_t)64 * E * BWD_ENTRY_BYTES + (size_t)park_rows(tile, E, kind) * (RB_ROW * 4 + 8) + 15) / 16 * 16;
@@ -313,9 +313,9 @@ __host__ __device__ constexpr size_t bwd_wave_bytes(int tile, int E, int kind) {
 // Lower end of the step that starts at list position h (walking down from
 // the list end): at most `depth` entries, not below `start`, and not across
 // the boundary of h's chunk.
-__device__ inline int step_floor(int h, int start, int depth, int end) {
-  const int k = (end - h) / CK;
-  return max(max(start, h - depth), end - (k + 1) * CK);
+__device__ inline int step_floor(int h, int start, int depth, int end, int ck_lg) {
+  const int k = (end - h) >> ck_lg;
+  return max(max(start, h - depth), end - ((k + 1) << ck_lg));
 }
 
 template <int C, int TILE, int E, int KIND>
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, const int32_t* __restrict__ plan,
-    int64_t gcap, int persistent) {
+    int64_t gcap, int persistent, int ck_lg) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   extern __shared__ __align__(16) char smem[];
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     // the records, so a step waits for one round trip, issued a step earlier
     Entry e[E];
     int gnext[E];  // Gaussian indices of the next step
-    int hi = end, lo_s = step_floor(hi, start, depth, end);
-    int nhi = lo_s, nlo = step_floor(nhi, start, depth, end);
+    int hi = end, lo_s = step_floor(hi, start, depth, end, ck_lg);
+    int nhi = lo_s, nlo = step_floor(nhi, start, depth, end, ck_lg);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
       const int k = u * 64 + lane;
@@ -430,8 +430,14 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const double sgd = (double)fr.sigma;
       const float coef = (float)(-0.5 * LOG2E / (sgd * sgd));  // as entry_geometry
+      // lane k holds G at squared lattice distance k, as the entry path forms it
+      const int gtab = __float_as_int(__builtin_amdgcn_exp2f(coef * (float)lane));
+      bool neg = false;
+#pragma unroll
+      for (int it = 0; it < FNIT; ++it) neg = neg || !(og[it] >= 0.0f);
+      const bool nonneg = __ballot(neg) == 0ull;  // no negative (or NaN) opacity in the run
       int nb[PPT];
-      const int nb0 = end - (n_ck + 1) * CK;  // the next chunk boundary still to store
+      const int nb0 = end - ((n_ck + 1) << ck_lg);  // the next chunk boundary still to store
 #pragma unroll
       for (int q = 0; q < PPT; ++q) nb[q] = nb0;
       // pixel q's LDS cell and the list position of its own lattice point:
@@ -449,7 +455,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           acc[q][2] = __builtin_fmaf(rc2, a, acc[q][2]);
         }
         Tst[q] = T[q];
-        float* ckp = w.ckbuf + (int64_t)(ck0 + (end - nb[q]) / CK - 1) * (4 * TILE * TILE);
+        float* ckp = w.ckbuf + (int64_t)(ck0 + ((end - nb[q]) >> ck_lg) - 1) * (4 * TILE * TILE);
         const int slot = (quad * PPT + q) * 64 + lane;
         ckp[slot] = T[q];
 #pragma unroll
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           ckp[(1 + ch) * TILE * TILE + slot] = acc[q][ch];
           acc[q][ch] = 0.0f;
         }
-        nb[q] -= CK;
+        nb[q] -= 1 << ck_lg;
       };
       // pixels are independent here: one pixel's whole walk at a time
 #pragma unroll
@@ -476,12 +482,15 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
                              rpos - dxm <= top;
             if (__ballot(any) == 0ull) continue;
           }
-          // the row's opacities first, one LDS wait per row
-          float orow[2 * FR_R + 1];
+          // the row's opacities first, one LDS wait per row, and its five
+          // Gaussian factors (|dx| = 0 .. 4) from the table
+          float orow[2 * FR_R + 1], Gr[FR_R + 1];
 #pragma unroll
           for (int dx = -FR_R; dx <= FR_R; ++dx) orow[dx + FR_R] = ol[roff + dx];
+#pragma unroll
+          for (int a = 0; a <= FR_R; ++a) Gr[a] = __int_as_float(__builtin_amdgcn_readlane(gtab, a * a + dy * dy));
           auto cell = [&](int dx, bool check) {
-            const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
+            const float G = Gr[dx < 0 ? -dx : dx];
             const float o = orow[dx + FR_R];
             const int pos = rpos + dx;
             if (check && o != 0.0f)
@@ -493,9 +502,23 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           };
           // a chunk boundary falls in the row of some lane only now and then
           if (__ballot(rpos - dxm < nb[q]) == 0ull) {
+            // With no negative opacity in the run T does not grow along the
+            // row, so a pixel live at its start whose T ends it at or above
+            // eps_T was live at every cell: the row's product, with no stop
+            // test, is then the cell-by-cell result.  Only where some pixel
+            // stops inside the row is the row taken cell by cell.
+            float Tr = T[q];
 #pragma unroll
             for (int dx = FR_R; dx >= -FR_R; --dx)
-              if (dx <= dxm && dx >= -dxm) cell(dx, false);
+              if (dx <= dxm && dx >= -dxm) Tr = Tr * (1.0f - fminf(amax, orow[dx + FR_R] * Gr[dx < 0 ? -dx : dx]));
+            const bool live = T[q] >= eps;
+            if (nonneg && __ballot(live && !(Tr >= eps)) == 0ull) {
+              T[q] = live ? Tr : T[q];
+            } else {
+#pragma unroll
+              for (int dx = FR_R; dx >= -FR_R; --dx)
+                if (dx <= dxm && dx >= -dxm) cell(dx, false);
+            }
           } else {
 #pragma unroll
             for (int dx = FR_R; dx >= -FR_R; --dx)
@@ -508,7 +531,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
 #pragma unroll
       for (int q = 0; q < PPT; ++q)
         while (nb[q] >= bl) store_boundary(q);
-      n_ck = (end - bl) / CK;
+      n_ck = (end - bl) >> ck_lg;
     };
     while (hi > start) {
       if (fill_lattice && __builtin_amdgcn_readfirstlane(e[0].kind) == 1) {
@@ -533,9 +556,9 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
           hi = fr.p_lo;
           // the next step's loads (as at the start of the list), in flight
           // during the walk
-          lo_s = step_floor(hi, start, depth, end);
+          lo_s = step_floor(hi, start, depth, end, ck_lg);
           nhi = lo_s;
-          nlo = step_floor(nhi, start, depth, end);
+          nlo = step_floor(nhi, start, depth, end, ck_lg);
 #pragma unroll
           for (int u = 0; u < E; ++u) {
             const int k = u * 64 + lane;
@@ -577,7 +600,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
       // next step's records (their indices arrived during this step's
       // predecessor) and the indices of the step after, in flight while
       // this step is composited
-      const int n2hi = nlo, n2lo = step_floor(n2hi, start, depth, end);
+      const int n2hi = nlo, n2lo = step_floor(n2hi, start, depth, end, ck_lg);
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
@@ -683,11 +706,11 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
       lo_s = nlo;
       nhi = n2hi;
       nlo = n2lo;
-      if (hi > start && (end - hi) % CK == 0) {
+      if (hi > start && ((end - hi) & ((1 << ck_lg) - 1)) == 0) {
         // at the front of chunk k = (end - hi) / CK: T, and the colour the
         // chunk just finished contributed (the current run closed at the
         // boundary; the sum restarts for the next chunk)
-        float* ckp = w.ckbuf + (int64_t)(ck0 + (end - hi) / CK - 1) * (4 * TILE * TILE);
+        float* ckp = w.ckbuf + (int64_t)(ck0 + ((end - hi) >> ck_lg) - 1) * (4 * TILE * TILE);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
           const float a = Tst[q] - T[q];
@@ -888,7 +911,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
-    const int32_t* __restrict__ plan, int64_t gcap, int persistent) {
+    const int32_t* __restrict__ plan, int64_t gcap, int persistent, int ck_lg) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
@@ -936,7 +959,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     const int lt = tile - st.tile_off;
     const int x0 = (lt % st.tiles_x) * TILE, y0 = (lt / st.tiles_x) * TILE;
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    const int c_hi = end - kc * CK, c_lo = max(start, end - (kc + 1) * CK);  // the chunk's positions
+    const int c_hi = end - (kc << ck_lg), c_lo = max(start, end - ((kc + 1) << ck_lg));  // the chunk's positions
     const int64_t plane = (int64_t)st.H * st.W;
     // the forward's state at the chunk's back end (the front of chunk kc + 1),
     // stored when a chunk follows
@@ -1017,7 +1040,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       // block; fill_lattice is false otherwise)
       constexpr int NB = BNB;                  // 16 cells per axis
       constexpr int NS = FR_NS;                // LDS row stride (conflict-free rows)
-      float* ol = (float*)mine_lds;  // [NB][NS] opacities (NaN: no Gaussian at p0 .. p1 there)
+      float* ol = (float*)mine_lds;  // [NB][NS] opacities (0: no Gaussian at p0 .. p1 there)
       float* gl = park;              // [NB][NS] dL/do_j
       if (n_rows > 0) {
         flush_rows<RB>(park, ptgt, n_rows, ggrad);
@@ -1042,12 +1065,17 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // an absent cell composites as a zero opacity (alpha 0, T unchanged);
+      // its dL/do_j sum is dropped by the presence bits
+      int pm = 0;
 #pragma unroll
       for (int it = 0; it < BNIT; ++it) {
         const int sl = it * 64 + lane;
         if (sl < NB * NB) {
-          ol[(sl / NB) * NS + sl % NB] = og[it];
+          const bool pres = og[it] == og[it];
+          ol[(sl / NB) * NS + sl % NB] = pres ? og[it] : 0.0f;
           gl[(sl / NB) * NS + sl % NB] = 0.0f;
+          pm |= (int)pres << it;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1055,6 +1083,9 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const double sgd = (double)fr.sigma;
       const float coef = (float)(-0.5 * LOG2E / (sgd * sgd));  // as entry_geometry
+      // lane k holds G at squared lattice distance k, as the entry path forms it
+      const int gtab = __float_as_int(__builtin_amdgcn_exp2f(coef * (float)lane));
+      const float nW = -Wc[0];  // dL/dalpha (1 - alpha) over the run
       const int lx = lane & 7, ly = lane >> 3;
       const bool col0 = lx == 0, col7 = lx == 7;
       const int pb0 = fr.p_lo + (y0 + qy + ly - fr.iy0 - fr.j0) * fr.w + (x0 + qx + lx - fr.ix0 - fr.i0);
@@ -1071,25 +1102,29 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
                            rpos + dxm >= max(p0, stop[0]) && rpos - dxm <= p1;
           if (__ballot(any) == 0ull) continue;
         }
-        // the row's opacities first, one LDS wait per row; each becomes
-        // the cell's dL/do_j in place
-        float v[2 * FR_R + 1];
+        // the row's opacities first, one LDS wait per row (each becomes the
+        // cell's dL/do_j in place), and its five Gaussian factors
+        float v[2 * FR_R + 1], Gr[FR_R + 1];
 #pragma unroll
         for (int dx = -FR_R; dx <= FR_R; ++dx) v[dx + FR_R] = ol[roff + dx];
+#pragma unroll
+        for (int a = 0; a <= FR_R; ++a) Gr[a] = __int_as_float(__builtin_amdgcn_readlane(gtab, a * a + dy * dy));
+        const int sd = stop[0] - rpos;  // cells at dx >= sd lie at or behind the pixel's stop
 #pragma unroll
         for (int dx = -FR_R; dx <= FR_R; ++dx) {
           const float o = v[dx + FR_R];
           v[dx + FR_R] = 0.0f;
           if (dx > dxm || dx < -dxm) continue;
-          const float G = __builtin_amdgcn_exp2f(coef * (float)(dx * dx + dy * dy));
-          const bool in = (o == o) && (rpos + dx >= stop[0]);
+          // a cell in front of the stop takes part with G = 0: alpha 0, T
+          // and alpha T unchanged, no gradient
+          const float G = dx >= sd ? Gr[dx < 0 ? -dx : dx] : 0.0f;
           const float oG = o * G;
-          const float alpha = in ? fminf(oG, amax) : 0.0f;
+          const bool lt = oG < amax;
+          const float alpha = lt ? oG : amax;
           const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
-          const float dLda = (in && oG < amax) ? -Wc[0] * r : 0.0f;
-          T[0] = in ? T[0] * r : T[0];
+          T[0] *= r;
           aT[0] = __builtin_fmaf(alpha, T[0], aT[0]);
-          v[dx + FR_R] = dLda * G;  // dL/do_j of the cell at dx (0 unless in)
+          v[dx + FR_R] = lt ? nW * r * G : 0.0f;  // dL/do_j of the cell at dx
         }
         // the row's cells get their sums over the pixels of each lane row
         // by two sliding sums along the row (DPP shifts by one lane, 8-lane
@@ -1114,8 +1149,8 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       for (int it = 0; it < (NB * NB + 63) / 64; ++it) {
         const int sl = it * 64 + lane;
         if (sl >= NB * NB) continue;
-        const float o = ol[(sl / NB) * NS + sl % NB], val = gl[(sl / NB) * NS + sl % NB];
-        if (o == o && val != 0.0f) {
+        const float val = gl[(sl / NB) * NS + sl % NB];
+        if (((pm >> it) & 1) && val != 0.0f) {
           const int j = jb + sl / NB, i = ib + sl % NB;
           unsafeAtomicAdd(ggrad + ((int64_t)fr.goff + (int64_t)j * fr.nx + i) * GG + 3, val);
         }
@@ -1455,7 +1490,7 @@ hipError_t fwd_t(const Launch& L, float* image, float* T_final, int32_t* n_last,
   Phase ph(L, NSPLAT_T_BLEND_FWD);
   hipLaunchKernelGGL((k_blend_fwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, n_items, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg, image,
-                     T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent);
+                     T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent, L.ck_lg);
   return hipGetLastError();
 }
 
@@ -1464,7 +1499,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   if (L.n_tiles <= 0) return hipSuccess;
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
-  const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * (L.bf->caps.pairs / CK + L.n_tiles);
+  const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * ((L.bf->caps.pairs >> L.ck_lg) + L.n_tiles);
   const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E, KIND);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {
@@ -1474,7 +1509,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   Phase ph(L, NSPLAT_T_BLEND_BWD);
   hipLaunchKernelGGL((k_blend_bwd<C, TILE, E, KIND>), dim3(grid), dim3(BLOCK), lds, L.stream, *L.cv, *L.pr, L.w,
                      L.sc->n_scenes, (int)L.n_tiles, (const Gauss*)L.bf->gauss, L.bf->ranges, L.bf->idx, L.sc->bg,
-                     dL, T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent);
+                     dL, T_final, n_last, L.bf->plan, (int64_t)L.bf->caps.gauss, persistent, L.ck_lg);
   return hipGetLastError();
 }
 

@@ -64,21 +64,22 @@ struct Work {
   double* sacc;        // [n_scenes + 1] per-scene sums (distance-weighted loss)
   int32_t* ck_off;     // [tiles at the smallest tile size + 1] first checkpoint of each tile (scan)
   int32_t* item_off;   // [tiles at the smallest tile size + 1] first adjoint item of each tile in blend order (scan)
-  float* ckbuf;        // [caps.pairs / CK + 1][4][32 * 32] forward state at chunk boundaries: T, and
+  float* ckbuf;        // [caps.pairs / CK_MIN + 1][4][32 * 32] forward state at chunk boundaries: T, and
                        // the colour of everything behind the boundary (per channel)
   float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and its kind (Kind below)
   float4* gaux;        // [caps.gauss] tangent-aligned Gaussians: tangent (x, y), axis across the curve
   double* segs;        // [caps.boundary + (SDF_CHUNK - 1) * n_curves][SEG_WORDS] fill SDF segment records
 };
 
-// The compositing lists are cut into chunks of CK list positions, counted
-// from each tile's front (list end): chunk k holds the positions
+// The compositing lists are cut into chunks of CK = 2^ck_lg list positions,
+// counted from each tile's front (list end): chunk k holds the positions
 // [end - (k + 1) CK, end - k CK).  The forward stores every pixel's state at
 // the chunk boundaries it passes, and the adjoint runs one work item per
 // (tile, quadrant, chunk), so that a long list no longer sets the length of
-// the adjoint pass.
-constexpr int CK = 512;
-__host__ __device__ inline int n_chunks(int len) { return (len + CK - 1) / CK; }
+// the adjoint pass.  CK is chosen per launch (chunk_log2), at least CK_MIN,
+// for which the checkpoint store is sized.
+constexpr int CK_MIN = 512, CK_MAX = 8192;
+__host__ __device__ inline int n_chunks(int len, int ck_lg) { return (len + (1 << ck_lg) - 1) >> ck_lg; }
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
 // boundary point boff) has a header at cbox_base(boff, c) holding the box
@@ -372,6 +373,7 @@ struct Launch {
   hipStream_t stream;
   int64_t n_tiles;
   int n_cu;
+  int ck_lg;  // log2 of the chunk length (chunk_log2)
 };
 
 // Scene table; also clears the NSPLAT_NUM_COUNTERS counters when given.

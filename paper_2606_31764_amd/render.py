@@ -45,6 +45,7 @@ class Params:
     kappa: int = 4
     tile: int = 16
     batch: int = 64
+    chunk: int = 0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -52,7 +53,7 @@ class Params:
     def cstruct(self, h_dev: Optional[torch.Tensor] = None) -> L.Params:
         return L.Params(self.delta_c, self.delta_b, self.rho, self.eta, self.gamma, self.nl_factor, self.fill_pad,
                         self.h, self.k_sigma, self.alpha_max, self.eps_T, self.delta_a, int(self.kappa),
-                        int(self.tile), int(self.batch), _ptr(h_dev))
+                        int(self.tile), int(self.batch), int(self.chunk), _ptr(h_dev))
 
 
 class Context:

@@ -467,6 +467,44 @@ def test_forward_and_backward_refuse_another_tile_than_bin():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("chunk", [512, 1024, 4096, 8192])
+def test_chunk_lengths_against_oracle(chunk):
+    """Every chunk length the adjoint's split of the tile lists allows gives
+    the oracle's image and gradients, on lists of a few chunks at 512."""
+    b = synth.config3(seed=3960, n_paths=12, size=96)
+    p = Params().replace(h=1.0, tile=16, chunk=chunk)
+    out = _full_parity(b, p)
+    lens = out["ranges"][:, 1] - out["ranges"][:, 0]
+    print("chunk", chunk, "longest list", int(lens.max()), flush=True)
+    assert lens.max() > 2 * 512
+
+
+def test_chunk_length_is_checked():
+    """params.chunk must be 0 or a power of two in [512, 8192], and the
+    forward and backward refuse a chunk length other than the one nsplat_bin
+    laid the lists out for."""
+    import torch
+    from paper_2606_31764_amd import _lib as L
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config2(seed=2802, n_curves=4, size=64)
+    p = Params(delta_c=3.0, chunk=1024)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    r.run_forward(t)
+    for bad in (256, 1000, 16384, -512):
+        with pytest.raises(L.NSplatError, match="chunk must be"):
+            r.bin(t, params=p.replace(chunk=bad))
+    with pytest.raises(L.NSplatError, match="chunk 1024"):
+        r.forward(t, params=p.replace(chunk=2048))
+    dL = torch.ones_like(r.image)
+    with pytest.raises(L.NSplatError, match="chunk 1024"):
+        r.backward(t, dL, params=p.replace(chunk=512))
+    r.bin(t, params=p.replace(chunk=2048))
+    r.forward(t, params=p.replace(chunk=2048))  # consistent again
+    r.backward(t, dL, params=p.replace(chunk=2048))
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("p_deg", [1, 4, 5])
 def test_fill_of_other_degrees(p_deg):
     """Filled closed curves of degree 1 (a polygon), 4 and 5, against the oracle."""
