@@ -185,9 +185,11 @@ typedef struct {
                        tile list (the forward stores every pixel's state at
                        chunk boundaries; the adjoint runs one work item per
                        tile quadrant and chunk): a power of two in
-                       [512, 8192], or 0 for 4096 when the launch has at
-                       least 16 tile quadrants per compute unit and 512
-                       otherwise.  It only changes FP32 rounding.            */
+                       [512, 8192], or 0: 512 for a batch without fills,
+                       else chosen by nsplat_bin on the device from the pair
+                       count (about pairs x quadrants per tile / (8 x compute
+                       units), rounded to a power of two in [512, 4096]).
+                       It only changes FP32 rounding.                        */
   const float* h_dev; /* (dev, optional) if non-NULL the grid step is read
                          from here, so a captured graph can anneal it        */
 } nsplat_params;

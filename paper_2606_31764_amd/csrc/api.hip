@@ -23,7 +23,7 @@ struct nsplat_ctx {
   // them)
   struct BinState {
     const void* ws;
-    int tile, ck_lg;
+    int tile, chunk;
   };
   std::vector<BinState> bin_tile;
 };
@@ -227,16 +227,15 @@ int check_params(nsplat_ctx* ctx, const nsplat_params* pr) {
   return NSPLAT_OK;
 }
 
-// log2 of the chunk length of a launch: params.chunk, or when it is 0, 4096
-// for a launch whose tile quadrants (the forward's work items) number at
-// least 16 per compute unit, so that the unsplit lists already fill the GPU
-// and fewer chunks save the per-chunk state and per-item set-up, and 512
-// otherwise, so that the adjoint splits long lists across wavefronts.
-int chunk_log2(const nsplat_params* pr, int64_t n_tiles, int n_cu) {
-  int ck = pr->chunk;
-  if (ck == 0) ck = n_tiles * (pr->tile == 8 ? 1 : 4) >= 16LL * n_cu ? 4096 : CK_MIN;
+// log2 of params.chunk; when it is 0, 512 for batches without fills and -1
+// (the binning chooses on the device, auto_chunk_log2) for batches with them:
+// the fill-run walks cost mostly per run and per item set-up, which longer
+// chunks save, while entry-by-entry stroke compositing gains more from
+// splitting long lists across wavefronts.
+int chunk_log2(const nsplat_curves* cv, const nsplat_params* pr) {
+  if (pr->chunk == 0) return (cv->any_flags & NSPLAT_FILLED) ? -1 : 9;
   int lg = 0;
-  while ((1 << lg) < ck) ++lg;
+  while ((1 << lg) < pr->chunk) ++lg;
   return lg;
 }
 
@@ -255,27 +254,27 @@ int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   return NSPLAT_OK;
 }
 
-void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int ck_lg) {
+void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
   for (auto& e : ctx->bin_tile)
     if (e.ws == ws) {
       e.tile = tile;
-      e.ck_lg = ck_lg;
+      e.chunk = chunk;
       return;
     }
-  ctx->bin_tile.push_back({ws, tile, ck_lg});
+  ctx->bin_tile.push_back({ws, tile, chunk});
 }
 
 // NSPLAT_EINVAL when the workspace's tile lists were built (by this context)
-// for another tile side or chunk length than this launch's.
-int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int ck_lg) {
+// for another tile side or params.chunk than this launch's.
+int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
   for (const auto& e : ctx->bin_tile) {
     if (e.ws != ws) continue;
     if (e.tile != tile)
       return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with tile %d, "
                   "but params.tile is %d", e.tile, tile);
-    if (e.ck_lg != ck_lg)
+    if (e.chunk != chunk)
       return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with chunk %d, "
-                  "but this launch's chunk is %d", 1 << e.ck_lg, 1 << ck_lg);
+                  "but params.chunk is %d", e.chunk, chunk);
   }
   return NSPLAT_OK;
 }
@@ -296,7 +295,7 @@ int prepare(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc, c
   L->stream = (hipStream_t)stream;
   L->n_tiles = nsplat_num_tiles(sc, pr->tile);
   L->n_cu = ctx->n_cu;
-  L->ck_lg = chunk_log2(pr, L->n_tiles, ctx->n_cu);
+  L->ck_lg = chunk_log2(cv, pr);
   L->tm = ctx->timer.on ? &ctx->timer : nullptr;
   return NSPLAT_OK;
 }
@@ -378,7 +377,7 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   hipError_t h = launch_scene_setup(L, nullptr);
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
-  record_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg);
+  record_bin_tile(ctx, bf->ws, pr->tile, pr->chunk);
   return NSPLAT_OK;
 }
 
@@ -389,7 +388,7 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!image || !T_final || !n_last) return fail(ctx, NSPLAT_EINVAL, "image / T_final / n_last is NULL");
-  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg))) return e;
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, pr->chunk))) return e;
   hipError_t h = launch_blend_fwd(L, image, T_final, n_last, persistent);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_forward");
   return NSPLAT_OK;
@@ -402,7 +401,7 @@ int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_s
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!dL || !T_final || !n_last || !gr) return fail(ctx, NSPLAT_EINVAL, "dL_dimage / T_final / n_last / grads is NULL");
-  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, L.ck_lg))) return e;
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, pr->chunk))) return e;
   const bool use_reg = reg && (reg->bbox_weight != 0.0f || reg->deriv_weight != 0.0f);
   if (use_reg) {
     if (reg->deriv_weight != 0.0f && (reg->deriv_order < 1 || reg->deriv_order > 3))

@@ -313,7 +313,16 @@ __global__ __launch_bounds__(256) void k_order_scatter(const int32_t* __restrict
 }
 
 // Forward-state checkpoints of tile t: one per chunk boundary inside its list.
-__global__ void k_chunk_counts(const int32_t* __restrict__ ranges, int n_tiles, int ck_lg, uint32_t* __restrict__ ck) {
+// The launch's log2 chunk length: the caller's (ck_arg >= 0), or chosen from
+// the pair count.
+__device__ inline int launch_chunk_log2(int ck_arg, const int32_t* counters, int quads, int n_cu) {
+  return ck_arg >= 0 ? ck_arg : auto_chunk_log2(counters[NSPLAT_CNT_PAIRS], quads, n_cu);
+}
+
+__global__ void k_chunk_counts(const int32_t* __restrict__ ranges, int n_tiles, int ck_arg, const int32_t* counters,
+                               int quads, int n_cu, int32_t* __restrict__ queue, uint32_t* __restrict__ ck) {
+  const int ck_lg = launch_chunk_log2(ck_arg, counters, quads, n_cu);
+  if (blockIdx.x == 0 && threadIdx.x == 0) queue[Q_CKLG] = ck_lg;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
     const int n = n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg);
     ck[t] = n > 0 ? (uint32_t)(n - 1) : 0u;
@@ -322,7 +331,9 @@ __global__ void k_chunk_counts(const int32_t* __restrict__ ranges, int n_tiles, 
 
 // Adjoint work items of the tile at blend-order position i: quadrants x chunks.
 __global__ void k_item_counts(const int32_t* __restrict__ ranges, const int32_t* __restrict__ order, int n_tiles,
-                              int quads, int ck_lg, uint32_t* __restrict__ items) {
+                              int quads, int ck_arg, const int32_t* counters, int n_cu,
+                              uint32_t* __restrict__ items) {
+  const int ck_lg = launch_chunk_log2(ck_arg, counters, quads, n_cu);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += gridDim.x * blockDim.x) {
     const int t = order[i];
     items[i] = (uint32_t)(quads * n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg));
@@ -351,7 +362,8 @@ __device__ inline uint32_t plan_wave_scan(uint32_t v) {
 // digit, `nd` digits) it first writes every tile's range: tile t is digit t,
 // its slice starts at the digit's first offset and ends where digit t + 1
 // starts (or at the pair count); empty tiles get [0, 0).
-__global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict__ ranges, int n_tiles, int quads, int ck_lg,
+__global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict__ ranges, int n_tiles, int quads,
+                                                            int ck_arg, int n_cu, int32_t* __restrict__ queue,
                                                             int32_t* __restrict__ order, int32_t* __restrict__ ck_off,
                                                             int32_t* __restrict__ item_off,
                                                             const uint32_t* __restrict__ hist, int sb, int nd,
@@ -359,6 +371,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict_
   __shared__ int h[32], base[32];
   __shared__ uint32_t wsum[2][PLAN_THREADS / 64];
   const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  const int ck_lg = launch_chunk_log2(ck_arg, counters, quads, n_cu);
+  if (tid == 0) queue[Q_CKLG] = ck_lg;
   if (hist) {
     const uint32_t total = (uint32_t)counters[NSPLAT_CNT_PAIRS];
     for (int t = tid; t < n_tiles; t += PLAN_THREADS) {
@@ -506,7 +520,7 @@ hipError_t launch_bin(const Launch& L) {
                          L.bf->ranges);
     if (nt > 0 && nt <= SMALL_TILES) {
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, nt,
-                         L.pr->tile == 8 ? 1 : 4, L.ck_lg, L.w.order, L.w.ck_off, L.w.item_off,
+                         L.pr->tile == 8 ? 1 : 4, L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
                          from_hist ? (const uint32_t*)L.w.hist : nullptr, sb, 1 << key_bits, cnt);
     } else if (nt > 0) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
@@ -514,12 +528,12 @@ hipError_t launch_bin(const Launch& L) {
       hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, L.stream, L.w.obin);
       hipLaunchKernelGGL(k_order_scatter, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin, L.w.order);
       const int cb = grid_for(nt, 256, 4096);
-      hipLaunchKernelGGL(k_chunk_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, nt, L.ck_lg,
-                         (uint32_t*)L.w.ck_off);
+      hipLaunchKernelGGL(k_chunk_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, nt, L.ck_lg, cnt,
+                         L.pr->tile == 8 ? 1 : 4, L.n_cu, L.w.queue, (uint32_t*)L.w.ck_off);
       e = launch_scan((uint32_t*)L.w.ck_off, nullptr, nt, (uint32_t*)L.w.ck_off + nt, L.w.scan_tmp, L.stream);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_item_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, L.w.order, nt,
-                         L.pr->tile == 8 ? 1 : 4, L.ck_lg, (uint32_t*)L.w.item_off);
+                         L.pr->tile == 8 ? 1 : 4, L.ck_lg, cnt, L.n_cu, (uint32_t*)L.w.item_off);
       e = launch_scan((uint32_t*)L.w.item_off, nullptr, nt, (uint32_t*)L.w.item_off + nt, L.w.scan_tmp, L.stream);
       if (e != hipSuccess) return e;
     } else {

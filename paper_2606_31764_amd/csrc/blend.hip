@@ -323,10 +323,13 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_items, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     float* __restrict__ image, float* __restrict__ Tfin, int32_t* __restrict__ nlast, const int32_t* __restrict__ plan,
-    int64_t gcap, int persistent, int ck_lg) {
+    int64_t gcap, int persistent, int ck_arg) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   extern __shared__ __align__(16) char smem[];
+  typedef const __attribute__((address_space(4))) int32_t* const_i32;
+  // the chunk length: the caller's, or the one the binning chose
+  const int ck_lg = ck_arg >= 0 ? ck_arg : ((const_i32)w.queue)[Q_CKLG];
   const int depth = min(pr.batch, 64 * E);   // entries per step (E per lane; fewer lanes below 64)
   const float amax = pr.alpha_max, eps = pr.eps_T, ks = pr.k_sigma;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
@@ -911,11 +914,13 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     nsplat_curves cv, nsplat_params pr, Work w, int n_scenes, int n_tiles, const Gauss* __restrict__ gs,
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
-    const int32_t* __restrict__ plan, int64_t gcap, int persistent, int ck_lg) {
+    const int32_t* __restrict__ plan, int64_t gcap, int persistent, int ck_arg) {
   using Cfg = TileCfg<TILE>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
   extern __shared__ __align__(16) char smem[];
+  typedef const __attribute__((address_space(4))) int32_t* const_i32;
+  const int ck_lg = ck_arg >= 0 ? ck_arg : ((const_i32)w.queue)[Q_CKLG];
   const int depth = min(pr.batch, 64 * E);
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
@@ -934,7 +939,6 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
   int n_rows = 0;                          // parked rows (wavefront-uniform)
   const uint64_t below = lanes_below();
   float* __restrict__ ggrad = w.ggrad;
-  typedef const __attribute__((address_space(4))) int32_t* const_i32;
   const const_i32 item_off = (const_i32)w.item_off;  // not written during the kernel: scalar loads
   const int n_items = item_off[n_tiles];
   for (int it = 0;; ++it) {
@@ -1499,7 +1503,8 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   if (L.n_tiles <= 0) return hipSuccess;
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
-  const int64_t max_items = (int64_t)TileCfg<TILE>::QUADS * ((L.bf->caps.pairs >> L.ck_lg) + L.n_tiles);
+  const int64_t max_items =
+      (int64_t)TileCfg<TILE>::QUADS * ((L.bf->caps.pairs >> (L.ck_lg >= 0 ? L.ck_lg : 9)) + L.n_tiles);
   const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E, KIND);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {

@@ -76,10 +76,21 @@ struct Work {
 // [end - (k + 1) CK, end - k CK).  The forward stores every pixel's state at
 // the chunk boundaries it passes, and the adjoint runs one work item per
 // (tile, quadrant, chunk), so that a long list no longer sets the length of
-// the adjoint pass.  CK is chosen per launch (chunk_log2), at least CK_MIN,
-// for which the checkpoint store is sized.
+// the adjoint pass.  CK is params.chunk, or chosen per launch by the
+// binning (auto_chunk_log2); it is at least CK_MIN, for which the checkpoint
+// store is sized.
 constexpr int CK_MIN = 512, CK_MAX = 8192;
 __host__ __device__ inline int n_chunks(int len, int ck_lg) { return (len + (1 << ck_lg) - 1) >> ck_lg; }
+// About one adjoint item per two wavefront slots of the GPU: pairs x
+// quadrants / (8 x compute units) positions per chunk, rounded to a power of
+// two in [512, 4096].  Large launches keep whole lists together (fewer stored
+// states and item set-ups); small ones split long lists across wavefronts.
+__host__ __device__ inline int auto_chunk_log2(int64_t pairs, int quads, int n_cu) {
+  const double v = (double)pairs * quads / (8.0 * (n_cu > 0 ? n_cu : 1));
+  int lg = 9;
+  while (lg < 12 && v >= 1.4142135623730951 * (double)(1 << lg)) ++lg;
+  return lg;
+}
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
 // boundary point boff) has a header at cbox_base(boff, c) holding the box
@@ -111,6 +122,9 @@ constexpr float KIND_STROKE = 0.0f, KIND_FILL = 1.0f, KIND_ANISO = 2.0f;
 // sampling pass asked for (written with the Gaussian offsets), which lets the
 // per-kind adjoint kernels return at once when there are none.
 constexpr int Q_NFILL = 8, Q_NSTROKE = 9, Q_NANISO = 10;
+// Work::queue slot with the log2 chunk length that the binning chose for the
+// launch's lists when params.chunk is 0 (read by the blend kernels).
+constexpr int Q_CKLG = 11;
 
 struct Layout {
   size_t off[N_WS];
@@ -373,7 +387,7 @@ struct Launch {
   hipStream_t stream;
   int64_t n_tiles;
   int n_cu;
-  int ck_lg;  // log2 of the chunk length (chunk_log2)
+  int ck_lg;  // log2 of params.chunk, or -1: chosen by the binning (Q_CKLG)
 };
 
 // Scene table; also clears the NSPLAT_NUM_COUNTERS counters when given.
