@@ -39,7 +39,11 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
   const int64_t gcap = caps->gauss, pcap = caps->pairs, bcap = caps->boundary;
   lay.sort_blocks = (pcap + SORT_ITEMS - 1) / SORT_ITEMS;
   const int64_t tiles8 = nsplat_num_tiles(sc, 8);
-  const int64_t scan_n = std::max<int64_t>({gcap, (int64_t)RADIX_MAX * lay.sort_blocks, tiles8 + 1, 1});
+  // the one-digit binning's per-block tile counts: RADIX_MAX rows and a row
+  // of block totals, one column per FB_ITEMS Gaussians
+  const int64_t fb_hist = (int64_t)(RADIX_MAX + 1) * std::max<int64_t>((gcap + FB_ITEMS - 1) / FB_ITEMS, 1);
+  const int64_t hist_n = std::max<int64_t>((int64_t)RADIX_MAX * std::max<int64_t>(lay.sort_blocks, 1), fb_hist);
+  const int64_t scan_n = std::max<int64_t>({gcap, hist_n, tiles8 + 1, 1});
   lay.scan_blocks = (scan_n + SCAN_ITEMS - 1) / SCAN_ITEMS;
   const size_t sizes[N_WS] = {
       sizeof(double) * (size_t)(T + N * KNOT_PAD),         // knots
@@ -51,7 +55,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys0
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // keys1
       sizeof(uint32_t) * (size_t)std::max<int64_t>(pcap, 1),  // vals1
-      sizeof(uint32_t) * (size_t)(RADIX_MAX * std::max<int64_t>(lay.sort_blocks, 1)),  // hist
+      sizeof(uint32_t) * (size_t)hist_n,                   // hist
       sizeof(uint32_t) * (size_t)(lay.scan_blocks + 1),    // scan_tmp
       sizeof(float) * GG * (size_t)std::max<int64_t>(gcap, 1),  // ggrad
       sizeof(double) * 4 * (size_t)(K + N * CP_PAD),       // gcp

@@ -6,6 +6,9 @@
 //   radix passes  stable LSD radix sort on the key (histogram, scan, scatter
 //                 with wavefront match-ranking), so each tile keeps ascending
 //                 Gaussian order
+//   (up to RADIX_MAX tiles, one digit: k_bin_tilehist counts each block's
+//   pairs per tile, one scan turns the counts into list positions and
+//   k_bin_place writes every pair at its final place, in the same order)
 //   k_tile_ranges [begin, end) of every tile's slice (after a one-pass sort the
 //                 tile plan reads them off the scanned digit counts instead)
 //   k_order_*     the blend kernels' tile order, longest lists first
@@ -90,6 +93,226 @@ __global__ __launch_bounds__(256) void k_bin_emit(nsplat_curves cv, nsplat_param
           keys[pos] = (uint32_t)(st.tile_off + ty * st.tiles_x + tx);
           vals[pos] = (uint32_t)g;
         }
+  }
+}
+
+// One-digit binning (at most RADIX_MAX tiles): the pairs go straight to
+// their sorted places, in the order the emission and a stable one-pass
+// radix sort give (tile, then Gaussian).  Block b owns the Gaussians
+// [b FB_ITEMS, (b + 1) FB_ITEMS).  k_bin_tilehist stores its pair count per
+// tile key in row `key`, column b, of hist, and its pair total in row nd;
+// one exclusive scan over the rows makes row `key`, column b, the list
+// position of the block's first pair with that key, and row nd, column 0,
+// the pair total.  k_bin_place then recomputes each Gaussian's tile
+// rectangle and writes its Gaussian index at the position: wavefront w of
+// the block owns 64 FB_PER_LANE consecutive Gaussians, counts their pairs per
+// key, adds the counts of the earlier wavefronts to the block's positions,
+// and places its pairs in Gaussian order (rectangle rows, then columns, per
+// Gaussian) 64 at a time, ranking equal keys with ballots, through a window
+// of FB_WIN pairs staged in LDS.
+constexpr int FB_THREADS = 1024;
+constexpr int FB_WAVES = FB_THREADS / 64;
+constexpr int FB_PER_LANE = FB_ITEMS / FB_THREADS;  // 4
+constexpr int FB_WIN = 256;
+static_assert(FB_ITEMS == FB_THREADS * FB_PER_LANE, "Gaussians per block");
+
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Lanes whose Gaussian has the same tile rectangle as the previous lane's
+// (fill lattice points in a row mostly do) are counted by the first lane of
+// their run: it returns the run's length, the others 0.
+__device__ inline uint32_t rect_run(bool ok, int key0, int wdt, int n) {
+  const int lane = __lane_id();
+  const int pk = __shfl_up(key0, 1), pw = __shfl_up(wdt, 1), pn = __shfl_up(n, 1);
+  const bool pok = __shfl_up((int)ok, 1) != 0;
+  const bool same = ok && lane > 0 && pok && pk == key0 && pw == wdt && pn == n;
+  const uint64_t sm = __ballot(same);
+  if (!ok || same) return 0u;
+  const uint64_t after = lane == 63 ? 0ull : (sm >> (lane + 1));
+  return 1u + (uint32_t)__builtin_ctzll(~after);
+}
+
+// Tile rectangles of the Gaussians g0 + i * stride, i < FB_PER_LANE, with
+// their loads issued together: key of the first tile, width, tile count (0
+// when none or past G), and the scene's tile columns.
+__device__ inline void fb_rects(const nsplat_curves& cv, const nsplat_params& pr, const Work& w,
+                                const Gauss* __restrict__ gs, int64_t G, int64_t g0, int stride, float inv,
+                                int (&key0)[FB_PER_LANE], int (&wdt)[FB_PER_LANE], int (&n)[FB_PER_LANE],
+                                int (&sx)[FB_PER_LANE]) {
+  Gauss r[FB_PER_LANE];
+  int sc[FB_PER_LANE];
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) {
+    const int64_t g = g0 + (int64_t)i * stride;
+    if (g < G) r[i] = gs[g];
+    else r[i].curve = -1;
+  }
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) sc[i] = r[i].curve >= 0 ? cv.scene[r[i].curve] : 0;
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) {
+    const SceneTab st = w.scenes[sc[i]];
+    Rect rc;
+    key0[i] = wdt[i] = n[i] = sx[i] = 0;
+    if (r[i].curve >= 0 && tile_rect(r[i], pr.k_sigma, inv, st, &rc)) {
+      key0[i] = st.tile_off + rc.y0 * st.tiles_x + rc.x0;
+      sx[i] = st.tiles_x;
+      wdt[i] = rc.x1 - rc.x0 + 1;
+      n[i] = wdt[i] * (rc.y1 - rc.y0 + 1);
+    }
+  }
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_bin_tilehist(nsplat_curves cv, nsplat_params pr, Work w,
+                                                             const Gauss* __restrict__ gs, const int32_t* counters,
+                                                             int nd, int nb, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[RADIX_MAX];
+  __shared__ uint32_t wt[FB_WAVES];
+  const int col = blockIdx.x;
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const float inv = 1.0f / (float)pr.tile;
+  const int t = threadIdx.x;
+  for (int d = t; d < nd; d += FB_THREADS) h[d] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)col * FB_ITEMS;
+  uint32_t tot = 0u;
+  int key0[FB_PER_LANE], wdt[FB_PER_LANE], kn[FB_PER_LANE], sx[FB_PER_LANE];
+  fb_rects(cv, pr, w, gs, G, base + t, FB_THREADS, inv, key0, wdt, kn, sx);
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) {
+    const uint32_t run = rect_run(kn[i] > 0, key0[i], wdt[i], kn[i]);
+    if (run > 0u)
+      for (int r = 0, key = key0[i]; r < kn[i]; r += wdt[i], key += sx[i])
+        for (int x = 0; x < wdt[i]; ++x) atomicAdd(&h[key + x], run);
+    tot += (uint32_t)kn[i];
+  }
+  tot = wave_sum_u32(tot);
+  if (__lane_id() == 0) wt[t >> 6] = tot;
+  __syncthreads();
+  for (int d = t; d < nd; d += FB_THREADS) hist[(int64_t)d * nb + col] = h[d];
+  if (t == 0) {
+    uint32_t s = 0u;
+#pragma unroll
+    for (int q = 0; q < FB_WAVES; ++q) s += wt[q];
+    hist[(int64_t)nd * nb + col] = s;
+  }
+}
+
+// hist: scanned.  Block 0 publishes the pair count; with more pairs than
+// `cap` nothing is written (the tile plan then leaves every list empty).
+__global__ __launch_bounds__(FB_THREADS) void k_bin_place(nsplat_curves cv, nsplat_params pr, Work w,
+                                                          const Gauss* __restrict__ gs, int32_t* counters, int nd,
+                                                          int nb, int bits, const uint32_t* __restrict__ hist,
+                                                          uint32_t* __restrict__ vals, int64_t cap) {
+  __shared__ uint32_t off[FB_WAVES][RADIX_MAX];
+  __shared__ uint32_t lkey[FB_WAVES][FB_WIN], lval[FB_WAVES][FB_WIN];
+  const uint32_t* total = hist + (int64_t)nd * nb;  // row nd, column 0: the pair total
+  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap);
+  if ((int64_t)*total > cap) return;
+  const int col = blockIdx.x;
+  const int64_t G = counters[NSPLAT_CNT_GAUSS];
+  const int64_t base = (int64_t)col * FB_ITEMS;
+  if (base >= G) return;
+  const float inv = 1.0f / (float)pr.tile;
+  const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
+  for (int d = lane; d < nd; d += 64) off[wid][d] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // this wavefront's Gaussians, lane-interleaved: g = wbase + 64 i + lane
+  const int64_t wbase = base + (int64_t)wid * (64 * FB_PER_LANE);
+  int kx0[FB_PER_LANE], kw[FB_PER_LANE], kn[FB_PER_LANE], ksx[FB_PER_LANE];
+  fb_rects(cv, pr, w, gs, G, wbase + lane, 64, inv, kx0, kw, kn, ksx);
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) {
+    const uint32_t run = rect_run(kn[i] > 0, kx0[i], kw[i], kn[i]);
+    if (run > 0u)
+      for (int r = 0, key = kx0[i]; r < kn[i]; r += kw[i], key += ksx[i])
+        for (int x = 0; x < kw[i]; ++x) atomicAdd(&off[wid][key + x], run);
+  }
+  __syncthreads();
+  // per key: the block's first position plus the counts of the earlier
+  // wavefronts (read only for the keys the block holds: a block's Gaussians
+  // reach few tiles)
+  for (int d = t; d < nd; d += FB_THREADS) {
+    uint32_t c[FB_WAVES], any = 0u;
+#pragma unroll
+    for (int q = 0; q < FB_WAVES; ++q) {
+      c[q] = off[q][d];
+      any |= c[q];
+    }
+    if (any == 0u) continue;
+    uint32_t run = hist[(int64_t)d * nb + col];
+#pragma unroll
+    for (int q = 0; q < FB_WAVES; ++q) {
+      off[q][d] = run;
+      run += c[q];
+    }
+  }
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int i = 0; i < FB_PER_LANE; ++i) {
+    // this round's pairs in Gaussian order: lane l's at [e, e + kn)
+    const uint32_t n = (uint32_t)kn[i];
+    const uint32_t e = wave_incl_scan_u32(n) - n;
+    const int R = __builtin_amdgcn_readlane((int)(e + n), 63);
+    const uint32_t g = (uint32_t)(wbase + 64 * i + lane);
+    for (int w0 = 0; w0 < R; w0 += FB_WIN) {
+      const int k0 = max(0, w0 - (int)e), k1 = min((int)n, w0 + FB_WIN - (int)e);
+      if (k0 < k1) {
+        // rectangle position of pair k0, then stepped along its rows
+        const int ry = k0 / kw[i];
+        int x = k0 - ry * kw[i], key = kx0[i] + ry * ksx[i];
+        for (int k = k0; k < k1; ++k) {
+          lkey[wid][(int)e + k - w0] = (uint32_t)(key + x);
+          lval[wid][(int)e + k - w0] = g;
+          if (++x == kw[i]) {
+            x = 0;
+            key += ksx[i];
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int m = min(FB_WIN, R - w0);
+      for (int j = 0; j < m; j += 64) {
+        const bool active = j + lane < m;
+        const uint32_t key = active ? lkey[wid][j + lane] : 0u;
+        const uint32_t val = active ? lval[wid][j + lane] : 0u;
+        uint64_t peers = __ballot(active);
+        for (int b = 0; b < bits; ++b) {
+          const bool bit = (key >> b) & 1u;
+          const uint64_t bal = __ballot(bit);
+          peers &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t o = off[wid][key];
+        if (active) vals[o + rank] = val;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (active && rank == 0) off[wid][key] = o + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
   }
 }
 
@@ -367,7 +590,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict_
                                                             int32_t* __restrict__ order, int32_t* __restrict__ ck_off,
                                                             int32_t* __restrict__ item_off,
                                                             const uint32_t* __restrict__ hist, int sb, int nd,
-                                                            const int32_t* counters) {
+                                                            const int32_t* counters, int empty_on_cap) {
   __shared__ int h[32], base[32];
   __shared__ uint32_t wsum[2][PLAN_THREADS / 64];
   const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
@@ -375,10 +598,12 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict_
   if (tid == 0) queue[Q_CKLG] = ck_lg;
   if (hist) {
     const uint32_t total = (uint32_t)counters[NSPLAT_CNT_PAIRS];
+    // (empty_on_cap: the one-digit binning writes no pairs on an overflow)
+    const bool none = empty_on_cap && (counters[NSPLAT_CNT_STATUS] & NSPLAT_STATUS_PAIR_CAP);
     for (int t = tid; t < n_tiles; t += PLAN_THREADS) {
       const uint32_t s0 = hist[(int64_t)t * sb];
       const uint32_t s1 = t + 1 < nd ? hist[(int64_t)(t + 1) * sb] : total;
-      const bool any = s1 > s0;
+      const bool any = !none && s1 > s0;
       ranges[2 * t] = any ? (int32_t)s0 : 0;
       ranges[2 * t + 1] = any ? (int32_t)s1 : 0;
     }
@@ -475,6 +700,30 @@ hipError_t launch_bin(const Launch& L) {
   uint32_t* ek = (passes % 2) ? L.w.keys1 : L.w.keys0;
   uint32_t* ev = (passes % 2) ? L.w.vals1 : idx;
   hipError_t e;
+  if (passes == 1 && L.n_tiles <= SMALL_TILES) {
+    // one digit: count per block and tile, scan, place (k_bin_tilehist)
+    const int nd = 1 << key_bits;
+    const int nbk = (int)std::max<int64_t>((gcap + FB_ITEMS - 1) / FB_ITEMS, 1);
+    {
+      Phase ph(L, NSPLAT_T_BIN);
+      hipLaunchKernelGGL(k_bin_tilehist, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w,
+                         gs, cnt, nd, nbk, L.w.hist);
+      e = launch_scan(L.w.hist, nullptr, (int64_t)(nd + 1) * nbk, nullptr, L.w.scan_tmp, L.stream);
+      if (e != hipSuccess) return e;
+    }
+    {
+      Phase ph(L, NSPLAT_T_SORT);
+      hipLaunchKernelGGL(k_bin_place, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, gs,
+                         cnt, nd, nbk, key_bits, (const uint32_t*)L.w.hist, idx, pcap);
+    }
+    {
+      Phase ph(L, NSPLAT_T_RANGES);
+      hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, (int)L.n_tiles,
+                         L.pr->tile == 8 ? 1 : 4, L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
+                         (const uint32_t*)L.w.hist, nbk, nd, cnt, 1);
+    }
+    return hipGetLastError();
+  }
   {
     Phase ph(L, NSPLAT_T_BIN);
     hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt,
@@ -521,7 +770,7 @@ hipError_t launch_bin(const Launch& L) {
     if (nt > 0 && nt <= SMALL_TILES) {
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, nt,
                          L.pr->tile == 8 ? 1 : 4, L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
-                         from_hist ? (const uint32_t*)L.w.hist : nullptr, sb, 1 << key_bits, cnt);
+                         from_hist ? (const uint32_t*)L.w.hist : nullptr, sb, 1 << key_bits, cnt, 0);
     } else if (nt > 0) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
       hipLaunchKernelGGL(k_order_count, dim3(ob), dim3(256), 0, L.stream, L.bf->ranges, nt, L.w.obin);

@@ -19,6 +19,7 @@ constexpr int SCAN_ITEMS = 4096;        // elements per block in the device-wide
 constexpr int SORT_ITEMS = 4096;        // elements per block in a radix pass
 constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
+constexpr int FB_ITEMS = 4096;          // Gaussians per block of the one-digit binning (bin.hip)
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
 constexpr int N_WS = 28;                // workspace entries
 
@@ -49,7 +50,7 @@ struct Work {
   uint32_t* keys0;     // [caps.pairs]
   uint32_t* keys1;     // [caps.pairs]
   uint32_t* vals1;     // [caps.pairs]
-  uint32_t* hist;      // [256 * sort_blocks]
+  uint32_t* hist;      // radix digit counts [RADIX_MAX][sort_blocks], or the one-digit binning's [RADIX_MAX + 1][blocks]
   uint32_t* scan_tmp;  // [scan_blocks + 1]
   float* ggrad;        // [caps.gauss][4] per-Gaussian adjoints (d/dmx, d/dmy, d/dsigma, d/dopacity)
   double* gcp;         // [(n_keys + n_curves * CP_PAD)][4] control-point adjoints (x, y, w, s)

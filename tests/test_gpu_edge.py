@@ -278,6 +278,38 @@ def test_capacity_overflow_without_growth_is_flagged_and_consistent():
     assert all(torch.isfinite(g).all().item() for g in grads)
 
 
+def test_pair_overflow_leaves_every_list_empty():
+    """With fewer pair slots than pairs (and at most 1024 tiles, where
+    binning places pairs straight at their sorted positions) no pair is
+    written: the status bit and the required count are set, every tile list
+    is empty, the image is the background and the step stays finite."""
+    import torch
+    from paper_2606_31764_amd import _lib as Lb
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=2903, n_paths=6, size=72)
+    p = Params().replace(h=1.0)
+    sizer = Renderer(b, p)
+    t = param_tensors(b)
+    sizer.run_forward(t)
+    full = sizer.read_counters()
+    caps = dict(gauss=full[Lb.CNT_GAUSS] + 64, pairs=full[Lb.CNT_PAIRS] // 2, boundary=2 * full[Lb.CNT_BOUND_REQ] + 64)
+    r = Renderer(b, p, caps=caps)
+    r.sample(t, sync=False)
+    r.bin(t, sync=False)
+    img = r.forward(t)
+    grads = r.backward(t, 2.0 * (img - 0.5))
+    torch.cuda.synchronize()
+    cnt = r.read_counters()
+    assert cnt[Lb.CNT_STATUS] & Lb.STATUS_PAIR_CAP
+    assert cnt[Lb.CNT_PAIRS_REQ] == full[Lb.CNT_PAIRS]
+    ranges, _ = r.tiles()
+    assert np.all(ranges[:, 1] == ranges[:, 0])
+    H, W = b.hw[0]
+    bg = np.repeat(np.asarray(b.bg[0], np.float32), H * W)
+    np.testing.assert_array_equal(img.cpu().numpy(), bg)
+    assert all(torch.isfinite(g).all().item() for g in grads)
+
+
 def test_timing_mask_records_only_selected_phases():
     """nsplat_timing with NSPLAT_TIMING_ONLY | mask records event pairs around the
     masked phases alone; plain enable records every phase of the step."""
