@@ -26,6 +26,15 @@ struct nsplat_ctx {
     int tile, chunk;
   };
   std::vector<BinState> bin_tile;
+  // what the scene table of each workspace was last built for (tile side,
+  // N_L factor, scene sizes), so that nsplat_bin need not rebuild it
+  struct SceneSig {
+    const void* ws;
+    int tile;
+    float nl_factor;
+    std::vector<int32_t> hw;
+  };
+  std::vector<SceneSig> scene_sig;
 };
 
 namespace nsp {
@@ -123,8 +132,10 @@ static hipEvent_t timer_event(Timer* t) {
     const int ncap = t->cap ? 2 * t->cap : 256;
     hipEvent_t* np = new hipEvent_t[ncap];
     for (int i = 0; i < t->cap; ++i) np[i] = t->pool[i];
+    // timing-only events: no system-scope fence (cache write-back) when they
+    // are recorded, so that the phases they bracket run as they would without
     for (int i = t->cap; i < ncap; ++i)
-      if (hipEventCreate(&np[i]) != hipSuccess) np[i] = nullptr;
+      if (hipEventCreateWithFlags(&np[i], hipEventDisableSystemFence) != hipSuccess) np[i] = nullptr;
     delete[] t->pool;
     t->pool = np;
     t->cap = ncap;
@@ -258,6 +269,26 @@ int check_bufs(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   return NSPLAT_OK;
 }
 
+void record_scene_table(nsplat_ctx* ctx, const void* ws, const nsplat_scenes* sc, const nsplat_params* pr) {
+  std::vector<int32_t> hw(sc->hw_host, sc->hw_host + 2 * (size_t)sc->n_scenes);
+  for (auto& e : ctx->scene_sig)
+    if (e.ws == ws) {
+      e.tile = pr->tile;
+      e.nl_factor = pr->nl_factor;
+      e.hw.swap(hw);
+      return;
+    }
+  ctx->scene_sig.push_back({ws, pr->tile, pr->nl_factor, std::move(hw)});
+}
+
+bool scene_table_current(nsplat_ctx* ctx, const void* ws, const nsplat_scenes* sc, const nsplat_params* pr) {
+  for (const auto& e : ctx->scene_sig)
+    if (e.ws == ws)
+      return e.tile == pr->tile && e.nl_factor == pr->nl_factor && e.hw.size() == 2 * (size_t)sc->n_scenes &&
+             std::equal(e.hw.begin(), e.hw.end(), sc->hw_host);
+  return false;
+}
+
 void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
   for (auto& e : ctx->bin_tile)
     if (e.ws == ws) {
@@ -367,6 +398,7 @@ int nsplat_sample(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes*
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   hipError_t h = launch_scene_setup(L, bf->counters);
+  record_scene_table(ctx, bf->ws, sc, pr);
   if (h == hipSuccess && cv->n_curves > 0) h = launch_sample(L, frozen);
   if (h == hipSuccess && cv->n_curves == 0) h = launch_fill_u32((uint32_t*)L.w.goff, 0u, 1, L.stream);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_sample");
@@ -378,7 +410,14 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   Launch L;
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
-  hipError_t h = launch_scene_setup(L, nullptr);
+  // the table is rebuilt unless the last build on this workspace (in stream
+  // order, e.g. the nsplat_sample of the same step) used the same tile side,
+  // N_L factor and scene sizes
+  hipError_t h = hipSuccess;
+  if (!scene_table_current(ctx, bf->ws, sc, pr)) {
+    h = launch_scene_setup(L, nullptr);
+    record_scene_table(ctx, bf->ws, sc, pr);
+  }
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
   record_bin_tile(ctx, bf->ws, pr->tile, pr->chunk);
