@@ -235,7 +235,9 @@ typedef struct {
 
 /* NSPLAT_ABI_VERSION as built (no device work).  Context: binds the library
  * to device `device` (made current by the caller's thread for every later
- * call).  Holds the last error message and the autotuner's choices. */
+ * call).  Holds the last error message and the autotuner's choices.  A failed
+ * nsplat_create (no such device, device set-up error) still stores a context
+ * in *ctx that carries the message; the caller destroys it either way.  */
 int nsplat_abi_version(void);
 int nsplat_create(nsplat_ctx** ctx, int device);
 int nsplat_destroy(nsplat_ctx* ctx);

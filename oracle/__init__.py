@@ -78,7 +78,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        # NSPLAT_ORACLE_LIB: a separately built copy (e.g. with AddressSanitizer)
+        _lib = ctypes.CDLL(os.environ.get("NSPLAT_ORACLE_LIB") or build())
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         sig = {
             "or_plan": (i64, [vp, vp, vp, vp, vp]),
