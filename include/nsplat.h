@@ -23,10 +23,10 @@
  *   - Sizes that change from step to step (Gaussians, tile pairs, boundary
  *     points) are computed on the device and stored in `counters`; buffers are
  *     sized by capacities.  If a capacity is exceeded the excess is not
- *     written (for the tile pairs of a launch with at most 1024 tiles, no
- *     pair is written and every tile list is left empty), the required size
- *     is stored and a status bit is set; the caller reads the counters, grows
- *     the buffer and calls again.
+ *     written (for the tile pairs: no pair is written, the pair count is 0
+ *     and every tile list is left empty), the required size is stored and a
+ *     status bit is set; the caller reads the counters, grows the buffer and
+ *     calls again.
  *   - Return value: NSPLAT_OK, or an error code with a message available from
  *     nsplat_last_error.  Argument checks run on the host before any device
  *     work is issued.  Value errors that only the device can see (a curve with

@@ -61,24 +61,27 @@ __global__ __launch_bounds__(256) void k_bin_count(nsplat_curves cv, nsplat_para
   }
 }
 
-// Pair count from the scan total, its capped value, and the capacity flag.
-__device__ inline void pairs_total(int32_t* counters, const uint32_t* total, int64_t cap) {
+// Pair count from the scan total, its capped value (0 with none_on_cap: a
+// binning that writes no pair on an overflow), and the capacity flag.
+__device__ inline void pairs_total(int32_t* counters, const uint32_t* total, int64_t cap, bool none_on_cap = false) {
   const uint32_t t = *total;
   counters[NSPLAT_CNT_PAIRS_REQ] = t > 0x7fffffffu ? 0x7fffffff : (int32_t)t;
-  counters[NSPLAT_CNT_PAIRS] = (int32_t)((int64_t)t < cap ? (int64_t)t : cap);
+  counters[NSPLAT_CNT_PAIRS] = (int32_t)((int64_t)t <= cap ? (int64_t)t : (none_on_cap ? 0 : cap));
   int32_t st = counters[NSPLAT_CNT_STATUS] & ~NSPLAT_STATUS_PAIR_CAP;
   if ((int64_t)t > cap) st |= NSPLAT_STATUS_PAIR_CAP;
   counters[NSPLAT_CNT_STATUS] = st;
 }
 
 // Thread 0 also publishes the pair count (off[G_cap] holds the scan total);
-// no thread of this kernel reads it.
+// no thread of this kernel reads it.  With more pairs than `cap` no pair is
+// written and the count is 0.
 __global__ __launch_bounds__(256) void k_bin_emit(nsplat_curves cv, nsplat_params pr, Work w,
                                                   const Gauss* __restrict__ gs, int32_t* counters,
                                                   const uint32_t* __restrict__ off, const uint32_t* total,
                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                   int64_t cap) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap, true);
+  if ((int64_t)*total > cap) return;  // an overflow writes no pair (the lists stay empty)
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const float inv = 1.0f / (float)pr.tile;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
@@ -179,13 +182,17 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 
 __global__ __launch_bounds__(FB_THREADS) void k_bin_tilehist(nsplat_curves cv, nsplat_params pr, Work w,
                                                              const Gauss* __restrict__ gs, const int32_t* counters,
-                                                             int nd, int nb, uint32_t* __restrict__ hist) {
+                                                             int nd, int nb, uint32_t* __restrict__ hist,
+                                                             int32_t* __restrict__ ranges, int64_t n_ranges) {
   __shared__ uint32_t h[RADIX_MAX];
   __shared__ uint32_t wt[FB_WAVES];
   const int col = blockIdx.x;
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const float inv = 1.0f / (float)pr.tile;
   const int t = threadIdx.x;
+  const uint32_t mask = (uint32_t)nd - 1u;  // the low digit of the tile key
+  // (the tile ranges that k_tile_ranges fills in after a multi-pass sort)
+  for (int64_t i = (int64_t)col * FB_THREADS + t; i < n_ranges; i += (int64_t)nb * FB_THREADS) ranges[i] = 0;
   for (int d = t; d < nd; d += FB_THREADS) h[d] = 0u;
   __syncthreads();
   const int64_t base = (int64_t)col * FB_ITEMS;
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_bin_tilehist(nsplat_curves cv, n
     const uint32_t run = rect_run(kn[i] > 0, key0[i], wdt[i], kn[i]);
     if (run > 0u)
       for (int r = 0, key = key0[i]; r < kn[i]; r += wdt[i], key += sx[i])
-        for (int x = 0; x < wdt[i]; ++x) atomicAdd(&h[key + x], run);
+        for (int x = 0; x < wdt[i]; ++x) atomicAdd(&h[(uint32_t)(key + x) & mask], run);
     tot += (uint32_t)kn[i];
   }
   tot = wave_sum_u32(tot);
@@ -213,16 +220,21 @@ __global__ __launch_bounds__(FB_THREADS) void k_bin_tilehist(nsplat_curves cv, n
 }
 
 // hist: scanned.  Block 0 publishes the pair count; with more pairs than
-// `cap` nothing is written (the tile plan then leaves every list empty).
+// `cap` nothing is written and the count is 0 (the tile plan then leaves
+// every list empty).  Places by the low digit (nd = 2^bits values) of the
+// tile key; with keys != nullptr also writes the keys (the input of the
+// remaining radix passes of a key wider than one digit).
 __global__ __launch_bounds__(FB_THREADS) void k_bin_place(nsplat_curves cv, nsplat_params pr, Work w,
                                                           const Gauss* __restrict__ gs, int32_t* counters, int nd,
                                                           int nb, int bits, const uint32_t* __restrict__ hist,
-                                                          uint32_t* __restrict__ vals, int64_t cap) {
+                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                          int64_t cap) {
   __shared__ uint32_t off[FB_WAVES][RADIX_MAX];
   __shared__ uint32_t lkey[FB_WAVES][FB_WIN], lval[FB_WAVES][FB_WIN];
   const uint32_t* total = hist + (int64_t)nd * nb;  // row nd, column 0: the pair total
-  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) pairs_total(counters, total, cap, true);
   if ((int64_t)*total > cap) return;
+  const uint32_t mask = (uint32_t)nd - 1u;
   const int col = blockIdx.x;
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
   const int64_t base = (int64_t)col * FB_ITEMS;
@@ -242,7 +254,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_bin_place(nsplat_curves cv, nspl
     const uint32_t run = rect_run(kn[i] > 0, kx0[i], kw[i], kn[i]);
     if (run > 0u)
       for (int r = 0, key = kx0[i]; r < kn[i]; r += kw[i], key += ksx[i])
-        for (int x = 0; x < kw[i]; ++x) atomicAdd(&off[wid][key + x], run);
+        for (int x = 0; x < kw[i]; ++x) atomicAdd(&off[wid][(uint32_t)(key + x) & mask], run);
   }
   __syncthreads();
   // per key: the block's first position plus the counts of the earlier
@@ -272,18 +284,44 @@ __global__ __launch_bounds__(FB_THREADS) void k_bin_place(nsplat_curves cv, nspl
     const uint32_t e = wave_incl_scan_u32(n) - n;
     const int R = __builtin_amdgcn_readlane((int)(e + n), 63);
     const uint32_t g = (uint32_t)(wbase + 64 * i + lane);
+    // large rectangles (some lane with more than 16 pairs) are expanded by
+    // list position: every lane fills window slots, each finding the lane
+    // whose pairs hold it, so that one large rectangle does not serialise
+    // the wavefront
+    const bool spread = __ballot(n > 16u) != 0ull;
     for (int w0 = 0; w0 < R; w0 += FB_WIN) {
-      const int k0 = max(0, w0 - (int)e), k1 = min((int)n, w0 + FB_WIN - (int)e);
-      if (k0 < k1) {
-        // rectangle position of pair k0, then stepped along its rows
-        const int ry = k0 / kw[i];
-        int x = k0 - ry * kw[i], key = kx0[i] + ry * ksx[i];
-        for (int k = k0; k < k1; ++k) {
-          lkey[wid][(int)e + k - w0] = (uint32_t)(key + x);
-          lval[wid][(int)e + k - w0] = g;
-          if (++x == kw[i]) {
-            x = 0;
-            key += ksx[i];
+      if (!spread) {
+        const int k0 = max(0, w0 - (int)e), k1 = min((int)n, w0 + FB_WIN - (int)e);
+        if (k0 < k1) {
+          // rectangle position of pair k0, then stepped along its rows
+          const int ry = k0 / kw[i];
+          int x = k0 - ry * kw[i], key = kx0[i] + ry * ksx[i];
+          for (int k = k0; k < k1; ++k) {
+            lkey[wid][(int)e + k - w0] = (uint32_t)(key + x);
+            lval[wid][(int)e + k - w0] = g;
+            if (++x == kw[i]) {
+              x = 0;
+              key += ksx[i];
+            }
+          }
+        }
+      } else {
+        const int m = min(FB_WIN, R - w0);
+        for (int j = 0; j < m; j += 64) {
+          const int q = w0 + j + lane;  // list position of this slot
+          // the last lane whose first position is at most q owns it
+          int lo = 0;
+#pragma unroll
+          for (int step = 32; step >= 1; step >>= 1) {
+            const int mid = lo + step;
+            if ((int)__shfl((int)e, mid) <= q) lo = mid;
+          }
+          const int oe = __shfl((int)e, lo), ow = __shfl(kw[i], lo), ok0 = __shfl(kx0[i], lo),
+                    osx = __shfl(ksx[i], lo);
+          if (j + lane < m) {
+            const int k = q - oe, ry = k / ow;
+            lkey[wid][j + lane] = (uint32_t)(ok0 + ry * osx + (k - ry * ow));
+            lval[wid][j + lane] = (uint32_t)(wbase + 64 * i + lo);
           }
         }
       }
@@ -295,19 +333,23 @@ __global__ __launch_bounds__(FB_THREADS) void k_bin_place(nsplat_curves cv, nspl
         const bool active = j + lane < m;
         const uint32_t key = active ? lkey[wid][j + lane] : 0u;
         const uint32_t val = active ? lval[wid][j + lane] : 0u;
+        const uint32_t dig = key & mask;
         uint64_t peers = __ballot(active);
         for (int b = 0; b < bits; ++b) {
-          const bool bit = (key >> b) & 1u;
+          const bool bit = (dig >> b) & 1u;
           const uint64_t bal = __ballot(bit);
           peers &= bit ? bal : ~bal;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        const uint32_t o = off[wid][key];
-        if (active) vals[o + rank] = val;
+        const uint32_t o = off[wid][dig];
+        if (active) {
+          vals[o + rank] = val;
+          if (keys) keys[o + rank] = key;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (active && rank == 0) off[wid][key] = o + (uint32_t)__popcll(peers);
+        if (active && rank == 0) off[wid][dig] = o + (uint32_t)__popcll(peers);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -700,31 +742,45 @@ hipError_t launch_bin(const Launch& L) {
   uint32_t* ek = (passes % 2) ? L.w.keys1 : L.w.keys0;
   uint32_t* ev = (passes % 2) ? L.w.vals1 : idx;
   hipError_t e;
-  if (passes == 1 && L.n_tiles <= SMALL_TILES) {
-    // one digit: count per block and tile, scan, place (k_bin_tilehist)
-    const int nd = 1 << key_bits;
+  const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
+  uint32_t *kin = ek, *vin = ev;  // input of the next radix pass
+  int first = 0;                  // first radix pass still to run
+  // The placement at once pays where a block's 4096 Gaussians carry few
+  // pairs each and there are enough blocks to fill the GPU; a few Gaussians
+  // with large tile rectangles (wide strokes, tangent-aligned ones) keep the
+  // emission and radix passes, which spread their pairs over more wavefronts.
+  const bool fused = passes >= 1 && gcap >= 65536 && pcap <= 8 * gcap;
+  if (fused) {
+    // the low digit at once: count per block and digit, scan, place the
+    // pairs (k_bin_tilehist); the other digits, if any, by radix passes
+    const int nd = 1 << digit;
     const int nbk = (int)std::max<int64_t>((gcap + FB_ITEMS - 1) / FB_ITEMS, 1);
+    const bool one = passes == 1;
+    uint32_t* k0 = (ek == L.w.keys0) ? L.w.keys1 : L.w.keys0;
+    uint32_t* v0 = (ev == idx) ? L.w.vals1 : idx;
     {
       Phase ph(L, NSPLAT_T_BIN);
-      hipLaunchKernelGGL(k_bin_tilehist, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w,
-                         gs, cnt, nd, nbk, L.w.hist);
+      hipLaunchKernelGGL(k_bin_tilehist, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, nd,
+                         nbk, L.w.hist, L.bf->ranges, one ? (int64_t)0 : 2 * L.n_tiles);
       e = launch_scan(L.w.hist, nullptr, (int64_t)(nd + 1) * nbk, nullptr, L.w.scan_tmp, L.stream);
       if (e != hipSuccess) return e;
     }
     {
       Phase ph(L, NSPLAT_T_SORT);
-      hipLaunchKernelGGL(k_bin_place, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, gs,
-                         cnt, nd, nbk, key_bits, (const uint32_t*)L.w.hist, idx, pcap);
+      hipLaunchKernelGGL(k_bin_place, dim3(nbk), dim3(FB_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, nd, nbk,
+                         digit, (const uint32_t*)L.w.hist, one ? nullptr : k0, v0, pcap);
     }
-    {
+    if (one) {
       Phase ph(L, NSPLAT_T_RANGES);
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, (int)L.n_tiles,
                          L.pr->tile == 8 ? 1 : 4, L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
                          (const uint32_t*)L.w.hist, nbk, nd, cnt, 1);
+      return hipGetLastError();
     }
-    return hipGetLastError();
-  }
-  {
+    kin = k0;
+    vin = v0;
+    first = 1;
+  } else {
     Phase ph(L, NSPLAT_T_BIN);
     hipLaunchKernelGGL(k_bin_count, dim3(gg), dim3(256), 0, L.stream, *L.cv, *L.pr, L.w, gs, cnt, L.w.gcnt,
                        L.bf->ranges, 2 * L.n_tiles);
@@ -735,9 +791,7 @@ hipError_t launch_bin(const Launch& L) {
   }
   {
     Phase ph(L, NSPLAT_T_SORT);
-    const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
-    uint32_t *kin = ek, *vin = ev;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = first; p < passes; ++p) {
       const int shift = p * digit;
       const int bits = (key_bits - shift) < digit ? (key_bits - shift) : digit;
       uint32_t* kout = (kin == L.w.keys0) ? L.w.keys1 : L.w.keys0;
@@ -761,9 +815,8 @@ hipError_t launch_bin(const Launch& L) {
   {
     Phase ph(L, NSPLAT_T_RANGES);
     const int nt = (int)L.n_tiles, ob = (nt + 255) / 256;
-    // a one-pass sort's scanned digit counts are the tile ranges already
-    const int sb = (int)((pcap + SORT_ITEMS - 1) / SORT_ITEMS);
-    const bool from_hist = passes == 1 && sb > 0 && nt > 0 && nt <= SMALL_TILES;
+    // a one-pass radix sort's scanned digit counts are the tile ranges already
+    const bool from_hist = !fused && passes == 1 && sb > 0 && nt > 0 && nt <= SMALL_TILES;
     if (!from_hist)
       hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(pcap, 256, 8192)), dim3(256), 0, L.stream, L.w.keys0, cnt,
                          L.bf->ranges);

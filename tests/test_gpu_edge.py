@@ -278,16 +278,19 @@ def test_capacity_overflow_without_growth_is_flagged_and_consistent():
     assert all(torch.isfinite(g).all().item() for g in grads)
 
 
-def test_pair_overflow_leaves_every_list_empty():
-    """With fewer pair slots than pairs (and at most 1024 tiles, where
-    binning places pairs straight at their sorted positions) no pair is
-    written: the status bit and the required count are set, every tile list
-    is empty, the image is the background and the step stays finite."""
+@pytest.mark.parametrize("n_paths,size,tile", [(6, 72, 16), (24, 560, 8)])
+def test_pair_overflow_leaves_every_list_empty(n_paths, size, tile):
+    """With fewer pair slots than pairs no pair is written, whether the
+    pairs are emitted and radix-sorted (the small scene) or placed straight
+    at their sorted positions by the low digit of a wider key (4900 tiles,
+    then one radix pass): the status bit and the required count are set, the
+    pair count is 0, every tile list is empty, the image is the background
+    and the step stays finite."""
     import torch
     from paper_2606_31764_amd import _lib as Lb
     from paper_2606_31764_amd.render import Renderer, param_tensors
-    b = synth.config3(seed=2903, n_paths=6, size=72)
-    p = Params().replace(h=1.0)
+    b = synth.config3(seed=2903, n_paths=n_paths, size=size)  # 114,491 Gaussians at 560^2
+    p = Params().replace(h=1.0, tile=tile)
     sizer = Renderer(b, p)
     t = param_tensors(b)
     sizer.run_forward(t)
@@ -301,7 +304,7 @@ def test_pair_overflow_leaves_every_list_empty():
     torch.cuda.synchronize()
     cnt = r.read_counters()
     assert cnt[Lb.CNT_STATUS] & Lb.STATUS_PAIR_CAP
-    assert cnt[Lb.CNT_PAIRS_REQ] == full[Lb.CNT_PAIRS]
+    assert cnt[Lb.CNT_PAIRS_REQ] == full[Lb.CNT_PAIRS] and cnt[Lb.CNT_PAIRS] == 0
     ranges, _ = r.tiles()
     assert np.all(ranges[:, 1] == ranges[:, 0])
     H, W = b.hw[0]
