@@ -201,13 +201,22 @@ def profiled_traffic(kernel):
     return float(m_b.group(1))
 
 
+FB_ITEMS = 4096  # Gaussians per block of the binning by placement (the library's constant)
+
+
 def phase_bytes(step, tile):
-    """Algorithmic HBM bytes of one step's sample / bin / sort / ranges phases:
+    """Algorithmic HBM bytes of one step's sample / bin / sort / ranges phases.
     emit writes the 32 B record of every Gaussian (+4 B argmin of a fill
-    Gaussian); bin reads the records twice (count, emit), writes and rescans
-    the 4 B counts and writes the 8 B (key, index) pairs; every radix pass
-    reads the keys for its histogram, then reads and writes keys and indices
-    (20 B per pair); ranges reads the keys and writes 8 B per tile."""
+    Gaussian).  Binning by placement (the library's choice for at least 65,536
+    Gaussian slots and at most 8 pair slots each): bin reads every record and
+    writes the per-block counts of the low key digit, which the scan reads and
+    writes; sort reads the records again and writes each pair's 4 B index
+    (+4 B key when more digits follow), then 20 B per pair for every further
+    radix pass; ranges reads the scanned counts (one digit) or the keys and
+    writes 8 B per tile.  Otherwise: bin reads the records twice (count,
+    emit), writes and rescans the 4 B counts and writes the 8 B (key, index)
+    pairs; every radix pass reads the keys for its histogram, then reads and
+    writes keys and indices (20 B per pair); ranges as above."""
     r = step.r
     cnt = r.read_counters()
     G, P = int(cnt[0]), int(cnt[1])
@@ -219,8 +228,19 @@ def phase_bytes(step, tile):
     while bits < 31 and (1 << bits) < n_tiles:
         bits += 1
     passes = (bits + 9) // 10
-    return dict(emit=32 * G + 4 * n_fill, bin=64 * G + 12 * G + 8 * P, sort=passes * 20 * P,
-                ranges=4 * P + 8 * n_tiles), passes
+    gcap, pcap = int(r.caps["gauss"]), int(r.caps["pairs"])
+    placed = passes >= 1 and gcap >= 65536 and pcap <= 8 * gcap
+    emit = 32 * G + 4 * n_fill
+    if placed:
+        digit = (bits + passes - 1) // passes
+        nb = max((gcap + FB_ITEMS - 1) // FB_ITEMS, 1)
+        counts = 4 * ((1 << digit) + 1) * nb
+        out = dict(emit=emit, bin=32 * G + 3 * counts,
+                   sort=32 * G + (4 if passes == 1 else 8) * P + (passes - 1) * 20 * P,
+                   ranges=(8 * n_tiles if passes == 1 else 4 * P + 8 * n_tiles))
+    else:
+        out = dict(emit=emit, bin=64 * G + 12 * G + 8 * P, sort=passes * 20 * P, ranges=4 * P + 8 * n_tiles)
+    return out, passes
 
 
 def hbm_table(nbytes, phases):

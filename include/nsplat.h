@@ -72,7 +72,7 @@ extern "C" {
 /* Version of the structure layouts below; nsplat_abi_version() returns the
  * value the library was built with, so a binding can refuse a library whose
  * structures it would misread. */
-#define NSPLAT_ABI_VERSION 6
+#define NSPLAT_ABI_VERSION 7
 
 /* counters[] layout (dev int32[NSPLAT_NUM_COUNTERS]) */
 #define NSPLAT_CNT_GAUSS 0      /* Gaussians produced (<= capacity)          */
@@ -144,7 +144,15 @@ typedef struct {
                               the batch, or a superset of it; a curve with a
                               flag outside it counts as invalid data.
                               Without NSPLAT_ANISO the blend kernels run
-                              their forms without the tangent-aligned kind */
+                              their forms without the tangent-aligned kind,
+                              without NSPLAT_FILLED the fill adjoints are not
+                              launched                                    */
+  int32_t all_flags;       /* (host) the intersection (bitwise and) of
+                              flags[c] over the batch, or a subset of it (0
+                              declares nothing); a curve without one of its
+                              flags counts as invalid data.  With
+                              NSPLAT_FILLED (every curve filled) the stroke
+                              adjoint is not launched                     */
   const int32_t* scene;    /* (dev) [n_curves] scene of each curve           */
   const int32_t* degree;   /* (dev) [n_curves] p                             */
   const int32_t* flags;    /* (dev) [n_curves] NSPLAT_CLOSED | NSPLAT_FILLED | NSPLAT_ANISO */

@@ -12,7 +12,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nsplat.h")
 OK, EINVAL, ECAPACITY, EHIP = 0, 1, 2, 3
 CLOSED, FILLED, ANISO = 1, 2, 4
 MAX_DEGREE = 5
-ABI_VERSION = 6  # NSPLAT_ABI_VERSION of include/nsplat.h
+ABI_VERSION = 7  # NSPLAT_ABI_VERSION of include/nsplat.h
 CNT_GAUSS, CNT_PAIRS, CNT_STATUS, CNT_GAUSS_REQ, CNT_PAIRS_REQ, CNT_BOUND_REQ, CNT_BOUND = range(7)
 NUM_COUNTERS = 16
 STATUS_GAUSS_CAP, STATUS_PAIR_CAP, STATUS_BOUND_CAP, STATUS_DATA, STATUS_VALUE = 1, 2, 4, 8, 16
@@ -25,7 +25,8 @@ vp = ctypes.c_void_p
 
 class Curves(ctypes.Structure):
     _fields_ = [("n_curves", ctypes.c_int32), ("channels", ctypes.c_int32), ("n_keys", ctypes.c_int32),
-                ("n_taus", ctypes.c_int32), ("max_degree", ctypes.c_int32), ("any_flags", ctypes.c_int32)] + [
+                ("n_taus", ctypes.c_int32), ("max_degree", ctypes.c_int32), ("any_flags", ctypes.c_int32),
+                ("all_flags", ctypes.c_int32)] + [
                     (n, vp) for n in (
                     "scene", "degree", "flags", "key_off", "tau_off", "key_xy", "key_w", "key_s", "tau",
                     "color", "opacity")]

@@ -1142,18 +1142,22 @@ hipError_t launch_reg(const Launch& L, const nsplat_reg* reg) {
 hipError_t launch_adjoint(const Launch& L, const nsplat_grads* g) {
   {
     Phase ph(L, NSPLAT_T_ADJ_GAUSS);
+    // kinds the batch declares none of are not launched (any_flags, all_flags)
     const bool ani = (L.cv->any_flags & NSPLAT_ANISO) != 0;
+    const bool strokes = (L.cv->all_flags & NSPLAT_FILLED) == 0;
+    const bool fills = (L.cv->any_flags & NSPLAT_FILLED) != 0;
     if (low_degree(L)) {
-      launch_adj_stroke_d<3>(L);
+      if (strokes) launch_adj_stroke_d<3>(L);
       if (ani) launch_adj_aniso_d<3>(L);
     } else {
-      launch_adj_stroke_d<MAXP>(L);
+      if (strokes) launch_adj_stroke_d<MAXP>(L);
       if (ani) launch_adj_aniso_d<MAXP>(L);
     }
-    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
-                       *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
+    if (fills)
+      hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                         *L.pr, L.w, L.bf->plan, L.bf->counters, (const Gauss*)L.bf->gauss);
   }
-  if (L.bf->caps.boundary > 0) {
+  if (L.bf->caps.boundary > 0 && (L.cv->any_flags & NSPLAT_FILLED)) {
     Phase ph(L, NSPLAT_T_ADJ_BOUND);
     if (low_degree(L)) launch_adj_boundary_d<3>(L);
     else launch_adj_boundary_d<MAXP>(L);

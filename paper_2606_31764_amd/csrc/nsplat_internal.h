@@ -143,6 +143,7 @@ struct CurveView {
   int p, nk, nt, flags, m, ncp, k0, t0;
   int pmax;   // the batch's degree bound
   int fmask;  // the batch's declared flags
+  int amask;  // the flags every curve of the batch declares it carries
   const double* U;
   __device__ bool closed() const { return (flags & NSPLAT_CLOSED) != 0; }
   __device__ bool filled() const { return (flags & NSPLAT_FILLED) != 0; }
@@ -162,6 +163,7 @@ __device__ inline CurveView curve_view(const nsplat_curves& cv, const double* kn
   v.pmax = (cv.max_degree >= 1 && cv.max_degree <= MAXP) ? cv.max_degree : MAXP;
   v.flags = cv.flags[c];
   v.fmask = cv.any_flags;
+  v.amask = cv.all_flags;
   v.k0 = cv.key_off[c];
   v.nk = cv.key_off[c + 1] - v.k0;
   v.t0 = cv.tau_off[c];
@@ -176,6 +178,7 @@ __device__ inline CurveView curve_view(const nsplat_curves& cv, const double* kn
 __device__ inline bool curve_valid(const CurveView& v) {
   if (v.p < 1 || v.p > v.pmax) return false;
   if (v.flags & ~v.fmask) return false;  // a flag the batch did not declare
+  if ((v.flags & v.amask) != v.amask) return false;  // a flag all curves were declared to carry
   if (v.nk < v.p + 1) return false;
   if (v.nt != (v.closed() ? v.nk : v.nk - v.p)) return false;
   if (v.filled() && !v.closed()) return false;

@@ -304,10 +304,49 @@ __global__ __launch_bounds__(1024) void k_curve_scan(nsplat_curves cv, int32_t* 
 // Boundary points b_j = C(u_j), u_j = u_p + j (u_{m-p} - u_p) / N_b, their
 // padded AABB clipped to the canvas, and the lattice window
 // i in [ceil(x0 / h - 1/2), floor(x1 / h - 1/2)] (same for rows).
+// With own_offsets (up to PREP_THREADS * 4 curves) each block also takes the
+// boundary offset of its curve (the sum of the boundary counts of the filled
+// curves before it, as k_curve_scan with which = 0 gives it), and block 0
+// publishes the boundary counters, so that scan need not run.
 __global__ __launch_bounds__(PREP_THREADS) void k_boundary(nsplat_curves cv, nsplat_params pr, Work w,
-                                                           int32_t* plan, int64_t cap, int frozen) {
+                                                           int32_t* plan, int64_t cap, int frozen, int own_offsets,
+                                                           int32_t* counters) {
   __shared__ double red[4][PREP_THREADS / 64];
+  __shared__ int64_t psum[2][PREP_THREADS / 64];
   const int c = blockIdx.x;
+  if (own_offsets) {
+    int64_t before = 0, all = 0;
+    for (int k = threadIdx.x; k < cv.n_curves; k += PREP_THREADS) {
+      const int nbk = plan[(int64_t)P_STRIDE * k + P_NSAMP];
+      const int64_t v = ((cv.flags[k] & NSPLAT_FILLED) && nbk > 0) ? nbk : 0;
+      all += v;
+      if (k < c) before += v;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      before += __shfl_xor(before, off);
+      all += __shfl_xor(all, off);
+    }
+    if (__lane_id() == 0) {
+      psum[0][threadIdx.x >> 6] = before;
+      psum[1][threadIdx.x >> 6] = all;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t b = 0, t = 0;
+      for (int q = 0; q < PREP_THREADS / 64; ++q) {
+        b += psum[0][q];
+        t += psum[1][q];
+      }
+      plan[(int64_t)P_STRIDE * c + P_BOFF] = (int32_t)b;
+      if (c == 0) {
+        counters[NSPLAT_CNT_BOUND_REQ] = t > 0x7fffffff ? 0x7fffffff : (int32_t)t;
+        counters[NSPLAT_CNT_BOUND] = (int32_t)(t < cap ? t : cap);
+        if (t > cap) atomicOr(&counters[NSPLAT_CNT_STATUS], NSPLAT_STATUS_BOUND_CAP);
+      }
+    }
+    __syncthreads();
+  }
   if (!(cv.flags[c] & NSPLAT_FILLED)) return;
   const CurveView v = curve_view(cv, w.knots, c);
   if (!curve_valid(v)) return;
@@ -943,10 +982,13 @@ hipError_t launch_sample(const Launch& L, int frozen) {
   else
     hipLaunchKernelGGL(k_curve_prep<PREP_THREADS>, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
                        cnt, frozen, L.sc->n_scenes);
-  hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
-                     (int64_t)L.bf->caps.boundary, L.w.queue + Q_NFILL);
+  // up to 1024 curves the boundary blocks take their own offsets
+  const int own = n <= 4 * PREP_THREADS;
+  if (!own)
+    hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 0,
+                       (int64_t)L.bf->caps.boundary, L.w.queue + Q_NFILL);
   hipLaunchKernelGGL(k_boundary, dim3(n), dim3(PREP_THREADS), 0, L.stream, *L.cv, *L.pr, L.w, plan,
-                     (int64_t)L.bf->caps.boundary, frozen);
+                     (int64_t)L.bf->caps.boundary, frozen, own, cnt);
   hipLaunchKernelGGL(k_curve_scan, dim3(1), dim3(1024), 0, L.stream, *L.cv, plan, L.w.goff, cnt, 1,
                      (int64_t)L.bf->caps.gauss, L.w.queue + Q_NFILL);
   }

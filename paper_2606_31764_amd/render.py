@@ -101,6 +101,7 @@ class Meta:
         # the degree bound handed to the library (0: its own maximum)
         self.max_degree = int(np.max(batch.degree)) if self.n_curves else 0
         self.any_flags = int(np.bitwise_or.reduce(np.asarray(batch.flags, np.int64))) if self.n_curves else 0
+        self.all_flags = int(np.bitwise_and.reduce(np.asarray(batch.flags, np.int64))) if self.n_curves else 0
         if not 1 <= self.max_degree <= L.MAX_DEGREE:
             self.max_degree = 0
         self.n_scenes = int(len(self.hw_host))
@@ -109,6 +110,7 @@ class Meta:
 
     def curves_c(self, key_xy, key_w, key_s, tau, color, opacity) -> L.Curves:
         return L.Curves(self.n_curves, self.channels, self.n_keys, self.n_taus, self.max_degree, self.any_flags,
+                        self.all_flags,
                         _ptr(self.scene),
                         _ptr(self.degree),
                         _ptr(self.flags), _ptr(self.key_off), _ptr(self.tau_off), _ptr(key_xy), _ptr(key_w),

@@ -40,7 +40,7 @@ class _Fake:
     def __init__(self, n_curves=2, channels=3, hw=((64, 48),)):
         self.hw = np.ascontiguousarray(hw, np.int32)
         fake = ctypes.c_void_p(0x1000)
-        self.curves = L.Curves(n_curves, channels, 16, 10, 0, 0, *([fake] * 11))
+        self.curves = L.Curves(n_curves, channels, 16, 10, 0, 0, 0, *([fake] * 11))
         self.scenes = L.Scenes(len(self.hw), ctypes.c_void_p(self.hw.ctypes.data), fake, fake)
         self.params = L.Params(10, 0.5, 2, 1.5, 5, 3, 0.1, 1.0, 6.0, 0.99, 1e-6, 0.25, 4, 16, 64, 0, None)
         self.caps = L.Caps(1000, 4000, 100)

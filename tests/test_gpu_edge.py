@@ -502,6 +502,39 @@ def test_forward_and_backward_refuse_another_tile_than_bin():
     torch.cuda.synchronize()
 
 
+def test_declared_flag_intersection():
+    """nsplat_curves.all_flags declares flags every curve carries: with
+    NSPLAT_FILLED declared the stroke adjoint is not launched and a stroke
+    in the batch is invalid data (no Gaussians, status bit, plan flag) while
+    the fills render and differentiate as without it; the binding's own
+    intersection (fills and strokes: nothing) leaves both adjoints on."""
+    import torch
+    from paper_2606_31764_amd import _lib as Lb
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    fills = synth.fills(3300, n_paths=3, size=64, radius=(6.0, 16.0))
+    strokes = synth.strokes(3301, n_curves=2, size=64, nk_range=(5, 7))
+    b = synth._assemble(fills + strokes, [[64, 64]], [[1.0, 1.0, 1.0]], 3)
+    p = Params().replace(h=1.0, delta_c=3.0)
+    r = Renderer(b, p)
+    assert r.meta.all_flags & synth.FILLED == 0
+    r.meta.all_flags = synth.FILLED | synth.CLOSED
+    t = param_tensors(b)
+    img = r.run_forward(t)
+    grads = r.backward(t, 2.0 * (img - 0.5))
+    torch.cuda.synchronize()
+    cnt = r.read_counters()
+    plan = r.plan_np()
+    filled = (b.flags & synth.FILLED) != 0
+    assert cnt[Lb.CNT_STATUS] & 8
+    assert np.all(plan[~filled, 0] == 0) and np.all(plan[~filled, Lb.PLAN_FLAGS] & Lb.PLAN_INVALID)
+    sub = synth._gather(b, np.flatnonzero(filled), lambda c: 0, b.hw, b.bg)
+    ref = oracle.render(sub, oracle_params(p))[0]
+    assert np.abs(img.cpu().numpy().astype(np.float64) - ref).max() <= IMG_TOL
+    ko = int(b.key_off[int(np.flatnonzero(~filled)[0])])
+    assert torch.all(grads[0].view(-1, 2)[ko:] == 0)  # no gradient reaches the invalid strokes
+    assert all(torch.isfinite(g).all().item() for g in grads)
+
+
 @pytest.mark.parametrize("chunk", [512, 1024, 4096, 8192])
 def test_chunk_lengths_against_oracle(chunk):
     """Every chunk length the adjoint's split of the tile lists allows gives
