@@ -299,15 +299,20 @@ __global__ __launch_bounds__(256) void k_adj_fill(nsplat_curves cv, nsplat_param
     int c = 0;
     bool fill = false;
     if (g < G) {
-      const Gauss r = gs[g];
-      c = r.curve;
+      // the curve and lattice index of Gaussian g from the emission offsets
+      // (the record holds the same two values), starting from the curve in
+      // the record of the wavefront's first Gaussian (one scalar load)
+      typedef const __attribute__((address_space(4))) Gauss* const_gauss;
+      const int64_t g0 = first_lane_i64(g);
+      c = curve_walk(w.goff, cv.n_curves, g, g0, ((const_gauss)gs)[g0].curve);
       if (cv.flags[c] & NSPLAT_FILLED) {
         fill = true;
         kcur = c;
+        const int local = (int)(g - w.goff[c]);
         const double dO = (double)w.ggrad[g * GG + 3];
         const int32_t* row = plan + (int64_t)P_STRIDE * c;
         const int nx = row[P_NX];
-        const int iy = r.local / nx, ix = r.local - iy * nx;
+        const int iy = local / nx, ix = local - iy * nx;
         const double qx = ((double)(row[P_IX0] + ix) + 0.5) * h;
         const double qy = ((double)(row[P_IY0] + iy) + 0.5) * h;
         const int nb = row[P_NSAMP];

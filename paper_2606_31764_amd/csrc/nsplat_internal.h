@@ -323,24 +323,18 @@ __device__ inline int curve_search(const int32_t* goff, int n, int64_t g) {
   return lo;
 }
 
-// The same for a wavefront whose active lanes hold ascending g: one search
-// for the first active lane's g (wavefront-uniform; goff is read through the
-// constant address space, so the loads are scalar), then each lane steps
-// forward over at most 8 curve starts; a lane that would need more, or holds
-// a smaller g, searches alone.  goff must not change during the kernel.
-__device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) {
-  typedef const __attribute__((address_space(4))) int32_t* const_i32;
-  const const_i32 cg = (const_i32)goff;
-  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g);
-  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)g >> 32));
-  const int64_t g0 = (int64_t)(((uint64_t)hi32 << 32) | lo32);
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (cg[mid] <= g0) lo = mid;
-    else hi = mid - 1;
-  }
-  const int c0 = lo;
+// A 64-bit value of the first active lane (wavefront-uniform).
+__device__ inline int64_t first_lane_i64(int64_t v) {
+  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+}
+
+// The curve of g for a lane of a wavefront whose active lanes hold ascending
+// g, given the curve c0 of the first active lane's g0: each lane steps
+// forward from c0 over at most 8 curve starts; a lane that would need more,
+// or holds a smaller g, searches alone.
+__device__ inline int curve_walk(const int32_t* goff, int n, int64_t g, int64_t g0, int c0) {
   if (g < g0) return curve_search(goff, n, g);
   int c = c0;
   for (int k = 0; k < 8; ++k) {
@@ -348,6 +342,22 @@ __device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) {
     ++c;
   }
   return curve_search(goff, n, g);
+}
+
+// The same with c0 found by one search for the first active lane's g
+// (wavefront-uniform; goff is read through the constant address space, so
+// the loads are scalar).  goff must not change during the kernel.
+__device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) {
+  typedef const __attribute__((address_space(4))) int32_t* const_i32;
+  const const_i32 cg = (const_i32)goff;
+  const int64_t g0 = first_lane_i64(g);
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cg[mid] <= g0) lo = mid;
+    else hi = mid - 1;
+  }
+  return curve_walk(goff, n, g, g0, lo);
 }
 
 __device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) {
