@@ -242,16 +242,19 @@ __global__ __launch_bounds__(256) void k_adj_stroke(nsplat_curves cv, nsplat_par
     v.p = 0;
     bool stroke = false;
     if (g < G) {
-      const Gauss r = gs[g];
-      c = r.curve;
+      // curve and sample index from the emission offsets, as in k_adj_fill
+      typedef const __attribute__((address_space(4))) Gauss* const_gauss;
+      const int64_t g0 = first_lane_i64(g);
+      c = curve_walk(w.goff, cv.n_curves, g, g0, ((const_gauss)gs)[g0].curve);
       if (!(cv.flags[c] & (NSPLAT_FILLED | NSPLAT_ANISO))) {
         stroke = true;
+        const int local = (int)(g - w.goff[c]);
         v = curve_view(cv, w.knots, c);
         const float* gg = w.ggrad + g * GG;
         const double ab[3] = {(double)gg[0], (double)gg[1], (double)gg[2] / (double)pr.rho};  // sigma = s / rho
         const int32_t* row = plan + (int64_t)P_STRIDE * c;
         const int M = row[P_NSAMP];
-        int j = v.closed() ? r.local : r.local - pr.kappa;
+        int j = v.closed() ? local : local - pr.kappa;
         j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
         double dt;
         const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), &dt);
@@ -395,14 +398,7 @@ __global__ __launch_bounds__(256) void k_adj_boundary(nsplat_curves cv, Work w, 
     CurveView v;
     v.p = 0;
     if (b < NB) {
-      // curve: the last c with boff <= b
-      int lo = 0, hi = n - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (plan[(int64_t)P_STRIDE * mid + P_BOFF] <= b) lo = mid;
-        else hi = mid - 1;
-      }
-      c = lo;
+      c = last_le_wave<P_STRIDE, P_BOFF>(plan, n, b);  // curve: the last c with boff <= b
       v = curve_view(cv, w.knots, c);
       const int32_t* row = plan + (int64_t)P_STRIDE * c;
       const int nb = row[P_NSAMP];
@@ -936,13 +932,7 @@ __global__ __launch_bounds__(256, PD <= 3 ? 2 : 1) void k_reg_boundary(nsplat_cu
     v.p = 0;
     bool act = false;
     if (bi < NB) {
-      int lo = 0, hi = n - 1;  // the last c with boff <= bi
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (plan[(int64_t)P_STRIDE * mid + P_BOFF] <= bi) lo = mid;
-        else hi = mid - 1;
-      }
-      c = lo;
+      c = last_le_wave<P_STRIDE, P_BOFF>(plan, n, bi);  // the last c with boff <= bi
       v = curve_view(cv, w.knots, c);
       const int32_t* row = plan + (int64_t)P_STRIDE * c;
       const int nb = row[P_NSAMP];

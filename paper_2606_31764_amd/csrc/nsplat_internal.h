@@ -310,14 +310,14 @@ __device__ inline bool tile_axis(float m, float r, float inv_tile, int n, float*
   return true;
 }
 
-// Scene of a global tile index (binary search over the scene table).
-// The curve of Gaussian g: the last c with goff[c] <= g (goff ascending,
-// goff[0] = 0).
-__device__ inline int curve_search(const int32_t* goff, int n, int64_t g) {
+// The last c with a[S c + O] <= x, for an ascending column of n entries
+// (stride S, offset O) whose first entry is <= x.
+template <int S, int O>
+__device__ inline int last_le(const int32_t* a, int n, int64_t x) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (goff[mid] <= g) lo = mid;
+    if (a[(int64_t)S * mid + O] <= x) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -330,36 +330,48 @@ __device__ inline int64_t first_lane_i64(int64_t v) {
   return (int64_t)(((uint64_t)hi32 << 32) | lo32);
 }
 
-// The curve of g for a lane of a wavefront whose active lanes hold ascending
-// g, given the curve c0 of the first active lane's g0: each lane steps
-// forward from c0 over at most 8 curve starts; a lane that would need more,
-// or holds a smaller g, searches alone.
-__device__ inline int curve_walk(const int32_t* goff, int n, int64_t g, int64_t g0, int c0) {
-  if (g < g0) return curve_search(goff, n, g);
+// last_le for a lane of a wavefront whose active lanes hold ascending x,
+// given the answer c0 for the first active lane's x0: each lane steps
+// forward from c0 over at most 8 entries; a lane that would need more, or
+// holds a smaller x, searches alone.
+template <int S, int O>
+__device__ inline int last_le_walk(const int32_t* a, int n, int64_t x, int64_t x0, int c0) {
+  if (x < x0) return last_le<S, O>(a, n, x);
   int c = c0;
   for (int k = 0; k < 8; ++k) {
-    if (c + 1 >= n || goff[c + 1] > g) return c;
+    if (c + 1 >= n || a[(int64_t)S * (c + 1) + O] > x) return c;
     ++c;
   }
-  return curve_search(goff, n, g);
+  return last_le<S, O>(a, n, x);
 }
 
-// The same with c0 found by one search for the first active lane's g
-// (wavefront-uniform; goff is read through the constant address space, so
-// the loads are scalar).  goff must not change during the kernel.
-__device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) {
+// The same with c0 found by one search for the first active lane's x
+// (wavefront-uniform; the column is read through the constant address space,
+// so the loads are scalar).  The column must not change during the kernel.
+template <int S, int O>
+__device__ inline int last_le_wave(const int32_t* a, int n, int64_t x) {
   typedef const __attribute__((address_space(4))) int32_t* const_i32;
-  const const_i32 cg = (const_i32)goff;
-  const int64_t g0 = first_lane_i64(g);
+  const const_i32 ca = (const_i32)a;
+  const int64_t x0 = first_lane_i64(x);
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (cg[mid] <= g0) lo = mid;
+    if (ca[(int64_t)S * mid + O] <= x0) lo = mid;
     else hi = mid - 1;
   }
-  return curve_walk(goff, n, g, g0, lo);
+  return last_le_walk<S, O>(a, n, x, x0, lo);
 }
 
+// The curve of Gaussian g: the last c with goff[c] <= g (goff ascending,
+// goff[0] = 0), per lane, per wavefront, and from the curve c0 of the first
+// active lane's g0.
+__device__ inline int curve_search(const int32_t* goff, int n, int64_t g) { return last_le<1, 0>(goff, n, g); }
+__device__ inline int curve_of_wave(const int32_t* goff, int n, int64_t g) { return last_le_wave<1, 0>(goff, n, g); }
+__device__ inline int curve_walk(const int32_t* goff, int n, int64_t g, int64_t g0, int c0) {
+  return last_le_walk<1, 0>(goff, n, g, g0, c0);
+}
+
+// Scene of a global tile index (binary search over the scene table).
 __device__ inline int scene_of_tile(const SceneTab* st, int n_scenes, int tile) {
   int lo = 0, hi = n_scenes - 1;
   while (lo < hi) {
