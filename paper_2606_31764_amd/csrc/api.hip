@@ -83,6 +83,7 @@ Layout workspace_layout(const nsplat_curves* cv, const nsplat_scenes* sc, const 
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gcol
       sizeof(double) * SEG_WORDS * (size_t)(bcap + (SDF_CHUNK - 1) * N + 1),  // segs
       sizeof(float4) * (size_t)std::max<int64_t>(gcap, 1),  // gaux
+      sizeof(float) * (size_t)std::max<int64_t>(gcap, 1),   // gop
   };
   size_t off = 0;
   for (int i = 0; i < N_WS; ++i) {
@@ -124,6 +125,7 @@ Work carve(void* ws, const Layout& lay) {
   w.gcol = (float4*)(b + lay.off[25]);
   w.segs = (double*)(b + lay.off[26]);
   w.gaux = (float4*)(b + lay.off[27]);
+  w.gop = (float*)(b + lay.off[28]);
   return w;
 }
 

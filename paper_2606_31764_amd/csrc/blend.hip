@@ -247,10 +247,11 @@ __device__ inline bool fill_corners_ok(const int32_t* __restrict__ idx, const Fi
 
 // Opacities of the quadrant's lattice neighbourhood (NB x NB cells, window
 // index (ib, jb) at cell 0; lane l gathers cells it * 64 + l): those of the
-// run's Gaussians at list positions p0 .. p1, `none` elsewhere.  Reads below
-// the record capacity only, so that a rectangle still to be checked is safe.
+// run's Gaussians at list positions p0 .. p1, `none` elsewhere, read from the
+// packed fill opacities (gop, the records' values).  Reads below the record
+// capacity only, so that a rectangle still to be checked is safe.
 template <int NB, int NIT>
-__device__ inline void fill_gather(const Gauss* __restrict__ gs, int64_t gcap, const FillRun& fr, int ib, int jb,
+__device__ inline void fill_gather(const float* __restrict__ gop, int64_t gcap, const FillRun& fr, int ib, int jb,
                                    int p0, int p1, float none, float (&og)[NIT]) {
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -260,7 +261,7 @@ __device__ inline void fill_gather(const Gauss* __restrict__ gs, int64_t gcap, c
     if (sl < NB * NB && i >= fr.i0 && i <= fr.i1 && j >= fr.j0 && j <= fr.j1) {
       const int pos = fr.p_lo + (j - fr.j0) * fr.w + (i - fr.i0);
       const int64_t g = (int64_t)fr.goff + (int64_t)j * fr.nx + i;
-      if (pos >= p0 && pos <= p1 && g < gcap) o = gs[g].opacity;
+      if (pos >= p0 && pos <= p1 && g < gcap) o = gop[g];
     }
     og[it] = o;
   }
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(BLOCK, E == 1 ? 4 : 1) void k_blend_fwd(
                         sg, hi - 1, start, end, 1.0, ks, inv_tile, st, lt, TILE, &fr)) {
           // the opacities and the corner check in flight together
           const int ib = x0 + (quad & 1) * Cfg::SUB - fr.ix0 - FR_R, jb = y0 + (quad >> 1) * Cfg::SUB - fr.iy0 - FR_R;
-          fill_gather<FNB, FNIT>(gs, gcap, fr, ib, jb, fr.p_lo, hi - 1, 0.0f, og);
+          fill_gather<FNB, FNIT>(w.gop, gcap, fr, ib, jb, fr.p_lo, hi - 1, 0.0f, og);
           take = fill_corners_ok(idx, fr);
         }
         if (take) {
@@ -1181,7 +1182,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
           // the opacities and the corner check in flight together
           p1 = min(fr.p_hi, c_hi - 1);
           const int ib = x0 + (quad & 1) * Cfg::SUB - fr.ix0 - FR_R, jb = y0 + (quad >> 1) * Cfg::SUB - fr.iy0 - FR_R;
-          fill_gather<BNB, BNIT>(gs, gcap, fr, ib, jb, s_lo, p1, __builtin_nanf(""), og);
+          fill_gather<BNB, BNIT>(w.gop, gcap, fr, ib, jb, s_lo, p1, __builtin_nanf(""), og);
           take = fill_corners_ok(idx, fr);
         }
         if (take) {

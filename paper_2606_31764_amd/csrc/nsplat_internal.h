@@ -21,7 +21,7 @@ constexpr int RADIX_BITS_MAX = 10;      // widest radix digit
 constexpr int RADIX_MAX = 1 << RADIX_BITS_MAX;
 constexpr int FB_ITEMS = 4096;          // Gaussians per block of the one-digit binning (bin.hip)
 constexpr int MAX_BATCH = 256;          // LDS depth limit of the blend kernels
-constexpr int N_WS = 28;                // workspace entries
+constexpr int N_WS = 29;                // workspace entries
 
 // One Gaussian (32 bytes).  The centre is kept in FP64 so that the blend can
 // form exact tile-local FP32 coordinates (a fl32 absolute centre is off by up
@@ -70,6 +70,7 @@ struct Work {
   float4* gcol;        // [caps.gauss] colour of each Gaussian's curve, and its kind (Kind below)
   float4* gaux;        // [caps.gauss] tangent-aligned Gaussians: tangent (x, y), axis across the curve
   double* segs;        // [caps.boundary + (SDF_CHUNK - 1) * n_curves][SEG_WORDS] fill SDF segment records
+  float* gop;          // [caps.gauss] fill Gaussians: the record's opacity, packed for the fill-run gathers
 };
 
 // The compositing lists are cut into chunks of CK = 2^ck_lg list positions,

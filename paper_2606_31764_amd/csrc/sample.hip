@@ -769,6 +769,7 @@ __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params
       r.opacity = (float)(o * (1.0 / (1.0 + exp(-z))));        // Eq. 7
       if (gp < G) {  // a capped (overflowing) emission may map past the capacity
         w.aux[gp] = arg | (sgn < 0.0 ? (int32_t)0x80000000 : 0);
+        w.gop[gp] = r.opacity;
         out[gp] = r;
         w.gcol[gp] = curve_colour(cv, c, KIND_FILL);
       }
