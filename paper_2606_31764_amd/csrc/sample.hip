@@ -492,9 +492,8 @@ __device__ inline double4 ld_box(P p, int i) {
 // against thr = min(ub, best) decides whether its segments are visited;
 // otherwise its crossings are counted in closed form where the box allows.
 template <class P>
-__device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P segd, int nb, double ub,
-                                 double abs_margin, double mx, double* best, int* ibest, double* tbest, int* wn) {
-  const double4 b = ld_box(boxd, 1 + k);  // x0, x1, y0, y1
+__device__ inline void sdf_chunk_box(int k, const double4& b, double qx, double qy, P bpd, P segd, int nb, double ub,
+                                     double abs_margin, double mx, double* best, int* ibest, double* tbest, int* wn) {
   const double ex0 = fmax(fmax(b.x - qx, qx - b.y), 0.0);
   const double ey0 = fmax(fmax(b.z - qy, qy - b.w), 0.0);
   const double lb = ex0 * ex0 + ey0 * ey0;
@@ -540,6 +539,13 @@ __device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P s
   *wn += wk;
 }
 
+// The same with the chunk's box (x0, x1, y0, y1) read here.
+template <class P>
+__device__ inline void sdf_chunk(int k, double qx, double qy, P bpd, P boxd, P segd, int nb, double ub,
+                                 double abs_margin, double mx, double* best, int* ibest, double* tbest, int* wn) {
+  sdf_chunk_box(k, ld_box(boxd, 1 + k), qx, qy, bpd, segd, nb, ub, abs_margin, mx, best, ibest, tbest, wn);
+}
+
 __device__ inline double sdf_scale(double ax, double ay, const double4& hb) {
   return 1.0 + ax + ay + 2.0 * fmax(fmax(fabs(hb.x), fabs(hb.y)), fmax(fabs(hb.z), fabs(hb.w)));
 }
@@ -564,6 +570,14 @@ __device__ inline double polyline_sdf(double qx, double qy, P bpd, P boxd, P seg
   *targ = tbest;
   *sgn_out = wn >= 1 ? 1.0 : -1.0;
   return sqrt(best);
+}
+
+// Lane l's value of v (wavefront-uniform).
+__device__ inline double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ inline double wave_min_f64(double v) {
@@ -592,6 +606,15 @@ __device__ inline double polyline_sdf_wave(double qx, double qy, double wx0, dou
   const int lane = __lane_id();
   typedef const double* gdp;
   const gdp bpv = (gdp)bpd, boxv = (gdp)boxd;  // per-lane (vector) reads
+  // the first 64 chunks' boxes are requested with their start points, so
+  // that both arrive in one round trip
+  double fb0 = 0.0, fb1 = 0.0, fb2 = 0.0, fb3 = 0.0;
+  if (lane < K) {
+    fb0 = boxv[4 * (1 + lane)];
+    fb1 = boxv[4 * (1 + lane) + 1];
+    fb2 = boxv[4 * (1 + lane) + 2];
+    fb3 = boxv[4 * (1 + lane) + 3];
+  }
   double u = INFINITY;
   for (int k = lane; k < K; k += 64) {
     const double vx = bpv[2 * k * SDF_CHUNK], vy = bpv[2 * k * SDF_CHUNK + 1];
@@ -609,9 +632,14 @@ __device__ inline double polyline_sdf_wave(double qx, double qy, double wx0, dou
   for (int k0 = 0; k0 < K; k0 += 64) {
     const int k = k0 + lane;
     bool full = false, endp = false;
+    double b0 = fb0, b1 = fb1, b2 = fb2, b3 = fb3;  // chunk k's box: x0, x1, y0, y1
     if (k < K) {
-      const double b0 = boxv[4 * (1 + k)], b1 = boxv[4 * (1 + k) + 1], b2 = boxv[4 * (1 + k) + 2],
-                   b3 = boxv[4 * (1 + k) + 3];  // x0, x1, y0, y1
+      if (k0 > 0) {
+        b0 = boxv[4 * (1 + k)];
+        b1 = boxv[4 * (1 + k) + 1];
+        b2 = boxv[4 * (1 + k) + 2];
+        b3 = boxv[4 * (1 + k) + 3];
+      }
       const double ex0 = fmax(fmax(b0 - wx1, wx0 - b1), 0.0);
       const double ey0 = fmax(fmax(b2 - wy1, wy0 - b3), 0.0);
       const bool cand = ex0 * ex0 + ey0 * ey0 <= ubW + 1e-8 * ubW + amW;
@@ -626,10 +654,12 @@ __device__ inline double polyline_sdf_wave(double qx, double qy, double wx0, dou
       const int bit = __builtin_ctzll(m);
       m &= m - 1;
       const int kk = k0 + bit;
+      // the chunk's box from the lane that classified it
+      const double4 b = make_double4(readlane_f64(b0, bit), readlane_f64(b1, bit), readlane_f64(b2, bit),
+                                     readlane_f64(b3, bit));
       if ((fm >> bit) & 1ull) {
-        sdf_chunk(kk, qx, qy, bpd, boxd, segd, nb, ubW, abs_margin, mx, &best, &ibest, &tbest, &wn);
+        sdf_chunk_box(kk, b, qx, qy, bpd, segd, nb, ubW, abs_margin, mx, &best, &ibest, &tbest, &wn);
       } else {
-        const double4 b = ld_box(boxd, 1 + kk);
         if (b.z <= qy && qy < b.w) {
           const int i0 = kk * SDF_CHUNK, i1 = i0 + SDF_CHUNK < nb ? i0 + SDF_CHUNK : nb;
           const double2 E = ld_pt(bpd, i1 < nb ? i1 : 0);
