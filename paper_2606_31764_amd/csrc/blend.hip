@@ -303,7 +303,8 @@ __host__ __device__ constexpr bool bwd_six_waves(int tile, int E, int kind) {
 }
 __host__ __device__ constexpr int park_rows(int tile, int E, int kind) { return bwd_six_waves(tile, E, kind) ? 12 : 16; }
 // wavefronts per SIMD the adjoint is built for: six without the fill-run
-// walk at one pixel per lane and depth 64, five with it
+// walk at one pixel per lane and one entry per lane, four with it (or at
+// several pixels per lane), one at several entries per lane
 __host__ __device__ constexpr int bwd_waves(int tile, int E, int kind) {
   return bwd_six_waves(tile, E, kind) ? 6 : (E == 1 ? 4 : 1);
 }
@@ -1125,7 +1126,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
           const float G = dx >= sd ? Gr[dx < 0 ? -dx : dx] : 0.0f;
           const float oG = o * G;
           const bool lt = oG < amax;
-          const float alpha = lt ? oG : amax;
+          const float alpha = fminf(oG, amax);  // lt ? oG : amax, also for a NaN oG
           const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
           T[0] *= r;
           aT[0] = __builtin_fmaf(alpha, T[0], aT[0]);
