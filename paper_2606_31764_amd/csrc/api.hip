@@ -18,12 +18,12 @@ struct nsplat_ctx {
   int n_cu = 256;
   std::string err;
   nsp::Timer timer;
-  // tile side and chunk length of the last nsplat_bin on each workspace (the
-  // tile lists, checkpoint offsets and adjoint items in it are laid out for
-  // them)
+  // tile side, chunk length and adjoint pixel blocks per chunk of the last
+  // nsplat_bin on each workspace (the tile lists, checkpoint offsets and
+  // adjoint items in it are laid out for them)
   struct BinState {
     const void* ws;
-    int tile, chunk;
+    int tile, chunk, blocks;
   };
   std::vector<BinState> bin_tile;
   // what the scene table of each workspace was last built for (tile side,
@@ -291,19 +291,22 @@ bool scene_table_current(nsplat_ctx* ctx, const void* ws, const nsplat_scenes* s
   return false;
 }
 
-void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
+void record_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk, int blocks) {
   for (auto& e : ctx->bin_tile)
     if (e.ws == ws) {
       e.tile = tile;
       e.chunk = chunk;
+      e.blocks = blocks;
       return;
     }
-  ctx->bin_tile.push_back({ws, tile, chunk});
+  ctx->bin_tile.push_back({ws, tile, chunk, blocks});
 }
 
 // NSPLAT_EINVAL when the workspace's tile lists were built (by this context)
-// for another tile side or params.chunk than this launch's.
-int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
+// for another tile side or params.chunk than this launch's, or (blocks > 0,
+// the adjoint) with adjoint items for another pixel-block split: at 32 x 32
+// tiles the split follows whether the curves declare fills.
+int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk, int blocks = 0) {
   for (const auto& e : ctx->bin_tile) {
     if (e.ws != ws) continue;
     if (e.tile != tile)
@@ -312,6 +315,10 @@ int check_bin_tile(nsplat_ctx* ctx, const void* ws, int tile, int chunk) {
     if (e.chunk != chunk)
       return fail(ctx, NSPLAT_EINVAL, "the tile lists of this workspace were built by nsplat_bin with chunk %d, "
                   "but params.chunk is %d", e.chunk, chunk);
+    if (blocks > 0 && e.blocks != blocks)
+      return fail(ctx, NSPLAT_EINVAL, "the adjoint items of this workspace were built by nsplat_bin for %d pixel "
+                  "blocks per chunk, but these curves need %d (any_flags differs in NSPLAT_FILLED)", e.blocks,
+                  blocks);
   }
   return NSPLAT_OK;
 }
@@ -422,7 +429,7 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_scenes* sc
   }
   if (h == hipSuccess) h = launch_bin(L);
   if (h != hipSuccess) return hip_fail(ctx, h, "nsplat_bin");
-  record_bin_tile(ctx, bf->ws, pr->tile, pr->chunk);
+  record_bin_tile(ctx, bf->ws, pr->tile, pr->chunk, nsp::adj_blocks_of(L));
   return NSPLAT_OK;
 }
 
@@ -446,7 +453,7 @@ int nsplat_backward_reg(nsplat_ctx* ctx, const nsplat_curves* cv, const nsplat_s
   int e = prepare(ctx, cv, sc, pr, bf, stream, &L);
   if (e) return e;
   if (!dL || !T_final || !n_last || !gr) return fail(ctx, NSPLAT_EINVAL, "dL_dimage / T_final / n_last / grads is NULL");
-  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, pr->chunk))) return e;
+  if ((e = check_bin_tile(ctx, bf->ws, pr->tile, pr->chunk, nsp::adj_blocks_of(L)))) return e;
   const bool use_reg = reg && (reg->bbox_weight != 0.0f || reg->deriv_weight != 0.0f);
   if (use_reg) {
     if (reg->deriv_weight != 0.0f && (reg->deriv_order < 1 || reg->deriv_order > 3))

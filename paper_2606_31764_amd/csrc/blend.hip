@@ -44,6 +44,38 @@ __device__ inline void pixel_of(int quad, int lane, int q, int* lx, int* ly) {
   *ly = (quad >> 1) * Cfg::SUB + (lane >> 3) * Cfg::BLK + q / Cfg::BLK;
 }
 
+// The adjoint's pixel blocks (adj_blocks): the forward's quadrants, or at
+// 32 x 32 tiles with the fill-run walk compiled in, sixteen 8 x 8 blocks with
+// one pixel per lane.  Block b sits at column b % COLS, row b / COLS of the
+// tile; lane l owns the BLK x BLK pixels at column l & 7, row l >> 3 of it.
+template <int TILE, int KIND>
+struct AdjCfg {
+  static constexpr bool SPLIT = TILE == 32 && (KIND & KIND_FILL) != 0;
+  static constexpr int QUADS = SPLIT ? 16 : TileCfg<TILE>::QUADS;
+  static constexpr int SUB = SPLIT ? 8 : TileCfg<TILE>::SUB;
+  static constexpr int BLK = SUB / 8;
+  static constexpr int PPT = BLK * BLK;
+  static constexpr int COLS = TILE / SUB;
+  static_assert(QUADS == adj_blocks(TILE, (KIND & KIND_FILL) != 0), "adjoint blocks follow the binning's items");
+};
+
+template <class A>
+__device__ inline void adj_pixel(int blk, int lane, int q, int* lx, int* ly) {
+  *lx = (blk % A::COLS) * A::SUB + (lane & 7) * A::BLK + q % A::BLK;
+  *ly = (blk / A::COLS) * A::SUB + (lane >> 3) * A::BLK + q / A::BLK;
+}
+
+// Slot of tile pixel (lx, ly) in a stored forward state: the forward's
+// (quadrant x pixels per lane + pixel) x 64 + lane, as pixel_of lays it out.
+template <int TILE>
+__device__ inline int fwd_slot(int lx, int ly) {
+  using F = TileCfg<TILE>;
+  const int quad = lx / F::SUB + 2 * (ly / F::SUB);
+  const int lane = (lx % F::SUB) / F::BLK + 8 * ((ly % F::SUB) / F::BLK);
+  const int q = lx % F::BLK + F::BLK * (ly % F::BLK);
+  return (quad * F::PPT + q) * 64 + lane;
+}
+
 // Next work item of this wavefront: the static assignment, or the next entry
 // of the device work queue (persistent form).
 __device__ inline int next_item(int it, int persistent, int32_t* queue) {
@@ -90,22 +122,26 @@ struct Box {
 // the BLK x BLK block at column l & 7, row l >> 3 of the quadrant): rows from
 // the lowest and highest set bits, columns from the eight row bytes folded
 // together.  Scalar work on a wavefront-uniform mask; `live` != 0.
-template <int TILE>
-__device__ inline Box live_box(int quad, uint64_t live) {
-  using Cfg = TileCfg<TILE>;
+template <class Cfg>
+__device__ inline Box live_box_of(int qx, int qy, uint64_t live) {
   const int r0 = __builtin_ctzll(live) >> 3, r1 = (63 - __builtin_clzll(live)) >> 3;
   uint64_t f = live | (live >> 32);
   f |= f >> 16;
   f |= f >> 8;
   const uint32_t cols = (uint32_t)f & 0xffu;
   const int c0 = __builtin_ctz(cols), c1 = 31 - __builtin_clz(cols);
-  const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
   Box b;
   b.x0 = (float)(qx + c0 * Cfg::BLK);
   b.x1 = (float)(qx + c1 * Cfg::BLK + Cfg::BLK - 1);
   b.y0 = (float)(qy + r0 * Cfg::BLK);
   b.y1 = (float)(qy + r1 * Cfg::BLK + Cfg::BLK - 1);
   return b;
+}
+
+template <int TILE>
+__device__ inline Box live_box(int quad, uint64_t live) {
+  using Cfg = TileCfg<TILE>;
+  return live_box_of<Cfg>((quad & 1) * Cfg::SUB, (quad >> 1) * Cfg::SUB, live);
 }
 
 // All pixel centres of the quadrant.
@@ -917,7 +953,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
     const int32_t* __restrict__ plan, int64_t gcap, int persistent, int ck_arg) {
-  using Cfg = TileCfg<TILE>;
+  using Cfg = AdjCfg<TILE, KIND>;
   constexpr int PPT = Cfg::PPT;
   constexpr int FLUSH = 32;
   extern __shared__ __align__(16) char smem[];
@@ -959,6 +995,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     }
     const int r_it = item - item_off[tq];
     const int quad = r_it % Cfg::QUADS, kc = r_it / Cfg::QUADS;
+    const int qx = (quad % Cfg::COLS) * Cfg::SUB, qy = (quad / Cfg::COLS) * Cfg::SUB;  // the block's first pixel
     const int tile = w.order[tq];
     const int s = scene_of_tile(w.scenes, n_scenes, tile);
     const SceneTab st = w.scenes[s];
@@ -976,7 +1013,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       int lx, ly;
-      pixel_of<TILE>(quad, lane, q, &lx, &ly);
+      adj_pixel<Cfg>(quad, lane, q, &lx, &ly);
       px[q] = (float)lx;
       py[q] = (float)ly;
       T[q] = 1.0f;
@@ -991,7 +1028,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         // a pixel still live behind this chunk starts from the stored state,
         // one that stopped inside it from T_final with only the background
         // behind it (no chunk is stored after a pixel's stop is passed)
-        const int slot = (quad * PPT + q) * 64 + lane;
+        const int slot = Cfg::SPLIT ? fwd_slot<TILE>(lx, ly) : (quad * PPT + q) * 64 + lane;
         float behind[3] = {0.0f, 0.0f, 0.0f};
         T[q] = tf;
         if (stop[q] < c_lo) {  // then c_lo > start, so a chunk follows and ckn is set
@@ -1039,10 +1076,10 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     // walk), with the per-pixel arithmetic of the entry-by-entry path; each
     // Gaussian's dL/do_j is summed over the lanes in LDS and added with one
     // atomic.
-    constexpr int BNB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the quadrant, per axis
+    constexpr int BNB = Cfg::SUB + 2 * FR_R;  // lattice neighbourhood of the pixel block, per axis
     constexpr int BNIT = (BNB * BNB + 63) / 64;
     auto fill_run_bwd = [&](const FillRun& fr, int p0, int p1, const float (&og)[BNIT]) {
-      // (one pixel per lane: lane (l & 7, l >> 3) of the quadrant's 8 x 8
+      // (one pixel per lane: lane (l & 7, l >> 3) of the 8 x 8 pixel
       // block; fill_lattice is false otherwise)
       constexpr int NB = BNB;                  // 16 cells per axis
       constexpr int NS = FR_NS;                // LDS row stride (conflict-free rows)
@@ -1066,7 +1103,6 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
         cur_aniso = false;
         since = 0;
       }
-      const int qx = (quad & 1) * Cfg::SUB, qy = (quad >> 1) * Cfg::SUB;
       const int ib = x0 + qx - fr.ix0 - FR_R, jb = y0 + qy - fr.iy0 - FR_R;  // window index of cell (0, 0)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1182,7 +1218,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
                         sg, s_lo, start, end, 1.0, ks, inv_tile, st, lt, TILE, &fr)) {
           // the opacities and the corner check in flight together
           p1 = min(fr.p_hi, c_hi - 1);
-          const int ib = x0 + (quad & 1) * Cfg::SUB - fr.ix0 - FR_R, jb = y0 + (quad >> 1) * Cfg::SUB - fr.iy0 - FR_R;
+          const int ib = x0 + qx - fr.ix0 - FR_R, jb = y0 + qy - fr.iy0 - FR_R;
           fill_gather<BNB, BNIT>(w.gop, gcap, fr, ib, jb, s_lo, p1, __builtin_nanf(""), og);
           take = fill_corners_ok(idx, fr);
         }
@@ -1206,7 +1242,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       bool lv = false, step_aniso = false;
 #pragma unroll
       for (int q = 0; q < PPT; ++q) lv = lv || (stop[q] < s_hi);
-      const Box box = live_box<TILE>(quad, __ballot(lv));
+      const Box box = live_box_of<Cfg>(qx, qy, __ballot(lv));
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int k = u * 64 + lane;
@@ -1506,7 +1542,7 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
   const int64_t max_items =
-      (int64_t)TileCfg<TILE>::QUADS * ((L.bf->caps.pairs >> (L.ck_lg >= 0 ? L.ck_lg : 9)) + L.n_tiles);
+      (int64_t)AdjCfg<TILE, KIND>::QUADS * ((L.bf->caps.pairs >> (L.ck_lg >= 0 ? L.ck_lg : 9)) + L.n_tiles);
   const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E, KIND);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {

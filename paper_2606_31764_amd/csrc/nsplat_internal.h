@@ -93,6 +93,13 @@ __host__ __device__ inline int auto_chunk_log2(int64_t pairs, int quads, int n_c
   while (lg < 12 && v >= 1.4142135623730951 * (double)(1 << lg)) ++lg;
   return lg;
 }
+// Adjoint work items per chunk of a tile list: the forward's quadrants (one
+// at 8 x 8 tiles, four above), except at 32 x 32 tiles of batches with fills,
+// where the adjoint takes each tile as sixteen 8 x 8 pixel blocks with one
+// pixel per lane (its fill-run walk is written for one pixel per lane).
+__host__ __device__ constexpr int adj_blocks(int tile, bool fills) {
+  return tile == 8 ? 1 : (tile == 32 && fills ? 16 : 4);
+}
 
 // Boundary segments per bounding box in the fill SDF.  Curve c (first
 // boundary point boff) has a header at cbox_base(boff, c) holding the box
@@ -416,6 +423,8 @@ struct Launch {
   int n_cu;
   int ck_lg;  // log2 of params.chunk, or -1: chosen by the binning (Q_CKLG)
 };
+// the adjoint's pixel blocks per chunk for this launch's tile side and curves
+inline int adj_blocks_of(const Launch& L) { return adj_blocks(L.pr->tile, (L.cv->any_flags & NSPLAT_FILLED) != 0); }
 
 // Scene table; also clears the NSPLAT_NUM_COUNTERS counters when given.
 hipError_t launch_scene_setup(const Launch& L, int32_t* clear_counters);

@@ -115,3 +115,31 @@ def test_backward_across_chunks(name, tile):
     lens = out["ranges"][:, 1] - out["ranges"][:, 0]
     print(name, tile, "longest list", int(lens.max()), "grad worst ratio", worst, flush=True)
     assert lens.max() > 2 * 512
+
+
+def _tile32_case(name):
+    if name == "behind_fills_h1":  # strokes behind opaque fills, fill runs walked at h = 1
+        from test_gpu_grad_components import behind_fills
+        b, p = behind_fills(7102), Params().replace(delta_c=2.0, h=1.0)
+    elif name == "c3s_dense_h1":
+        b, p = synth.config3(seed=3300, n_paths=10, size=64), Params().replace(h=1.0)
+    else:
+        b, p = CASES[name]
+        return b, p, _target(name)
+    return b, p, oracle.render(synth.perturbed(b, seed=97), oracle_params(p))[0]
+
+
+@pytest.mark.parametrize("name", ["c3s_h1", "c3s_h2", "c3s_dense_h1", "behind_fills_h1"])
+def test_backward_tile32_fill_blocks(name):
+    """At 32 x 32 tiles a batch with fills takes its adjoint in sixteen 8 x 8
+    pixel blocks per tile (fill runs pixel by pixel at h = 1, entry by entry
+    otherwise and for strokes), starting from the forward's stored state laid
+    out by its 16 x 16 quadrants: image and every gradient component against
+    the oracle, lists spanning several chunks in the dense case."""
+    b, p, target = _tile32_case(name)
+    p = p.replace(tile=32)
+    out, worst, rep = gpu_vs_oracle(b, p, target)
+    lens = out["ranges"][:, 1] - out["ranges"][:, 0]
+    print(name, "longest list", int(lens.max()), "grad worst ratio", worst, rep, flush=True)
+    if name == "c3s_dense_h1":
+        assert lens.max() > 2 * 512
