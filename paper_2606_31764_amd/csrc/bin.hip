@@ -594,16 +594,35 @@ __global__ void k_chunk_counts(const int32_t* __restrict__ ranges, int n_tiles, 
   }
 }
 
+// Marks the scenes that hold a filled curve (SceneTab.fills), which the
+// adjoint takes in 8 x 8 pixel blocks at 32 x 32 tiles.  One block.
+__global__ void k_scene_fills(nsplat_curves cv, SceneTab* st, int n_scenes) {
+  for (int s = threadIdx.x; s < n_scenes; s += blockDim.x) st[s].fills = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < cv.n_curves; c += blockDim.x) {
+    const int s = cv.scene[c];
+    if ((cv.flags[c] & NSPLAT_FILLED) && s >= 0 && s < n_scenes) st[s].fills = 1;
+  }
+}
+
+// Adjoint pixel blocks per chunk of tile t: `blocks` (adj_blocks), where 16
+// stands for 16 on the tiles of scenes with fills and 4 on the others.
+__device__ inline int tile_blocks(int blocks, const SceneTab* st, int n_scenes, int t) {
+  if (blocks != 16) return blocks;
+  return st[scene_of_tile(st, n_scenes, t)].fills ? 16 : 4;
+}
+
 // Adjoint work items of the tile at blend-order position i: quadrants x chunks.
 // (quads, the forward's quadrants per tile, feeds the chunk rule; blocks is
-// the adjoint's pixel blocks per chunk, adj_blocks)
+// the adjoint's pixel blocks per chunk, see tile_blocks)
 __global__ void k_item_counts(const int32_t* __restrict__ ranges, const int32_t* __restrict__ order, int n_tiles,
-                              int quads, int blocks, int ck_arg, const int32_t* counters, int n_cu,
-                              uint32_t* __restrict__ items) {
+                              int quads, int blocks, const SceneTab* st, int n_scenes, int ck_arg,
+                              const int32_t* counters, int n_cu, uint32_t* __restrict__ items) {
   const int ck_lg = launch_chunk_log2(ck_arg, counters, quads, n_cu);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += gridDim.x * blockDim.x) {
     const int t = order[i];
-    items[i] = (uint32_t)(blocks * n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg));
+    const int nb = tile_blocks(blocks, st, n_scenes, t);
+    items[i] = (uint32_t)(nb * n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg));
   }
 }
 
@@ -630,7 +649,8 @@ __device__ inline uint32_t plan_wave_scan(uint32_t v) {
 // its slice starts at the digit's first offset and ends where digit t + 1
 // starts (or at the pair count); empty tiles get [0, 0).
 __global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict__ ranges, int n_tiles, int quads,
-                                                            int blocks, int ck_arg, int n_cu, int32_t* __restrict__ queue,
+                                                            int blocks, const SceneTab* st, int n_scenes,
+                                                            int ck_arg, int n_cu, int32_t* __restrict__ queue,
                                                             int32_t* __restrict__ order, int32_t* __restrict__ ck_off,
                                                             int32_t* __restrict__ item_off,
                                                             const uint32_t* __restrict__ hist, int sb, int nd,
@@ -688,7 +708,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_tile_plan(int32_t* __restrict_
         const int n = n_chunks(ranges[2 * i + 1] - ranges[2 * i], ck_lg);
         ck = n > 0 ? (uint32_t)(n - 1) : 0u;
         const int t = order[i];
-        it = (uint32_t)(blocks * n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg));
+        const int nb = tile_blocks(blocks, st, n_scenes, t);
+        it = (uint32_t)(nb * n_chunks(ranges[2 * t + 1] - ranges[2 * t], ck_lg));
       }
       v[0][j] = ck;
       v[1][j] = it;
@@ -752,6 +773,8 @@ hipError_t launch_bin(const Launch& L) {
   // with large tile rectangles (wide strokes, tangent-aligned ones) keep the
   // emission and radix passes, which spread their pairs over more wavefronts.
   const bool fused = passes >= 1 && gcap >= 65536 && pcap <= 8 * gcap;
+  if (adj_blocks_of(L) == 16)
+    hipLaunchKernelGGL(k_scene_fills, dim3(1), dim3(256), 0, L.stream, *L.cv, L.w.scenes, (int)L.sc->n_scenes);
   if (fused) {
     // the low digit at once: count per block and digit, scan, place the
     // pairs (k_bin_tilehist); the other digits, if any, by radix passes
@@ -775,7 +798,8 @@ hipError_t launch_bin(const Launch& L) {
     if (one) {
       Phase ph(L, NSPLAT_T_RANGES);
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, (int)L.n_tiles,
-                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
+                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.w.scenes, (int)L.sc->n_scenes, L.ck_lg,
+                         L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
                          (const uint32_t*)L.w.hist, nbk, nd, cnt, 1);
       return hipGetLastError();
     }
@@ -824,7 +848,8 @@ hipError_t launch_bin(const Launch& L) {
                          L.bf->ranges);
     if (nt > 0 && nt <= SMALL_TILES) {
       hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(PLAN_THREADS), 0, L.stream, L.bf->ranges, nt,
-                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.ck_lg, L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
+                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.w.scenes, (int)L.sc->n_scenes, L.ck_lg,
+                         L.n_cu, L.w.queue, L.w.order, L.w.ck_off, L.w.item_off,
                          from_hist ? (const uint32_t*)L.w.hist : nullptr, sb, 1 << key_bits, cnt, 0);
     } else if (nt > 0) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, L.stream, L.w.obin, 0, (int64_t)64);
@@ -837,7 +862,8 @@ hipError_t launch_bin(const Launch& L) {
       e = launch_scan((uint32_t*)L.w.ck_off, nullptr, nt, (uint32_t*)L.w.ck_off + nt, L.w.scan_tmp, L.stream);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_item_counts, dim3(cb), dim3(256), 0, L.stream, L.bf->ranges, L.w.order, nt,
-                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.ck_lg, cnt, L.n_cu, (uint32_t*)L.w.item_off);
+                         L.pr->tile == 8 ? 1 : 4, adj_blocks_of(L), L.w.scenes, (int)L.sc->n_scenes, L.ck_lg,
+                         cnt, L.n_cu, (uint32_t*)L.w.item_off);
       e = launch_scan((uint32_t*)L.w.item_off, nullptr, nt, (uint32_t*)L.w.item_off + nt, L.w.scan_tmp, L.stream);
       if (e != hipSuccess) return e;
     } else {

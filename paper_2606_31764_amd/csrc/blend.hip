@@ -44,19 +44,20 @@ __device__ inline void pixel_of(int quad, int lane, int q, int* lx, int* ly) {
   *ly = (quad >> 1) * Cfg::SUB + (lane >> 3) * Cfg::BLK + q / Cfg::BLK;
 }
 
-// The adjoint's pixel blocks (adj_blocks): the forward's quadrants, or at
-// 32 x 32 tiles with the fill-run walk compiled in, sixteen 8 x 8 blocks with
+// The adjoint's pixel blocks (adj_blocks): the forward's quadrants, or, for
+// the tiles of scenes with fills at 32 x 32 tiles, sixteen 8 x 8 blocks with
 // one pixel per lane.  Block b sits at column b % COLS, row b / COLS of the
 // tile; lane l owns the BLK x BLK pixels at column l & 7, row l >> 3 of it.
-template <int TILE, int KIND>
+template <int TILE, bool SPLIT_>
 struct AdjCfg {
-  static constexpr bool SPLIT = TILE == 32 && (KIND & KIND_FILL) != 0;
+  static constexpr bool SPLIT = SPLIT_;
   static constexpr int QUADS = SPLIT ? 16 : TileCfg<TILE>::QUADS;
   static constexpr int SUB = SPLIT ? 8 : TileCfg<TILE>::SUB;
   static constexpr int BLK = SUB / 8;
   static constexpr int PPT = BLK * BLK;
   static constexpr int COLS = TILE / SUB;
-  static_assert(QUADS == adj_blocks(TILE, (KIND & KIND_FILL) != 0), "adjoint blocks follow the binning's items");
+  static_assert(!SPLIT || TILE == 32, "8 x 8 blocks split 32 x 32 tiles only");
+  static_assert(QUADS == adj_blocks(TILE, SPLIT), "adjoint blocks follow the binning's items");
 };
 
 template <class A>
@@ -953,8 +954,10 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     const int32_t* __restrict__ ranges, const int32_t* __restrict__ idx, const float* __restrict__ bg,
     const float* __restrict__ dL, const float* __restrict__ Tfin, const int32_t* __restrict__ nlast,
     const int32_t* __restrict__ plan, int64_t gcap, int persistent, int ck_arg) {
-  using Cfg = AdjCfg<TILE, KIND>;
-  constexpr int PPT = Cfg::PPT;
+  // both block forms in one kernel where a launch can hold both (32 x 32
+  // tiles with fills): scenes with fills in 8 x 8 blocks, the others in
+  // quadrants
+  constexpr bool DUAL = TILE == 32 && (KIND & KIND_FILL) != 0;
   constexpr int FLUSH = 32;
   extern __shared__ __align__(16) char smem[];
   typedef const __attribute__((address_space(4))) int32_t* const_i32;
@@ -963,8 +966,8 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
   const float amax = pr.alpha_max, ks = pr.k_sigma;
   const float ln2 = (float)LN2;
   constexpr bool ANI = (KIND & KIND_ANI) != 0;
-  // fill runs pixel by pixel (see FillRun), with one pixel per lane
-  const bool fill_lattice = (KIND & KIND_FILL) != 0 && PPT == 1 && read_h(pr) == 1.0f;
+  // fill runs pixel by pixel (see FillRun), in blocks of one pixel per lane
+  const bool fill_h1 = (KIND & KIND_FILL) != 0 && read_h(pr) == 1.0f;
   const float inv_tile = 1.0f / (float)TILE;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   constexpr int RB = park_rows(TILE, E, KIND);
@@ -994,11 +997,15 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       tq = lo_t;
     }
     const int r_it = item - item_off[tq];
-    const int quad = r_it % Cfg::QUADS, kc = r_it / Cfg::QUADS;
-    const int qx = (quad % Cfg::COLS) * Cfg::SUB, qy = (quad / Cfg::COLS) * Cfg::SUB;  // the block's first pixel
     const int tile = w.order[tq];
     const int s = scene_of_tile(w.scenes, n_scenes, tile);
     const SceneTab st = w.scenes[s];
+    auto item_body = [&](auto cfg) {
+    using Cfg = decltype(cfg);
+    constexpr int PPT = Cfg::PPT;
+    const bool fill_lattice = fill_h1 && PPT == 1;
+    const int quad = r_it % Cfg::QUADS, kc = r_it / Cfg::QUADS;
+    const int qx = (quad % Cfg::COLS) * Cfg::SUB, qy = (quad / Cfg::COLS) * Cfg::SUB;  // the block's first pixel
     const int lt = tile - st.tile_off;
     const int x0 = (lt % st.tiles_x) * TILE, y0 = (lt / st.tiles_x) * TILE;
     const int start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -1049,7 +1056,7 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
     }
     // positions below every pixel's stopping position take no part
     const int lo = max(wave_min(my_lo), c_lo);
-    if (c_hi <= lo) continue;
+    if (c_hi <= lo) return;
     int cur = -1, since = 0;
     bool cur_fill = false, cur_aniso = false;
     // per pixel: K of the current curve, W (fixed over a run of one curve),
@@ -1501,6 +1508,13 @@ __global__ __launch_bounds__(BLOCK, bwd_waves(TILE, E, KIND)) void k_blend_bwd(
       n_rows = 0;
     }
     if (cur >= 0) flush_curve<C, PPT>(w.gcurve, cur, cur_fill, gI, aT, accO);
+    };
+    if constexpr (DUAL) {
+      if (st.fills) item_body(AdjCfg<TILE, true>{});
+      else item_body(AdjCfg<TILE, false>{});
+    } else {
+      item_body(AdjCfg<TILE, false>{});
+    }
   }
 }
 
@@ -1542,7 +1556,8 @@ hipError_t bwd_t(const Launch& L, const float* dL, const float* T_final, const i
   // the item count lives on the device; the grid covers its bound
   // sum over tiles of QUADS * ceil(len / CK) <= QUADS * (pairs / CK + tiles)
   const int64_t max_items =
-      (int64_t)AdjCfg<TILE, KIND>::QUADS * ((L.bf->caps.pairs >> (L.ck_lg >= 0 ? L.ck_lg : 9)) + L.n_tiles);
+      (int64_t)adj_blocks(TILE, (KIND & KIND_FILL) != 0) * ((L.bf->caps.pairs >> (L.ck_lg >= 0 ? L.ck_lg : 9)) +
+                                                             L.n_tiles);
   const size_t lds = (size_t)WPB * bwd_wave_bytes(TILE, E, KIND);
   int grid = (int)((max_items + WPB - 1) / WPB);
   if (persistent) {

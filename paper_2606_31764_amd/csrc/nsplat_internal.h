@@ -34,7 +34,8 @@ struct __align__(16) Gauss {
 static_assert(sizeof(Gauss) == 32, "Gaussian record must be 32 bytes");
 
 struct SceneTab {
-  int32_t H, W, tiles_x, tiles_y, tile_off, pix_off, n_L, pad;
+  int32_t H, W, tiles_x, tiles_y, tile_off, pix_off, n_L;
+  int32_t fills;  // 1: a curve of the scene is filled (set by nsplat_bin at 32 x 32 tiles, see adj_blocks)
 };
 
 enum { P_COUNT = 0, P_NSAMP, P_IX0, P_IY0, P_NX, P_NY, P_GOFF, P_BOFF, P_FLAGS, P_STRIDE };
@@ -94,9 +95,9 @@ __host__ __device__ inline int auto_chunk_log2(int64_t pairs, int quads, int n_c
   return lg;
 }
 // Adjoint work items per chunk of a tile list: the forward's quadrants (one
-// at 8 x 8 tiles, four above), except at 32 x 32 tiles of batches with fills,
-// where the adjoint takes each tile as sixteen 8 x 8 pixel blocks with one
-// pixel per lane (its fill-run walk is written for one pixel per lane).
+// at 8 x 8 tiles, four above), except for the tiles of scenes with fills at
+// 32 x 32 tiles, which the adjoint takes as sixteen 8 x 8 pixel blocks with
+// one pixel per lane (its fill-run walk is written for one pixel per lane).
 __host__ __device__ constexpr int adj_blocks(int tile, bool fills) {
   return tile == 8 ? 1 : (tile == 32 && fills ? 16 : 4);
 }

@@ -37,7 +37,7 @@ __global__ void k_scene_setup(nsplat_scenes sc, nsplat_params pr, SceneTab* st, 
     t.tile_off = toff;
     t.pix_off = poff;
     t.n_L = (int32_t)llrint((double)pr.nl_factor * (double)(t.H > t.W ? t.H : t.W));
-    t.pad = 0;
+    t.fills = 0;
     st[s] = t;
     toff += t.tiles_x * t.tiles_y;
     poff += t.H * t.W;
