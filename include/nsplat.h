@@ -194,7 +194,8 @@ typedef struct {
   int32_t chunk;    /* list positions per chunk of the adjoint's split of each
                        tile list (the forward stores every pixel's state at
                        chunk boundaries; the adjoint runs one work item per
-                       tile quadrant and chunk): a power of two in
+                       tile quadrant, or 8 x 8 block, and chunk): a power
+                       of two in
                        [512, 8192], or 0: 512 for a batch without fills,
                        else chosen by nsplat_bin on the device from the pair
                        count (about pairs x quadrants per tile / (8 x compute
@@ -285,7 +286,8 @@ int nsplat_bin(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes
  * k_sigma sigma, colour += c alpha T, T *= 1 - alpha, stop once T < eps_T;
  * image = colour + T bg.  Uses the tile lists and scene table built by the
  * last nsplat_bin on these buffers; NSPLAT_EINVAL if that call (on this
- * context) used another params.tile (the same holds for nsplat_backward).  image is per scene [channels][H][W], concatenated
+ * context) used another params.tile or params.chunk (the same holds for
+ * nsplat_backward).  image is per scene [channels][H][W], concatenated
  * over scenes; T_final and n_last are per scene [H][W]: the final
  * transmittance and the idx position where the pixel stopped.
  * persistent != 0 runs one resident grid that pulls tiles from a device work
@@ -296,15 +298,19 @@ int nsplat_forward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_sc
 
 /* Adjoint of nsplat_forward o nsplat_bin o nsplat_sample for the upstream
  * gradient dL_dimage (layout of image).  Must follow the nsplat_forward of
- * the same buffers: it starts each chunk of 512 list positions from the
- * per-pixel state that forward stored in the workspace at the chunk's front
- * boundary (and uses the final accumulated colour it stored), walks the
- * chunk front to back down to n_last, and
+ * the same buffers: it starts each chunk of a tile list (the chunk length
+ * nsplat_bin chose) from the per-pixel state that forward stored in the
+ * workspace at the chunk's back boundary, walks the chunk back to front
+ * (from n_last where a pixel stopped inside it), and
  * chains through the Gaussians into the Cox-de Boor basis (control points,
  * weights, widths, knots -> intervals), the SDF (nearest segment, detached
  * sign), the sample parameters u_j (which depend on the domain ends) and the
  * key-point / interval parametrisation.  Counts, windows and span choices are
- * held fixed (piecewise constant).  All gradients are overwritten. */
+ * held fixed (piecewise constant).  All gradients are overwritten.
+ * NSPLAT_EINVAL also when, at 32 x 32 tiles, the last nsplat_bin on these
+ * buffers saw curves that differ from these in whether any is NSPLAT_FILLED:
+ * it laid out the adjoint's work items per 8 x 8 pixel block for the tiles
+ * of scenes with fills and per quadrant for the others. */
 int nsplat_backward(nsplat_ctx* ctx, const nsplat_curves* curves, const nsplat_scenes* scenes,
                     const nsplat_params* params, const nsplat_buffers* bufs, const float* dL_dimage,
                     const float* T_final, const int32_t* n_last, const nsplat_grads* grads,

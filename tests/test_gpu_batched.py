@@ -87,9 +87,13 @@ def test_batched_matches_per_scene_plain(persistent):
         tile_off += nt
 
 
-def test_batched_against_oracle():
+@pytest.mark.parametrize("tile,h", [(16, 2.0), (32, 1.0)])
+def test_batched_against_oracle(tile, h):
+    """Mixed batch against the oracle; at 32 x 32 tiles and h = 1 the adjoint
+    takes the fill scenes' tiles in 8 x 8 blocks (fill runs walked) and the
+    other scenes' tiles in quadrants, in one launch."""
     b = synth.concat(_mixed(7100))
-    p = Params().replace(delta_c=2.0, h=2.0)
+    p = Params().replace(delta_c=2.0, h=h, tile=tile)
     op = oracle_params(p)
     target = oracle.render(synth.perturbed(b, seed=4), op)[0]
     from helpers import gpu_vs_oracle
