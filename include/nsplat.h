@@ -199,7 +199,7 @@ typedef struct {
                        [512, 8192], or 0: 512 for a batch without fills,
                        else chosen by nsplat_bin on the device from the pair
                        count (about pairs x quadrants per tile / (8 x compute
-                       units), rounded to a power of two in [512, 4096]).
+                       units), rounded to a power of two in [512, 8192]).
                        It only changes FP32 rounding.                        */
   const float* h_dev; /* (dev, optional) if non-NULL the grid step is read
                          from here, so a captured graph can anneal it        */

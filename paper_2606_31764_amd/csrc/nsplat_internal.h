@@ -86,12 +86,13 @@ constexpr int CK_MIN = 512, CK_MAX = 8192;
 __host__ __device__ inline int n_chunks(int len, int ck_lg) { return (len + (1 << ck_lg) - 1) >> ck_lg; }
 // About one adjoint item per two wavefront slots of the GPU: pairs x
 // quadrants / (8 x compute units) positions per chunk, rounded to a power of
-// two in [512, 4096].  Large launches keep whole lists together (fewer stored
-// states and item set-ups); small ones split long lists across wavefronts.
+// two in [CK_MIN, CK_MAX].  Large launches keep whole lists together (fewer
+// stored states and item set-ups); small ones split long lists across
+// wavefronts.
 __host__ __device__ inline int auto_chunk_log2(int64_t pairs, int quads, int n_cu) {
   const double v = (double)pairs * quads / (8.0 * (n_cu > 0 ? n_cu : 1));
   int lg = 9;
-  while (lg < 12 && v >= 1.4142135623730951 * (double)(1 << lg)) ++lg;
+  while ((1 << lg) < CK_MAX && v >= 1.4142135623730951 * (double)(1 << lg)) ++lg;
   return lg;
 }
 // Adjoint work items per chunk of a tile list: the forward's quadrants (one

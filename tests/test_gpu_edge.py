@@ -502,6 +502,29 @@ def test_forward_and_backward_refuse_another_tile_than_bin():
     torch.cuda.synchronize()
 
 
+def test_backward_refuses_items_of_another_fill_split():
+    """At 32 x 32 tiles nsplat_bin lays out the adjoint items of scenes with
+    fills per 8 x 8 block; a backward whose curves differ in NSPLAT_FILLED
+    (so it would read them per quadrant) is an argument error."""
+    import torch
+    from paper_2606_31764_amd import _lib as L
+    from paper_2606_31764_amd.render import Renderer, param_tensors
+    b = synth.config3(seed=3960, n_paths=4, size=64)
+    p = Params().replace(h=1.0, tile=32)
+    r = Renderer(b, p)
+    t = param_tensors(b)
+    r.run_forward(t)
+    dL = torch.ones_like(r.image)
+    m = r.meta
+    declared = (m.any_flags, m.all_flags)
+    m.any_flags, m.all_flags = declared[0] & ~synth.FILLED, declared[1] & ~synth.FILLED
+    with pytest.raises(L.NSplatError, match="pixel blocks"):
+        r.backward(t, dL)
+    m.any_flags, m.all_flags = declared
+    r.backward(t, dL)  # consistent again
+    torch.cuda.synchronize()
+
+
 def test_declared_flag_intersection():
     """nsplat_curves.all_flags declares flags every curve carries: with
     NSPLAT_FILLED declared the stroke adjoint is not launched and a stroke
