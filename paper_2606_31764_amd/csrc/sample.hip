@@ -681,9 +681,115 @@ __device__ inline float4 curve_colour(const nsplat_curves& cv, int c, float tag)
   return make_float4(col[0], cv.channels == 3 ? col[1] : 0.0f, cv.channels == 3 ? col[2] : 0.0f, tag);
 }
 
+// Stroke samples of a wavefront whose 64 lanes all lie on one curve: the
+// wavefront finds the span window of its samples with a 64-ary search (one
+// knot per lane per round, so two rounds cover 4096 knots instead of a
+// binary search of a dozen dependent loads per lane), stages the window's
+// knots and control points in LDS, and each lane finds its span and
+// evaluates its sample there.  WIN spans at most per window.
+constexpr int WIN = 64;
+struct StrokeStage {
+  double U[WIN + 2 * MAXP];   // knots s_lo - p + 1 .. s_hi + p
+  float cp[WIN + MAXP][4];    // control points s_lo - p .. s_hi: x, y, w, width
+};
+
+// find_span for a wavefront-uniform x (the largest i in [p, m-p-1] with
+// U[i] <= x, the right-end and left-end rules as find_span's).
+__device__ inline int span_uniform(const double* U, int p, int m, double x) {
+  const int lo = p, hi = m - p - 1;
+  if (x >= U[hi + 1] || !(U[lo] <= x)) return find_span(U, p, m, x);
+  const int lane = __lane_id();
+  int a = lo, n = hi - lo + 1;  // U[a] <= x; the answer lies in [a, a + n)
+  while (n > 1) {
+    const int step = (n + 63) >> 6;
+    const int idx = a + lane * step;
+    const bool ok = idx < a + n && U[idx] <= x;  // a prefix of the lanes (U ascending), lane 0 always
+    const int k = 63 - __builtin_clzll(__ballot(ok));
+    const int end = a + n;
+    a += k * step;
+    n = min(step, end - a);
+  }
+  return a;
+}
+
+// Sample point (and derivative) of this lane's u; false (nothing computed)
+// when the wavefront's samples span more than WIN knot spans.  The result is
+// curve_point at find_span(u): the span is the largest in [s_lo, s_hi] with
+// U[span] <= u (s_lo, s_hi the spans of the wavefront's lowest and highest u,
+// find_span being monotone), and the arithmetic is curve_point's.
+__device__ bool stroke_point_wave(const nsplat_curves& cv, const CurveView& v, double u, StrokeStage* st,
+                                  double (&pt)[3], double* d) {
+  double umin = u, umax = u;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    umin = fmin(umin, __shfl_xor(umin, off));
+    umax = fmax(umax, __shfl_xor(umax, off));
+  }
+  const int s_lo = __builtin_amdgcn_readfirstlane(span_uniform(v.U, v.p, v.m, umin));
+  const int s_hi = __builtin_amdgcn_readfirstlane(span_uniform(v.U, v.p, v.m, umax));
+  const int W = s_hi - s_lo + 1;
+  if (W > WIN) return false;
+  const int p = v.p, lane = __lane_id();
+  const int kb = s_lo - p + 1, cb = s_lo - p;  // first staged knot and control point
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int t = lane; t < W + 2 * p; t += 64) st->U[t] = v.U[kb + t];
+  for (int t = lane; t < W + p; t += 64) {
+    const int k = v.k0 + v.key_of_cp(cb + t);
+    st->cp[t][0] = cv.key_xy[2 * k];
+    st->cp[t][1] = cv.key_xy[2 * k + 1];
+    st->cp[t][2] = cv.key_w[k];
+    st->cp[t][3] = cv.key_s[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // the lane's span, relative to the first staged knot (span s sits at s - kb)
+  int a = s_lo - kb, b = s_hi - kb;  // U[a] <= u unless u is left of the domain
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (st->U[mid] <= u) a = mid;
+    else b = mid - 1;
+  }
+  const int span = a;  // in the staged knots' numbering
+  double N[MAXP + 1], dN[MAXP + 1];
+  basis_funs(st->U, span, p, u, N, d ? dN : nullptr);
+  double S[3] = {0.0, 0.0, 0.0}, Sd[3] = {0.0, 0.0, 0.0}, Wt = 0.0, Wd = 0.0;
+#pragma unroll
+  for (int r = 0; r <= MAXP; ++r) {
+    if (r > p) break;
+    const float* c = st->cp[span + kb - p + r - cb];
+    const double w = (double)c[2];
+    const double P[3] = {(double)c[0], (double)c[1], (double)c[3]};
+    const double nw = N[r] * w;
+    Wt += nw;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S[q] += nw * P[q];
+    if (d) {
+      const double dnw = dN[r] * w;
+      Wd += dnw;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Sd[q] += dnw * P[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) pt[q] = S[q] / Wt;
+  if (d) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d[q] = (Wt * Sd[q] - S[q] * Wd) / (Wt * Wt);
+  }
+  return true;
+}
+
 // One lane per Gaussian.  Emission order per curve: open strokes kappa copies
 // of sample 0, samples 0..M-1, kappa copies of sample M-1; closed strokes
-// samples 0..M-1; fills the lattice window row by row.
+// samples 0..M-1; fills the lattice window row by row.  FILLS: the batch
+// declares fills (nsplat_curves.any_flags).  Batches without them take their
+// stroke samples through the wavefront-staged evaluation (stroke_point_wave);
+// with the fill path in the same kernel that evaluation's registers would
+// spill, so batches with fills evaluate every sample on its own.
+template <bool FILLS>
 __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params pr, Work w, const int32_t* plan,
                                               const int32_t* counters, Gauss* __restrict__ out) {
   const int64_t G = counters[NSPLAT_CNT_GAUSS];
@@ -698,14 +804,21 @@ __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params
     r.curve = c;
     r.local = local;
     const double o = (double)cv.opacity[c];
-    if (!v.filled()) {
+    if (!(FILLS && v.filled())) {  // (a batch without fills has no Gaussian of a filled curve)
       const int M = row[P_NSAMP];
       int j = v.closed() ? local : local - pr.kappa;
       j = j < 0 ? 0 : (j > M - 1 ? M - 1 : j);
       const double u = sample_u(v.U[v.p], v.U[v.m - v.p], j, M, v.closed(), nullptr);
       double pt[3], d[3];
       const bool an = v.aniso();
-      curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, an ? d : nullptr);
+      bool staged = false;
+      if constexpr (!FILLS) {
+        __shared__ StrokeStage stage[4];  // one per wavefront of the 256-thread block
+        const int cu = __builtin_amdgcn_readfirstlane(c);
+        staged = __ballot(c != cu) == 0ull && __ballot(true) == ~0ull &&
+                 stroke_point_wave(cv, v, u, &stage[threadIdx.x >> 6], pt, an ? d : nullptr);
+      }
+      if (!staged) curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, an ? d : nullptr);
       r.mx = pt[0];
       r.my = pt[1];
       const double sg = pt[2] / (double)pr.rho;
@@ -1024,8 +1137,12 @@ hipError_t launch_sample(const Launch& L, int frozen) {
                      (int64_t)L.bf->caps.gauss, L.w.queue + Q_NFILL);
   }
   Phase ph(L, NSPLAT_T_EMIT);
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv, *L.pr,
-                     L.w, plan, cnt, (Gauss*)L.bf->gauss);
+  if (L.cv->any_flags & NSPLAT_FILLED)
+    hipLaunchKernelGGL(k_emit<true>, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                       *L.pr, L.w, plan, cnt, (Gauss*)L.bf->gauss);
+  else
+    hipLaunchKernelGGL(k_emit<false>, dim3(grid_for(L.bf->caps.gauss, 256, 8192)), dim3(256), 0, L.stream, *L.cv,
+                       *L.pr, L.w, plan, cnt, (Gauss*)L.bf->gauss);
   return hipGetLastError();
 }
 
