@@ -15,6 +15,7 @@
 #include <mutex>
 
 #include "nsplat_internal.h"
+#include "span_wave.h"
 
 namespace nsp {
 
@@ -693,25 +694,6 @@ struct StrokeStage {
   float cp[WIN + MAXP][4];    // control points s_lo - p .. s_hi: x, y, w, width
 };
 
-// find_span for a wavefront-uniform x (the largest i in [p, m-p-1] with
-// U[i] <= x, the right-end and left-end rules as find_span's).
-__device__ inline int span_uniform(const double* U, int p, int m, double x) {
-  const int lo = p, hi = m - p - 1;
-  if (x >= U[hi + 1] || !(U[lo] <= x)) return find_span(U, p, m, x);
-  const int lane = __lane_id();
-  int a = lo, n = hi - lo + 1;  // U[a] <= x; the answer lies in [a, a + n)
-  while (n > 1) {
-    const int step = (n + 63) >> 6;
-    const int idx = a + lane * step;
-    const bool ok = idx < a + n && U[idx] <= x;  // a prefix of the lanes (U ascending), lane 0 always
-    const int k = 63 - __builtin_clzll(__ballot(ok));
-    const int end = a + n;
-    a += k * step;
-    n = min(step, end - a);
-  }
-  return a;
-}
-
 // Sample point (and derivative) of this lane's u; false (nothing computed)
 // when the wavefront's samples span more than WIN knot spans.  The result is
 // curve_point at find_span(u): the span is the largest in [s_lo, s_hi] with
@@ -818,7 +800,15 @@ __global__ __launch_bounds__(256, 5) void k_emit(nsplat_curves cv, nsplat_params
         staged = __ballot(c != cu) == 0ull && __ballot(true) == ~0ull &&
                  stroke_point_wave(cv, v, u, &stage[threadIdx.x >> 6], pt, an ? d : nullptr);
       }
-      if (!staged) curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, an ? d : nullptr);
+      if constexpr (FILLS) {
+        // the span only: one cooperative search when all 64 lanes sample one curve
+        const int cu = __builtin_amdgcn_readfirstlane(c);
+        const bool uni = __ballot(c != cu) == 0ull && __ballot(true) == ~0ull;
+        curve_point(cv, v, u, uni ? span_wave(v.U, v.p, v.m, u) : find_span(v.U, v.p, v.m, u), pt,
+                    an ? d : nullptr);
+      } else if (!staged) {
+        curve_point(cv, v, u, find_span(v.U, v.p, v.m, u), pt, an ? d : nullptr);
+      }
       r.mx = pt[0];
       r.my = pt[1];
       const double sg = pt[2] / (double)pr.rho;
