@@ -631,3 +631,25 @@ def test_clockwise_fill():
     b2 = _batch([_part(xy_ccw, p=3, closed=True, filled=True, color=(0.9, 0.1, 0.1), o=0.9, seed=7)], hw=(44, 48))
     img2 = gpu_run(b2, Params(h=1.0), backward=False)["image"].reshape(3, 44, 48)
     assert np.all(np.abs(img2[0, 18:27, 20:29] - (0.9 * 0.9 + 0.1 * 1.0)) < 2e-2)
+
+
+@pytest.mark.parametrize("n_cp,delta_c", [(6000, 3.0), (3000, 0.02)])
+def test_stroke_span_search_long_and_sparse(n_cp, delta_c):
+    """Stroke samples of a wavefront on one curve find their knot spans
+    cooperatively: over 6000 key points (three search rounds, more than 4096
+    knots) and, with very sparse sampling, windows wider than the 64 spans a
+    wavefront stages (the per-sample fallback).  Plan, curve and sample
+    indices bit-exact, centres within 1e-9 px of the oracle."""
+    b = synth._assemble(synth.long_splines(4300, n_curves=1, n_cp=n_cp, size=512, channels=3), [[512, 512]],
+                        [[1.0, 1.0, 1.0]], 3)
+    p = Params().replace(delta_c=delta_c)
+    ref = oracle.gaussians(b, oracle_params(p))
+    out = gpu_run(b, p, backward=False)
+    assert out["counters"][2] == 0
+    plans_equal(out["plan"], ref["plan"])
+    g = out["gauss"]
+    print("n_cp", n_cp, "delta_c", delta_c, "Gaussians", len(g["sigma"]), flush=True)
+    np.testing.assert_array_equal(g["curve"], ref["curve"])
+    np.testing.assert_array_equal(g["local"], ref["local"])
+    assert np.abs(g["mu"] - ref["mu"]).max() < 1e-9
+    np.testing.assert_allclose(g["sigma"], ref["sigma"].astype(np.float32), rtol=2e-7, atol=0)
