@@ -6,10 +6,12 @@
 // entry is loaded (FP64 centre minus the tile origin, rounded once).  The
 // forward stops a pixel once T < eps_T and a wavefront once all its pixels
 // have stopped, and stores each pixel's state at every chunk boundary (a
-// chunk is 2^ck_lg list positions, chosen per launch) it passes.  The adjoint runs one wavefront per (tile,
-// quadrant, chunk), front to back from that stored state, parks each
-// Gaussian's per-lane gradient values in LDS and sums sixteen of them at a
-// time, with one atomic per value and wavefront.
+// chunk is 2^ck_lg list positions, chosen per launch) it passes.  The
+// adjoint runs one wavefront per (tile, quadrant or 8x8 pixel block, chunk)
+// (AdjCfg), back to front from the state stored at the chunk's back
+// boundary, parks each Gaussian's per-lane gradient values in LDS and sums
+// a dozen or more such rows at a time, with one atomic per value and
+// wavefront.
 #include "nsplat_internal.h"
 
 namespace nsp {
